@@ -1,0 +1,147 @@
+"""Benchmark: neutron histories per second on one MI355X.
+
+Workload (the headline metric's configuration): the biased powder-sample
+problem, 1e7 histories per step: monochromatic 1.8 A pencil beam on a solid
+cylinder (r=5 mm, h=20 mm, axis y) of a synthetic fcc powder (a=4.0 A, 26
+reflection families, sigma_inc=5 b, sigma_abs=2 b at 1.798 A), scattering
+cross section biased by 4 with the probability-conserving weight correction;
+tallies: 2theta(1800) x lambda(100) of scattered escapes, transmitted counter,
+absorbed counter.  One step = one pr_run_histories call over 1e7 histories
+(source, flights, collisions, scoring all inside the timed kernel) with the
+inputs already resident on the GPU.
+
+The FP32-mixed policy is the headline value; the FP64-plain policy is timed
+beside it.  The oracle is timed on the host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "neutron histories/sec on 1 MI355X, FP32-mixed & batched vs FP64 plain, at tally match"
+
+# Minimal VALU lane-instruction counts of the algorithm's steps in FP32 (see the
+# roofline section of the design notes): per random draw (a Philox4x32-10 block
+# of 2 x 4 32-bit multiplies, 2 three-way xors and 2 key adds per round,
+# amortised over its two draws, plus the conversion), per transport step
+# (ray-cylinder and ray-sphere intersection, log, reciprocal, move, exp and the
+# weight product), per scattering (sqrt, sin/cos, frame, rotation, family
+# search) and per history (source, cross sections, tally angle and binning).
+OPS_PER_DRAW = 43
+OPS_PER_STEP = 96
+OPS_PER_SCATTER = 48
+OPS_PER_HISTORY = 60
+# VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz, one lane-instruction per lane per clock
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def algorithmic_ops(stats: dict) -> float:
+    return (OPS_PER_DRAW * stats["draws"] + OPS_PER_STEP * stats["steps"] + OPS_PER_SCATTER * stats["scatters"]
+            + OPS_PER_HISTORY * stats["histories"])
+
+
+def cpu_baseline(prob, seconds: float) -> dict:
+    from oracle import oracle as O
+    threads = min(os.cpu_count() or 1, 64)
+    t0 = time.perf_counter()
+    O.run(prob, first=0, n=20_000, threads=1)
+    rate1 = 20_000 / max(time.perf_counter() - t0, 1e-6)
+    n = int(min(max(rate1 * threads * seconds, 1e5), 5e8))
+    t0 = time.perf_counter()
+    O.run(prob, first=0, n=n, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} histories of the same workload (FP64 oracle, {threads} threads, {dt:.1f} s)"}
+
+
+def time_policy(torch, sim, n, precision, steps, warmup):
+    for _ in range(warmup):
+        sim.run(first=0, n=n, precision=precision)
+    torch.cuda.synchronize()
+    sim.ctx.reset_stats()
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for k in range(steps):
+        sim.run(first=(k + 1) * n, n=n, precision=precision)
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    stats = sim.ctx.read_stats()
+    return ms, stats
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--histories", type=int, default=10_000_000)
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the history range would be "
+              "sharded across GPUs with a final tally sum, which this build does not run.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2304_06226_amd import binding as B
+    from paper_2304_06226_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.histories
+    prob = W.config1(n=n)
+    ctx = B.Context(device=0, seed=W.RUN_SEED)
+    sim = B.Simulation(ctx, prob)
+
+    out = {"metric": METRIC, "unit": "histories/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "data": "synthetic",
+           "config": {"workload": "biased powder cylinder (scatter bias 4), 1.8 A pencil beam, "
+                                  "2theta(1800) x lambda(100) + transmitted + absorbed tallies",
+                      "histories_per_step": n, "seed": W.RUN_SEED}}
+    fp32 = fp64 = None
+    if args.only in ("fp32", "both"):
+        ms, st = time_policy(torch, sim, n, "fp32", args.steps, args.warmup)
+        fp32 = (ms, st)
+        print(f"[bench] fp32-mixed {ms:.3f} ms/step, {n / ms * 1e3:.4g} histories/s", file=sys.stderr, flush=True)
+    if args.only in ("fp64", "both"):
+        ms64, st64 = time_policy(torch, sim, n, "fp64", args.fp64_steps, 1)
+        fp64 = (ms64, st64)
+        print(f"[bench] fp64-plain {ms64:.3f} ms/step, {n / ms64 * 1e3:.4g} histories/s", file=sys.stderr, flush=True)
+
+    head_ms, head_st = fp32 if fp32 else fp64
+    out["value"] = n / head_ms * 1e3
+    out["ms_per_step"] = head_ms
+    out["dtype"] = "f32" if fp32 else "f64"
+    per_launch_ops = algorithmic_ops(head_st) / max(1, head_st["histories"]) * n
+    achieved = per_launch_ops / (head_ms * 1e-3) / 1e12
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+                       "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                       "kernel": "k_mixed" if fp32 else "k_plain",
+                       "ops_per_history": per_launch_ops / n}
+    if fp32 and fp64:
+        out["fp64_plain"] = {"value": n / fp64[0] * 1e3, "ms_per_step": fp64[0]}
+        out["speedup_vs_fp64_plain"] = fp64[0] / fp32[0]
+    out["events_per_history"] = {"steps": head_st["steps"] / head_st["histories"],
+                                 "draws": head_st["draws"] / head_st["histories"],
+                                 "scatters": head_st["scatters"] / head_st["histories"]}
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,237 @@
+/*
+ * prompt_mi355x: MI355X-native biased neutron history loop behind a C-ABI.
+ *
+ * The library runs the per-neutron history loop of "Prompt: probability-
+ * conserved cross section biasing Monte Carlo particle transport system"
+ * (Pan et al., arXiv 2304.06226) on one AMD Instinct MI355X (gfx950):
+ *   source neutron (particle gun section) ->
+ *   free flight through boxes, cylinders, spheres and shells under biased
+ *   cross sections sigma_g = g sigma, with the probability-conserving weight
+ *   correction (cross section biasing mechanism section, step-length and
+ *   weight equations) ->
+ *   absorption, bound incoherent or powder-Bragg coherent elastic scattering
+ *   (neutron scattering cross section section) or mirror reflection (mirror
+ *   section, reflectivity and reflection equations) ->
+ *   weighted tallies (scorer section).
+ *
+ * Conventions
+ *   - Units: mm, Angstrom, barn, eV, degrees.  Number densities in 1/A^3.
+ *   - Every call returns PR_OK (0) or a negative PR_E* code; the message of
+ *     the last failure is kept per context (pr_last_error).  No exception or
+ *     abort crosses the ABI.
+ *   - create_* calls deep-copy caller arrays; the caller keeps its inputs.
+ *     The context owns every object it creates (freed by pr_destroy),
+ *     including the device storage of tallies.
+ *   - "stream" arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  Runs are asynchronous on that stream; pr_read_* calls
+ *     synchronise it.
+ *   - One context per host thread.  A context is bound to one HIP device.
+ *   - Random numbers: draw k of history h is taken from Philox4x32-10 with
+ *     key = seed and counter = (k/2, h); even draws use words 0-1, odd draws
+ *     words 2-3.  History ids are global, so running [0,k) and [k,n) gives the
+ *     same histories as [0,n) (split and resume).
+ */
+#ifndef PROMPT_MI355X_H
+#define PROMPT_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PR_OK 0
+#define PR_EINVAL (-1)      /* a field is invalid; the message names it */
+#define PR_ENOTFOUND (-2)   /* an id does not name an object of this context */
+#define PR_EOVERLAP (-3)    /* volumes overlap or a daughter leaves its mother */
+#define PR_EWORKSPACE (-4)  /* a caller buffer is too small */
+#define PR_EDEVICE (-5)     /* a HIP call failed; the message holds its error string */
+#define PR_ENOMEM (-6)      /* host or device allocation failed */
+
+/* ---- enumerations ---- */
+enum { PR_BOX = 0, PR_CYLINDER = 1, PR_CYL_SHELL = 2, PR_SPHERE = 3, PR_SPH_SHELL = 4 };
+enum { PR_PENCIL = 0, PR_RECT = 1, PR_RECT_DIVERGENT = 2 };
+enum { PR_MONO = 0, PR_UNIFORM = 1, PR_MAXWELL = 2 };
+enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2 };
+enum { PR_FILT_ALL = 0, PR_FILT_UNSCATTERED = 1, PR_FILT_SCATTERED = 2, PR_FILT_NSCAT_EQ = 3 };
+enum { PR_Q_THETA2 = 0, PR_Q_LAMBDA = 1, PR_Q_X = 2, PR_Q_Y = 3, PR_Q_Z = 4, PR_Q_DIVX = 5, PR_Q_DIVY = 6,
+       PR_Q_NSCAT = 7 };
+enum { PR_MIRROR_LINEAR = 0, PR_MIRROR_TANH = 1 };
+enum { PR_ACC_FP64 = 0, PR_ACC_KAHAN_FP32 = 1 };
+/* precision policies of pr_run_histories */
+enum {
+    PR_FP64_PLAIN = 0,   /* one thread per history, everything in FP64, global tables and atomics */
+    PR_FP32_MIXED = 1    /* persistent lanes refilled from a wave-shared history counter; FP32
+                            positions, directions, cross sections and sampling; FP64 weight
+                            product and tallies; LDS-staged tables, LDS-privatised small tallies */
+};
+/* termination codes written to history records */
+enum { PR_END_ESCAPE = 1, PR_END_ABSORB = 2, PR_END_KILL = 3, PR_END_DETECT = 4, PR_END_CAPPED = 5,
+       PR_END_OUTSIDE = 6 };
+
+#define PR_MAX_STEPS 10000   /* steps per history before it is killed and counted as capped */
+#define PR_MAX_TALLIES 8     /* tallies per run */
+
+typedef struct pr_ctx pr_ctx;
+
+/* Material (simulation physics section; material listing with bias factors).
+ *   Sigma_abs(lambda) = 0.1 n sigma_abs_ref lambda / 1.798          [1/mm]  (1/v law)
+ *   Sigma_inc         = 0.1 n sigma_inc                              [1/mm]
+ *   Sigma_coh(lambda) = 0.1 n lambda^2 / (2 v0 N) sum_{2 d_j > lambda} m_j d_j F2_j
+ * (the powder average of the coherent elastic scattering function).  Bias
+ * factors scale the cross sections used for sampling (sigma_g = g sigma); a
+ * factor of 0 removes that process.  d must be in canonical order (non-
+ * increasing); families with equal d stay separate.  Arrays are copied. */
+typedef struct {
+    double number_density;    /* atoms / A^3, > 0 */
+    double sigma_inc;         /* b, >= 0 */
+    double sigma_abs_ref;     /* b at 1.798 A, >= 0 */
+    double scatter_bias;      /* >= 0 (default 1) */
+    double abs_bias;          /* >= 0 (default 1) */
+    double cell_volume;       /* A^3; 0 together with n_families = 0 means no Bragg scattering */
+    int32_t atoms_per_cell;   /* N */
+    int32_t n_families;       /* 0..1024 */
+    const double* d;          /* [n_families] A, > 0, non-increasing */
+    const int32_t* mult;      /* [n_families] > 0 */
+    const double* f2;         /* [n_families] b per cell, >= 0 */
+} pr_material_desc;
+
+/* Mirror on faces of a volume (mirror section).  "tanh": the empirical form
+ *   R = R0 (Q <= Qc), R0/2 (1 - alpha (Q - Qc)) (1 - tanh((Q - m Qc)/W)) (Q > Qc);
+ * "linear": R0 up to Qc, R0 - alpha (Q - Qc) up to m Qc, 0 beyond.
+ * Q = 4 pi |u.n| / lambda.  The weight is multiplied by R (clipped at 0) and
+ * the direction reflected, u' = u - 2 n (u.n); R = 0 ends the history. */
+typedef struct {
+    int32_t model;            /* PR_MIRROR_* */
+    int32_t pad;
+    double R0, Qc, alpha, m, W;
+} pr_mirror_desc;
+
+/* Volume (geometry section).  size by kind:
+ *   PR_BOX        {side_x, side_y, side_z} (full sides, axis aligned)
+ *   PR_CYLINDER   {r, h}               axis = 0,1,2
+ *   PR_CYL_SHELL  {r_in, r_out, h}     open-ended tube wall (the bore belongs to the mother)
+ *   PR_SPHERE     {r}
+ *   PR_SPH_SHELL  {r_in, r_out}
+ * Volume 0 is the world (parent -1); leaving it is an escape.  Every other
+ * volume names its mother (a lower index) and must lie strictly inside it and
+ * strictly apart from its sisters (checked: PR_EOVERLAP).  Face ids used by
+ * mirror_mask bits: box 0..5 = -x,+x,-y,+y,-z,+z; cylinder and shell 0 outer
+ * wall, 1 low cap, 2 high cap, 3 inner wall; sphere 0 outer, 3 inner.  A
+ * mirror acts when the particle leaves the volume through a masked face. */
+typedef struct {
+    int32_t kind;             /* PR_BOX .. PR_SPH_SHELL */
+    int32_t axis;             /* cylinders: 0 x, 1 y, 2 z */
+    int32_t parent;           /* -1 for volume 0, else a lower index */
+    int32_t material;         /* material id or -1 (vacuum) */
+    int32_t is_detector;      /* 1: entering it ends the history and fires PR_TRIG_DETECT tallies */
+    int32_t mirror_mask;      /* faces carrying the mirror */
+    double center[3];         /* mm */
+    double size[3];           /* mm, see above */
+    pr_mirror_desc mirror;
+} pr_volume_desc;
+
+/* Source (particle gun section).  PR_PENCIL: origin and direction.
+ * PR_RECT: origin + ((u0 - 1/2) size_x, (u1 - 1/2) size_y, 0), direction dir.
+ * PR_RECT_DIVERGENT: as PR_RECT, then alpha_x, alpha_y uniform in
+ * [-div, div] degrees and direction ~ (tan alpha_x, tan alpha_y, 1).
+ * Spectrum: PR_MONO lam0; PR_UNIFORM lambda uniform in [lam_lo, lam_hi];
+ * PR_MAXWELL energy density ~ sqrt(E) exp(-E/kT), rejected to [lam_lo, lam_hi]
+ * (at most 64 tries of three draws).  Draw order: position, divergence, lambda. */
+typedef struct {
+    int32_t kind;             /* PR_PENCIL, PR_RECT, PR_RECT_DIVERGENT */
+    int32_t spectrum;         /* PR_MONO, PR_UNIFORM, PR_MAXWELL */
+    double origin[3];         /* mm */
+    double dir[3];            /* non-zero; PR_RECT_DIVERGENT requires +z */
+    double size[2];           /* mm */
+    double div_deg[2];        /* degrees */
+    double lam0, lam_lo, lam_hi;   /* A */
+    double kT;                /* eV */
+} pr_source_desc;
+
+typedef struct {
+    int32_t quantity;         /* PR_Q_*: 2theta = acos(u.beam) deg; lambda A; x,y,z mm;
+                                 div_x = atan2(u_x, u_z) deg; div_y = atan2(u_y, u_z) deg; n_scat */
+    int32_t nbins;            /* >= 1 */
+    double lo, hi;            /* hi > lo; bin = floor((x - lo) / (hi - lo) nbins); x = hi goes to the
+                                 last bin; values outside [lo, hi] are not scored */
+} pr_tally_axis;
+
+/* Tally (scorer section): fires once per history at its end when the
+ * trigger and filter match, adding w to sum_w and w^2 to sum_w2 of one bin
+ * (row-major over the axes, axis 0 slowest; 0 axes = one counter bin). */
+typedef struct {
+    int32_t trigger;          /* PR_TRIG_* */
+    int32_t trigger_volume;   /* PR_TRIG_DETECT: detector volume index, -1 = any */
+    int32_t filter;           /* PR_FILT_* on the history's scattering count */
+    int32_t filter_arg;       /* k of PR_FILT_NSCAT_EQ */
+    int32_t naxes;            /* 0..4 */
+    int32_t accumulator;      /* PR_ACC_FP64 (PR_ACC_KAHAN_FP32 is accepted and stored in FP64) */
+    pr_tally_axis axes[4];
+    double beam[3];           /* 2theta reference direction (need not be normalised) */
+} pr_tally_desc;
+
+/* Per-history outcome (96 bytes, little endian), written when a record
+ * buffer is given: FNV-1a hash of the event sequence, final weight, final
+ * position and direction, wavelength, termination code, scatterings, steps,
+ * random draws consumed and the final volume. */
+typedef struct {
+    uint64_t hash;
+    double w;
+    double pos[3];
+    double dir[3];
+    double lambda;
+    int32_t term, n_scat, n_steps, n_draws, region, pad;
+} pr_history_record;
+
+typedef struct {
+    uint64_t histories, escaped, absorbed, killed, detected, capped, outside, steps, draws, scatters;
+} pr_run_stats;
+
+/* ---- context ---- */
+/* Create a context on HIP device hip_device with run seed `seed` (the
+ * launcher's default is 4096).  *out receives the context or NULL. */
+int pr_init(pr_ctx** out, int hip_device, uint64_t seed);
+void pr_destroy(pr_ctx* ctx);
+const char* pr_last_error(const pr_ctx* ctx);
+int pr_set_seed(pr_ctx* ctx, uint64_t seed);
+
+/* ---- problem objects ---- */
+int pr_create_material(pr_ctx* ctx, const pr_material_desc* desc, int32_t* id);
+/* n volumes, volume 0 the world; validates kinds, sizes, tree and overlaps. */
+int pr_create_geometry(pr_ctx* ctx, const pr_volume_desc* volumes, int32_t n, int32_t* id);
+int pr_create_source(pr_ctx* ctx, const pr_source_desc* desc, int32_t* id);
+/* allocates and zeroes the tally's device storage (2 x nbins doubles) */
+int pr_create_tally(pr_ctx* ctx, const pr_tally_desc* desc, int32_t* id);
+int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
+
+/* ---- running ---- */
+/* Run histories [first_history, first_history + n) of source `src` through
+ * geometry `geom`, scoring into the n_tallies tallies listed.  precision is
+ * PR_FP64_PLAIN or PR_FP32_MIXED.  records_dev is NULL or a device buffer of
+ * n pr_history_record entries (record i is history first_history + i).
+ * Asynchronous on `stream`; tallies and run statistics accumulate across runs
+ * until reset. */
+int pr_run_histories(pr_ctx* ctx, int32_t geom, int32_t src, const int32_t* tallies, int32_t n_tallies,
+                     uint64_t first_history, uint64_t n, int32_t precision, void* records_dev, void* stream);
+
+/* ---- results ---- */
+/* Synchronise `stream` and copy the tally into host arrays of nbins doubles
+ * each (either may be NULL); *n_hist receives the histories run since the
+ * last reset.  The mean per source neutron is sum_w / n_hist. */
+int pr_read_tally(pr_ctx* ctx, int32_t tally, double* sum_w, double* sum_w2, uint64_t* n_hist, size_t nbins,
+                  void* stream);
+/* As pr_read_tally for bins [offset, offset + count). */
+int pr_read_tally_range(pr_ctx* ctx, int32_t tally, uint64_t offset, uint64_t count, double* sum_w,
+                        double* sum_w2, void* stream);
+int pr_reset_tally(pr_ctx* ctx, int32_t tally, void* stream);
+/* Run statistics accumulated since the last pr_reset_stats (synchronises). */
+int pr_read_stats(pr_ctx* ctx, pr_run_stats* out, void* stream);
+int pr_reset_stats(pr_ctx* ctx, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,796 @@
+// C-ABI of prompt_mi355x: object creation with validation, scene building,
+// run orchestration and result readback.  See include/prompt_mi355x.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/prompt_mi355x.h"
+#include "device.h"
+#include "launch.h"
+
+using namespace prk;
+
+namespace {
+
+struct Material {
+    pr_material_desc desc;
+    std::vector<double> d, f2;
+    std::vector<int32_t> mult;
+};
+
+struct Geometry {
+    std::vector<pr_volume_desc> vols;
+    int nv = 0, nm = 0, nf = 0, nc = 0;
+    void* vols_d = nullptr;
+    void* mats_d = nullptr;
+    void* fams_d = nullptr;
+    void* vols_f = nullptr;
+    void* mats_f = nullptr;
+    void* fams_f = nullptr;
+    void* children = nullptr;
+};
+
+struct Tally {
+    pr_tally_desc desc;
+    uint64_t nbins = 0;
+    double* dev = nullptr;   // [sum_w | sum_w2]
+    uint64_t n_hist = 0;
+};
+
+}  // namespace
+
+struct pr_ctx {
+    int device = -1;
+    uint64_t seed = 4096;
+    std::string err;
+    std::vector<Material> mats;
+    std::vector<Geometry> geoms;
+    std::vector<pr_source_desc> srcs;
+    std::vector<Tally> tallies;
+    unsigned long long* stats = nullptr;
+    unsigned long long* counter = nullptr;
+    int num_cus = 256;
+    // launch tuning of the mixed policy
+    int mixed_block = 256;
+    int mixed_blocks_per_cu = 0;        // 0 = occupancy limit
+    int refill_threshold = 16;
+    int lds_tally_budget = 32768;       // bytes of LDS per block for privatised tallies
+};
+
+namespace {
+
+int fail(pr_ctx* c, int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+int hipfail(pr_ctx* c, hipError_t e, const char* what) {
+    return fail(c, PR_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(ctx, call)                                   \
+    do {                                                    \
+        hipError_t e_ = (call);                             \
+        if (e_ != hipSuccess) return hipfail(ctx, e_, #call); \
+    } while (0)
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// ---- geometry helpers (host, double) ----
+
+struct Box3 {
+    double lo[3], hi[3];
+};
+
+Box3 aabb(const pr_volume_desc& v) {
+    Box3 b;
+    double e[3] = {0, 0, 0};
+    switch (v.kind) {
+    case PR_BOX: e[0] = 0.5 * v.size[0]; e[1] = 0.5 * v.size[1]; e[2] = 0.5 * v.size[2]; break;
+    case PR_CYLINDER:
+    case PR_CYL_SHELL: {
+        double r = v.kind == PR_CYLINDER ? v.size[0] : v.size[1];
+        double h = v.kind == PR_CYLINDER ? v.size[1] : v.size[2];
+        e[0] = e[1] = e[2] = r;
+        e[v.axis] = 0.5 * h;
+        break;
+    }
+    case PR_SPHERE: e[0] = e[1] = e[2] = v.size[0]; break;
+    default: e[0] = e[1] = e[2] = v.size[1]; break;
+    }
+    for (int k = 0; k < 3; ++k) {
+        b.lo[k] = v.center[k] - e[k];
+        b.hi[k] = v.center[k] + e[k];
+    }
+    return b;
+}
+
+// point inside the solid; strict excludes the boundary
+bool inside(const pr_volume_desc& v, const double p[3], bool strict) {
+    double q[3] = {p[0] - v.center[0], p[1] - v.center[1], p[2] - v.center[2]};
+    auto le = [strict](double a, double b) { return strict ? a < b : a <= b; };
+    switch (v.kind) {
+    case PR_BOX:
+        return le(std::fabs(q[0]), 0.5 * v.size[0]) && le(std::fabs(q[1]), 0.5 * v.size[1]) &&
+               le(std::fabs(q[2]), 0.5 * v.size[2]);
+    case PR_CYLINDER:
+    case PR_CYL_SHELL: {
+        int a = v.axis, b = (a + 1) % 3, c = (a + 2) % 3;
+        double rho = std::sqrt(q[b] * q[b] + q[c] * q[c]);
+        double ro = v.kind == PR_CYLINDER ? v.size[0] : v.size[1];
+        double h = v.kind == PR_CYLINDER ? v.size[1] : v.size[2];
+        bool in = le(rho, ro) && le(std::fabs(q[a]), 0.5 * h);
+        if (v.kind == PR_CYL_SHELL) in = in && le(v.size[0], rho);
+        return in;
+    }
+    case PR_SPHERE: return le(std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]), v.size[0]);
+    default: {
+        double r = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+        return le(r, v.size[1]) && le(v.size[0], r);
+    }
+    }
+}
+
+// deterministic sample of points on the solid's surfaces
+void surface_points(const pr_volume_desc& v, std::vector<std::array<double, 3>>& out) {
+    out.clear();
+    const double PI = 3.14159265358979323846;
+    auto add = [&](double x, double y, double z) { out.push_back({v.center[0] + x, v.center[1] + y, v.center[2] + z}); };
+    if (v.kind == PR_BOX) {
+        double h[3] = {0.5 * v.size[0], 0.5 * v.size[1], 0.5 * v.size[2]};
+        const int g = 17;
+        for (int f = 0; f < 3; ++f)
+            for (int s = -1; s <= 1; s += 2)
+                for (int i = 0; i < g; ++i)
+                    for (int j = 0; j < g; ++j) {
+                        double p[3];
+                        int a = (f + 1) % 3, b = (f + 2) % 3;
+                        p[f] = s * h[f];
+                        p[a] = h[a] * (2.0 * i / (g - 1) - 1.0);
+                        p[b] = h[b] * (2.0 * j / (g - 1) - 1.0);
+                        add(p[0], p[1], p[2]);
+                    }
+        return;
+    }
+    auto cyl = [&](double r, double hh, bool caps_annulus_from) {
+        int a = v.axis, b = (a + 1) % 3, c = (a + 2) % 3;
+        for (int i = 0; i < 96; ++i)
+            for (int j = 0; j < 17; ++j) {
+                double p[3];
+                double ph = 2 * PI * i / 96;
+                p[b] = r * std::cos(ph);
+                p[c] = r * std::sin(ph);
+                p[a] = hh * (2.0 * j / 16 - 1.0);
+                add(p[0], p[1], p[2]);
+            }
+        (void)caps_annulus_from;
+    };
+    if (v.kind == PR_CYLINDER || v.kind == PR_CYL_SHELL) {
+        int a = v.axis, b = (a + 1) % 3, c = (a + 2) % 3;
+        double rin = v.kind == PR_CYLINDER ? 0.0 : v.size[0];
+        double rout = v.kind == PR_CYLINDER ? v.size[0] : v.size[1];
+        double hh = 0.5 * (v.kind == PR_CYLINDER ? v.size[1] : v.size[2]);
+        cyl(rout, hh, false);
+        if (v.kind == PR_CYL_SHELL) cyl(rin, hh, false);
+        for (int s = -1; s <= 1; s += 2)
+            for (int i = 0; i < 9; ++i)
+                for (int j = 0; j < 48; ++j) {
+                    double p[3];
+                    double r = rin + (rout - rin) * i / 8.0;
+                    double ph = 2 * PI * j / 48;
+                    p[b] = r * std::cos(ph);
+                    p[c] = r * std::sin(ph);
+                    p[a] = s * hh;
+                    add(p[0], p[1], p[2]);
+                }
+        return;
+    }
+    auto sph = [&](double r) {
+        for (int i = 0; i <= 32; ++i)
+            for (int j = 0; j < 64; ++j) {
+                double th = PI * i / 32, ph = 2 * PI * j / 64;
+                add(r * std::sin(th) * std::cos(ph), r * std::sin(th) * std::sin(ph), r * std::cos(th));
+            }
+    };
+    if (v.kind == PR_SPHERE) {
+        sph(v.size[0]);
+    } else {
+        sph(v.size[0]);
+        sph(v.size[1]);
+    }
+}
+
+bool boxes_apart(const Box3& a, const Box3& b) {
+    for (int k = 0; k < 3; ++k)
+        if (a.hi[k] < b.lo[k] || b.hi[k] < a.lo[k]) return true;
+    return false;
+}
+
+bool box_inside(const Box3& in, const Box3& out) {
+    for (int k = 0; k < 3; ++k)
+        if (!(in.lo[k] > out.lo[k] && in.hi[k] < out.hi[k])) return false;
+    return true;
+}
+
+template <class T>
+int upload(pr_ctx* c, void** dst, const std::vector<T>& v) {
+    size_t bytes = std::max<size_t>(v.size() * sizeof(T), 16);
+    HIPCHK(c, hipMalloc(dst, bytes));
+    if (!v.empty()) HIPCHK(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return PR_OK;
+}
+
+void free_geometry(Geometry& g) {
+    void* ps[] = {g.vols_d, g.mats_d, g.fams_d, g.vols_f, g.mats_f, g.fams_f, g.children};
+    for (void* p : ps)
+        if (p) (void)hipFree(p);
+    g.vols_d = g.mats_d = g.fams_d = g.vols_f = g.mats_f = g.fams_f = g.children = nullptr;
+}
+
+int set_device(pr_ctx* c) {
+    if (c->device < 0) return fail(c, PR_EDEVICE, "context has no device (created with hip_device = -1)");
+    HIPCHK(c, hipSetDevice(c->device));
+    return PR_OK;
+}
+
+// E = h^2 / (2 m_n lambda^2): the constant in eV A^2 from CODATA 2018
+double ev_angstrom2() {
+    const double h = 6.62607015e-34, mn = 1.67492749804e-27, ev = 1.602176634e-19;
+    return h * h / (2.0 * mn) / ev * 1e20;
+}
+
+}  // namespace
+
+// =========================================================================
+// context
+// =========================================================================
+
+extern "C" int pr_init(pr_ctx** out, int hip_device, uint64_t seed) {
+    if (!out) return PR_EINVAL;
+    *out = nullptr;
+    pr_ctx* c = new (std::nothrow) pr_ctx();
+    if (!c) return PR_ENOMEM;
+    c->seed = seed;
+    c->device = hip_device;
+    if (hip_device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || hip_device >= n) {
+            delete c;
+            return PR_EDEVICE;
+        }
+        if (hipSetDevice(hip_device) != hipSuccess ||
+            hipMalloc((void**)&c->stats, ST_N * sizeof(unsigned long long)) != hipSuccess ||
+            hipMalloc((void**)&c->counter, 64) != hipSuccess ||
+            hipMemset(c->stats, 0, ST_N * sizeof(unsigned long long)) != hipSuccess) {
+            delete c;
+            return PR_EDEVICE;
+        }
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
+            c->num_cus = cus;
+    }
+    *out = c;
+    return PR_OK;
+}
+
+extern "C" void pr_destroy(pr_ctx* c) {
+    if (!c) return;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        for (auto& g : c->geoms) free_geometry(g);
+        for (auto& t : c->tallies)
+            if (t.dev) (void)hipFree(t.dev);
+        if (c->stats) (void)hipFree(c->stats);
+        if (c->counter) (void)hipFree(c->counter);
+    }
+    delete c;
+}
+
+extern "C" const char* pr_last_error(const pr_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+extern "C" int pr_set_seed(pr_ctx* c, uint64_t seed) {
+    if (!c) return PR_EINVAL;
+    c->seed = seed;
+    return PR_OK;
+}
+
+// =========================================================================
+// materials
+// =========================================================================
+
+extern "C" int pr_create_material(pr_ctx* c, const pr_material_desc* d, int32_t* id) {
+    if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
+    if (!(std::isfinite(d->number_density) && d->number_density > 0))
+        return fail(c, PR_EINVAL, "material.number_density must be > 0");
+    if (!finite_nonneg(d->sigma_inc)) return fail(c, PR_EINVAL, "material.sigma_inc must be >= 0");
+    if (!finite_nonneg(d->sigma_abs_ref)) return fail(c, PR_EINVAL, "material.sigma_abs_ref must be >= 0");
+    if (!finite_nonneg(d->scatter_bias)) return fail(c, PR_EINVAL, "material.scatter_bias must be >= 0");
+    if (!finite_nonneg(d->abs_bias)) return fail(c, PR_EINVAL, "material.abs_bias must be >= 0");
+    if (d->n_families < 0 || d->n_families > 1024) return fail(c, PR_EINVAL, "material.n_families must be in [0, 1024]");
+    if (d->n_families > 0) {
+        if (!(std::isfinite(d->cell_volume) && d->cell_volume > 0))
+            return fail(c, PR_EINVAL, "material.cell_volume must be > 0 with Bragg families");
+        if (d->atoms_per_cell <= 0) return fail(c, PR_EINVAL, "material.atoms_per_cell must be > 0 with Bragg families");
+        if (!d->d || !d->mult || !d->f2) return fail(c, PR_EINVAL, "material family arrays must not be null");
+        for (int j = 0; j < d->n_families; ++j) {
+            if (!(std::isfinite(d->d[j]) && d->d[j] > 0)) return fail(c, PR_EINVAL, "material.d[%d] must be > 0", j);
+            if (j > 0 && d->d[j] > d->d[j - 1])
+                return fail(c, PR_EINVAL, "material.d must be non-increasing (d[%d] > d[%d])", j, j - 1);
+            if (d->mult[j] <= 0) return fail(c, PR_EINVAL, "material.mult[%d] must be > 0", j);
+            if (!finite_nonneg(d->f2[j])) return fail(c, PR_EINVAL, "material.f2[%d] must be >= 0", j);
+        }
+    }
+    Material m;
+    m.desc = *d;
+    m.d.assign(d->d, d->d + d->n_families);
+    m.mult.assign(d->mult, d->mult + d->n_families);
+    m.f2.assign(d->f2, d->f2 + d->n_families);
+    m.desc.d = nullptr;
+    m.desc.mult = nullptr;
+    m.desc.f2 = nullptr;
+    c->mats.push_back(std::move(m));
+    *id = (int32_t)c->mats.size() - 1;
+    return PR_OK;
+}
+
+// =========================================================================
+// geometry
+// =========================================================================
+
+static int validate_volume(pr_ctx* c, const pr_volume_desc& v, int i, int nmat) {
+    if (v.kind < PR_BOX || v.kind > PR_SPH_SHELL) return fail(c, PR_EINVAL, "volume[%d].kind invalid", i);
+    if ((v.kind == PR_CYLINDER || v.kind == PR_CYL_SHELL) && (v.axis < 0 || v.axis > 2))
+        return fail(c, PR_EINVAL, "volume[%d].axis must be 0, 1 or 2", i);
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(v.center[k])) return fail(c, PR_EINVAL, "volume[%d].center not finite", i);
+    int ns = v.kind == PR_BOX ? 3 : v.kind == PR_CYLINDER ? 2 : v.kind == PR_CYL_SHELL ? 3 : v.kind == PR_SPHERE ? 1 : 2;
+    for (int k = 0; k < ns; ++k)
+        if (!(std::isfinite(v.size[k]) && v.size[k] > 0)) return fail(c, PR_EINVAL, "volume[%d].size[%d] must be > 0", i, k);
+    if ((v.kind == PR_CYL_SHELL || v.kind == PR_SPH_SHELL) && !(v.size[0] < v.size[1]))
+        return fail(c, PR_EINVAL, "volume[%d]: shell needs r_in < r_out", i);
+    if (v.material < -1 || v.material >= nmat) return fail(c, PR_ENOTFOUND, "volume[%d].material %d unknown", i, v.material);
+    if (i == 0 && v.parent != -1) return fail(c, PR_EINVAL, "volume[0] is the world and needs parent -1");
+    if (i > 0 && (v.parent < 0 || v.parent >= i)) return fail(c, PR_EINVAL, "volume[%d].parent must be in [0, %d)", i, i);
+    if (i == 0 && v.is_detector) return fail(c, PR_EINVAL, "the world cannot be a detector");
+    if (v.mirror_mask < 0 || v.mirror_mask > 63) return fail(c, PR_EINVAL, "volume[%d].mirror_mask out of range", i);
+    if (v.mirror_mask) {
+        const pr_mirror_desc& m = v.mirror;
+        if (m.model != PR_MIRROR_LINEAR && m.model != PR_MIRROR_TANH)
+            return fail(c, PR_EINVAL, "volume[%d].mirror.model invalid", i);
+        if (!(finite_nonneg(m.R0) && m.R0 <= 1.0)) return fail(c, PR_EINVAL, "volume[%d].mirror.R0 must be in [0,1]", i);
+        if (!finite_nonneg(m.Qc) || !finite_nonneg(m.alpha) || !finite_nonneg(m.m))
+            return fail(c, PR_EINVAL, "volume[%d].mirror parameters must be >= 0", i);
+        if (m.model == PR_MIRROR_TANH && !(std::isfinite(m.W) && m.W > 0))
+            return fail(c, PR_EINVAL, "volume[%d].mirror.W must be > 0", i);
+    }
+    return PR_OK;
+}
+
+extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t n, int32_t* id) {
+    if (!c || !vols || !id) return fail(c, PR_EINVAL, "null argument");
+    if (n < 1 || n > 100000) return fail(c, PR_EINVAL, "geometry needs 1..100000 volumes");
+    const int nmat = (int)c->mats.size();
+    for (int i = 0; i < n; ++i) {
+        int rc = validate_volume(c, vols[i], i, nmat);
+        if (rc) return rc;
+    }
+    // containment in the mother and separation from sisters
+    std::vector<Box3> bb(n);
+    for (int i = 0; i < n; ++i) bb[i] = aabb(vols[i]);
+    std::vector<std::array<double, 3>> pts, pts2;
+    for (int i = 1; i < n; ++i) {
+        const pr_volume_desc& mo = vols[vols[i].parent];
+        bool ok = box_inside(bb[i], bb[vols[i].parent]);
+        if (ok && !(mo.kind == PR_BOX && vols[i].kind == PR_BOX)) {
+            surface_points(vols[i], pts);
+            for (auto& p : pts)
+                if (!inside(mo, p.data(), true)) { ok = false; break; }
+        }
+        if (!ok) return fail(c, PR_EOVERLAP, "volume[%d] is not strictly inside its mother volume[%d]", i, vols[i].parent);
+    }
+    // sisters: group by parent, sort by x to prune the pair scan
+    std::vector<int> order(n > 0 ? n - 1 : 0);
+    for (int i = 1; i < n; ++i) order[i - 1] = i;
+    std::sort(order.begin(), order.end(), [&](int a, int b) { return bb[a].lo[0] < bb[b].lo[0]; });
+    for (size_t ia = 0; ia < order.size(); ++ia) {
+        int a = order[ia];
+        for (size_t ib = ia + 1; ib < order.size(); ++ib) {
+            int b = order[ib];
+            if (bb[b].lo[0] > bb[a].hi[0]) break;
+            if (vols[a].parent != vols[b].parent || boxes_apart(bb[a], bb[b])) continue;
+            bool clash = vols[a].kind == PR_BOX && vols[b].kind == PR_BOX;   // AABBs of boxes are exact
+            if (!clash) {
+                surface_points(vols[a], pts);
+                for (auto& p : pts)
+                    if (inside(vols[b], p.data(), false)) { clash = true; break; }
+            }
+            if (!clash) {
+                surface_points(vols[b], pts2);
+                for (auto& p : pts2)
+                    if (inside(vols[a], p.data(), false)) { clash = true; break; }
+            }
+            if (clash) return fail(c, PR_EOVERLAP, "volumes %d and %d overlap or touch", a, b);
+        }
+    }
+
+    Geometry g;
+    g.vols.assign(vols, vols + n);
+    // children lists
+    std::vector<std::vector<int32_t>> kids(n);
+    for (int i = 1; i < n; ++i) kids[vols[i].parent].push_back(i);
+    std::vector<int32_t> children;
+    std::vector<int32_t> cbeg(n), ccnt(n);
+    for (int i = 0; i < n; ++i) {
+        cbeg[i] = (int32_t)children.size();
+        ccnt[i] = (int32_t)kids[i].size();
+        children.insert(children.end(), kids[i].begin(), kids[i].end());
+    }
+    // materials used, re-indexed in order of first use
+    std::vector<int> mat_map(nmat, -1), used;
+    for (int i = 0; i < n; ++i) {
+        int m = vols[i].material;
+        if (m >= 0 && mat_map[m] < 0) { mat_map[m] = (int)used.size(); used.push_back(m); }
+    }
+    std::vector<VolT<double>> vd(n);
+    std::vector<VolT<float>> vf(n);
+    for (int i = 0; i < n; ++i) {
+        const pr_volume_desc& v = vols[i];
+        VolT<double> o{};
+        for (int k = 0; k < 3; ++k) o.c[k] = v.center[k];
+        switch (v.kind) {
+        case PR_BOX: o.s[0] = 0.5 * v.size[0]; o.s[1] = 0.5 * v.size[1]; o.s[2] = 0.5 * v.size[2]; break;
+        case PR_CYLINDER: o.s[0] = v.size[0]; o.s[1] = 0.5 * v.size[1]; break;
+        case PR_CYL_SHELL: o.s[0] = v.size[0]; o.s[1] = v.size[1]; o.s[2] = 0.5 * v.size[2]; break;
+        case PR_SPHERE: o.s[0] = v.size[0]; break;
+        default: o.s[0] = v.size[0]; o.s[1] = v.size[1]; break;
+        }
+        o.kind = v.kind;
+        o.axis = v.axis;
+        o.parent = v.parent;
+        o.mat = v.material >= 0 ? mat_map[v.material] : -1;
+        o.detector = v.is_detector ? 1 : 0;
+        o.mirror_mask = v.mirror_mask;
+        o.child_begin = cbeg[i];
+        o.child_count = ccnt[i];
+        o.mirror_model = v.mirror.model;
+        o.R0 = v.mirror.R0;
+        o.Qc = v.mirror.Qc;
+        o.alpha = v.mirror.alpha;
+        o.mQc = v.mirror.m * v.mirror.Qc;
+        o.W = v.mirror.W > 0 ? v.mirror.W : 1.0;
+        vd[i] = o;
+        VolT<float> f{};
+        for (int k = 0; k < 3; ++k) { f.c[k] = (float)o.c[k]; f.s[k] = (float)o.s[k]; }
+        f.kind = o.kind; f.axis = o.axis; f.parent = o.parent; f.mat = o.mat; f.detector = o.detector;
+        f.mirror_mask = o.mirror_mask; f.child_begin = o.child_begin; f.child_count = o.child_count;
+        f.mirror_model = o.mirror_model;
+        f.R0 = (float)o.R0; f.Qc = (float)o.Qc; f.alpha = (float)o.alpha; f.mQc = (float)o.mQc; f.W = (float)o.W;
+        vf[i] = f;
+    }
+    std::vector<MatT<double>> md;
+    std::vector<MatT<float>> mf;
+    std::vector<FamT<double>> fd;
+    std::vector<FamT<float>> ff;
+    for (int m : used) {
+        const Material& M = c->mats[m];
+        const pr_material_desc& d = M.desc;
+        MatT<double> o{};
+        o.sa_per_lambda = 0.1 * d.number_density * d.sigma_abs_ref / 1.798;
+        o.si = 0.1 * d.number_density * d.sigma_inc;
+        o.sc_k = d.n_families > 0 ? 0.1 * d.number_density / (2.0 * d.cell_volume * d.atoms_per_cell) : 0.0;
+        o.ga = d.abs_bias;
+        o.gs = d.scatter_bias;
+        o.fam_begin = (int32_t)fd.size();
+        o.nfam = d.n_families;
+        double cum = 0.0;
+        for (int j = 0; j < d.n_families; ++j) {
+            cum += M.mult[j] * M.d[j] * M.f2[j];
+            FamT<double> f{2.0 * M.d[j], cum, 1.0 / (2.0 * M.d[j] * M.d[j]), 0.0};
+            fd.push_back(f);
+            ff.push_back(FamT<float>{(float)f.edge, (float)f.cum, (float)f.inv2d2, 0.0f});
+        }
+        md.push_back(o);
+        mf.push_back(MatT<float>{(float)o.sa_per_lambda, (float)o.si, (float)o.sc_k, (float)o.ga, (float)o.gs,
+                                 o.fam_begin, o.nfam});
+    }
+    g.nv = n;
+    g.nm = (int)md.size();
+    g.nf = (int)fd.size();
+    g.nc = (int)children.size();
+    if (c->device >= 0) {
+        int rc = set_device(c);
+        if (rc) return rc;
+        if ((rc = upload(c, &g.vols_d, vd)) || (rc = upload(c, &g.vols_f, vf)) || (rc = upload(c, &g.mats_d, md)) ||
+            (rc = upload(c, &g.mats_f, mf)) || (rc = upload(c, &g.fams_d, fd)) || (rc = upload(c, &g.fams_f, ff)) ||
+            (rc = upload(c, &g.children, children))) {
+            free_geometry(g);
+            return rc;
+        }
+    }
+    c->geoms.push_back(std::move(g));
+    *id = (int32_t)c->geoms.size() - 1;
+    return PR_OK;
+}
+
+// =========================================================================
+// source
+// =========================================================================
+
+extern "C" int pr_create_source(pr_ctx* c, const pr_source_desc* d, int32_t* id) {
+    if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
+    if (d->kind < PR_PENCIL || d->kind > PR_RECT_DIVERGENT) return fail(c, PR_EINVAL, "source.kind invalid");
+    if (d->spectrum < PR_MONO || d->spectrum > PR_MAXWELL) return fail(c, PR_EINVAL, "source.spectrum invalid");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(d->origin[k]) || !std::isfinite(d->dir[k])) return fail(c, PR_EINVAL, "source origin/dir not finite");
+    double nd = std::sqrt(d->dir[0] * d->dir[0] + d->dir[1] * d->dir[1] + d->dir[2] * d->dir[2]);
+    if (!(nd > 0)) return fail(c, PR_EINVAL, "source.dir must be non-zero");
+    if (d->kind != PR_PENCIL && !(finite_nonneg(d->size[0]) && finite_nonneg(d->size[1])))
+        return fail(c, PR_EINVAL, "source.size must be >= 0");
+    if (d->kind == PR_RECT_DIVERGENT) {
+        if (!(d->dir[0] == 0 && d->dir[1] == 0 && d->dir[2] > 0))
+            return fail(c, PR_EINVAL, "PR_RECT_DIVERGENT needs dir = +z");
+        for (int k = 0; k < 2; ++k)
+            if (!(finite_nonneg(d->div_deg[k]) && d->div_deg[k] < 89.0))
+                return fail(c, PR_EINVAL, "source.div_deg must be in [0, 89)");
+    }
+    if (d->spectrum == PR_MONO && !(std::isfinite(d->lam0) && d->lam0 > 0)) return fail(c, PR_EINVAL, "source.lam0 must be > 0");
+    if (d->spectrum != PR_MONO && !(std::isfinite(d->lam_lo) && d->lam_lo > 0 && d->lam_hi > d->lam_lo && std::isfinite(d->lam_hi)))
+        return fail(c, PR_EINVAL, "source needs 0 < lam_lo < lam_hi");
+    if (d->spectrum == PR_MAXWELL && !(std::isfinite(d->kT) && d->kT > 0)) return fail(c, PR_EINVAL, "source.kT must be > 0");
+    c->srcs.push_back(*d);
+    *id = (int32_t)c->srcs.size() - 1;
+    return PR_OK;
+}
+
+// =========================================================================
+// tallies
+// =========================================================================
+
+extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
+    if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
+    if (d->trigger < PR_TRIG_ESCAPE || d->trigger > PR_TRIG_DETECT) return fail(c, PR_EINVAL, "tally.trigger invalid");
+    if (d->filter < PR_FILT_ALL || d->filter > PR_FILT_NSCAT_EQ) return fail(c, PR_EINVAL, "tally.filter invalid");
+    if (d->naxes < 0 || d->naxes > 4) return fail(c, PR_EINVAL, "tally.naxes must be in [0, 4]");
+    if (d->accumulator != PR_ACC_FP64 && d->accumulator != PR_ACC_KAHAN_FP32)
+        return fail(c, PR_EINVAL, "tally.accumulator invalid");
+    uint64_t nb = 1;
+    for (int a = 0; a < d->naxes; ++a) {
+        const pr_tally_axis& x = d->axes[a];
+        if (x.quantity < PR_Q_THETA2 || x.quantity > PR_Q_NSCAT) return fail(c, PR_EINVAL, "tally.axes[%d].quantity invalid", a);
+        if (x.nbins < 1) return fail(c, PR_EINVAL, "tally.axes[%d].nbins must be >= 1", a);
+        if (!(std::isfinite(x.lo) && std::isfinite(x.hi) && x.hi > x.lo))
+            return fail(c, PR_EINVAL, "tally.axes[%d] needs lo < hi", a);
+        nb *= (uint64_t)x.nbins;
+        if (nb > (1ull << 36)) return fail(c, PR_EINVAL, "tally has too many bins");
+    }
+    double bn = std::sqrt(d->beam[0] * d->beam[0] + d->beam[1] * d->beam[1] + d->beam[2] * d->beam[2]);
+    for (int a = 0; a < d->naxes; ++a)
+        if (d->axes[a].quantity == PR_Q_THETA2 && !(bn > 0)) return fail(c, PR_EINVAL, "tally.beam must be non-zero");
+    Tally t;
+    t.desc = *d;
+    t.nbins = nb;
+    if (c->device >= 0) {
+        int rc = set_device(c);
+        if (rc) return rc;
+        if (hipMalloc((void**)&t.dev, 2 * nb * sizeof(double)) != hipSuccess)
+            return fail(c, PR_ENOMEM, "cannot allocate %llu tally bins on the device", (unsigned long long)nb);
+        hipError_t e = zero_f64(t.dev, 2 * nb, nullptr);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            (void)hipFree(t.dev);
+            return hipfail(c, e, "zeroing tally");
+        }
+    }
+    c->tallies.push_back(t);
+    *id = (int32_t)c->tallies.size() - 1;
+    return PR_OK;
+}
+
+extern "C" int pr_tally_nbins(pr_ctx* c, int32_t tally, uint64_t* nbins) {
+    if (!c || !nbins) return fail(c, PR_EINVAL, "null argument");
+    if (tally < 0 || tally >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", tally);
+    *nbins = c->tallies[tally].nbins;
+    return PR_OK;
+}
+
+// =========================================================================
+// run
+// =========================================================================
+
+static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
+                        uint64_t n, int32_t precision, void* records, Params& P) {
+    if (geom < 0 || geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "geometry %d unknown", geom);
+    if (src < 0 || src >= (int)c->srcs.size()) return fail(c, PR_ENOTFOUND, "source %d unknown", src);
+    if (nt < 0 || nt > kMaxTallies) return fail(c, PR_EINVAL, "n_tallies must be in [0, %d]", kMaxTallies);
+    if (nt > 0 && !tallies) return fail(c, PR_EINVAL, "tallies is null");
+    if (precision != PR_FP64_PLAIN && precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "precision invalid");
+    if (n > (1ull << 48) || first > (1ull << 62)) return fail(c, PR_EINVAL, "history range too large");
+    const Geometry& g = c->geoms[geom];
+    memset(&P, 0, sizeof(P));
+    P.vols_d = (const VolT<double>*)g.vols_d;
+    P.mats_d = (const MatT<double>*)g.mats_d;
+    P.fams_d = (const FamT<double>*)g.fams_d;
+    P.vols_f = (const VolT<float>*)g.vols_f;
+    P.mats_f = (const MatT<float>*)g.mats_f;
+    P.fams_f = (const FamT<float>*)g.fams_f;
+    P.children = (const int32_t*)g.children;
+    P.n_vols = g.nv;
+    P.n_mats = g.nm;
+    P.n_fams = g.nf;
+    P.n_children = g.nc;
+    const pr_source_desc& s = c->srcs[src];
+    SourceDev& d = P.src;
+    d.kind = s.kind;
+    d.spectrum = s.spectrum;
+    double nd = std::sqrt(s.dir[0] * s.dir[0] + s.dir[1] * s.dir[1] + s.dir[2] * s.dir[2]);
+    for (int k = 0; k < 3; ++k) {
+        d.o[k] = s.origin[k];
+        d.u[k] = s.dir[k] / nd;
+    }
+    d.size[0] = s.size[0];
+    d.size[1] = s.size[1];
+    d.div_rad[0] = s.div_deg[0] * 3.14159265358979323846 / 180.0;
+    d.div_rad[1] = s.div_deg[1] * 3.14159265358979323846 / 180.0;
+    d.lam0 = s.lam0;
+    d.lam_lo = s.lam_lo;
+    d.lam_hi = s.lam_hi;
+    d.kT = s.kT;
+    d.e_const = ev_angstrom2();
+    P.n_tallies = nt;
+    int lds_doubles = 0;
+    const int budget = precision == PR_FP32_MIXED ? c->lds_tally_budget / 8 : 0;
+    for (int i = 0; i < nt; ++i) {
+        int t = tallies[i];
+        if (t < 0 || t >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", t);
+        for (int j = 0; j < i; ++j)
+            if (tallies[j] == t) return fail(c, PR_EINVAL, "tally %d listed twice", t);
+        const Tally& T = c->tallies[t];
+        const pr_tally_desc& td = T.desc;
+        if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= g.nv)
+            return fail(c, PR_EINVAL, "tally %d: trigger_volume beyond the geometry", t);
+        TallyDev& o = P.tallies[i];
+        o.trigger = td.trigger;
+        o.trigger_volume = td.trigger_volume;
+        o.filter = td.filter;
+        o.filter_arg = td.filter_arg;
+        o.naxes = td.naxes;
+        for (int a = 0; a < td.naxes; ++a) {
+            o.quantity[a] = td.axes[a].quantity;
+            o.nbins[a] = td.axes[a].nbins;
+            o.lo[a] = td.axes[a].lo;
+            o.hi[a] = td.axes[a].hi;
+            o.scale[a] = td.axes[a].nbins / (td.axes[a].hi - td.axes[a].lo);
+        }
+        double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
+        for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
+        o.sw = T.dev;
+        o.sw2 = T.dev ? T.dev + T.nbins : nullptr;
+        o.total = (int64_t)T.nbins;
+        o.lds_offset = -1;
+        if ((int64_t)lds_doubles + 2 * (int64_t)T.nbins <= budget) {
+            o.lds_offset = lds_doubles;
+            lds_doubles += 2 * (int)T.nbins;
+        }
+    }
+    P.lds_tally_doubles = lds_doubles;
+    P.seed = c->seed;
+    P.first = first;
+    P.n = n;
+    P.records = (pr_history_record*)records;
+    P.stats = c->stats;
+    P.counter = c->counter;
+    P.refill_threshold = c->refill_threshold;
+    return PR_OK;
+}
+
+extern "C" int pr_run_histories(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt,
+                                uint64_t first, uint64_t n, int32_t precision, void* records, void* stream) {
+    if (!c) return PR_EINVAL;
+    Params P;
+    int rc = build_params(c, geom, src, tallies, nt, first, n, precision, records, P);
+    if (rc) return rc;
+    if ((rc = set_device(c))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (precision == PR_FP64_PLAIN) {
+        e = launch_plain(P, records != nullptr, st);
+    } else {
+        const int block = c->mixed_block;
+        int lds = mixed_lds_bytes(P);
+        if (lds > 160 * 1024) return fail(c, PR_EINVAL, "scene and tallies need %d bytes of LDS", lds);
+        int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : mixed_occupancy(P, block);
+        uint64_t want = (n + block - 1) / block;
+        uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, want);
+        if (grid < 1) grid = 1;
+        e = launch_mixed(P, records != nullptr, (int)grid, block, st);
+    }
+    if (e != hipSuccess) return hipfail(c, e, "kernel launch");
+    for (int i = 0; i < nt; ++i) c->tallies[tallies[i]].n_hist += n;
+    return PR_OK;
+}
+
+// =========================================================================
+// results
+// =========================================================================
+
+extern "C" int pr_read_tally_range(pr_ctx* c, int32_t tally, uint64_t offset, uint64_t count, double* sw, double* sw2,
+                                   void* stream) {
+    if (!c) return PR_EINVAL;
+    if (tally < 0 || tally >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", tally);
+    const Tally& T = c->tallies[tally];
+    if (offset > T.nbins || count > T.nbins - offset) return fail(c, PR_EWORKSPACE, "range beyond the tally's bins");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    if (count == 0) return PR_OK;
+    if (sw) HIPCHK(c, hipMemcpy(sw, T.dev + offset, count * sizeof(double), hipMemcpyDeviceToHost));
+    if (sw2) HIPCHK(c, hipMemcpy(sw2, T.dev + T.nbins + offset, count * sizeof(double), hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+extern "C" int pr_read_tally(pr_ctx* c, int32_t tally, double* sw, double* sw2, uint64_t* n_hist, size_t nbins,
+                             void* stream) {
+    if (!c) return PR_EINVAL;
+    if (tally < 0 || tally >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", tally);
+    const Tally& T = c->tallies[tally];
+    if ((sw || sw2) && nbins < T.nbins)
+        return fail(c, PR_EWORKSPACE, "tally %d has %llu bins, buffer holds %zu", tally, (unsigned long long)T.nbins, nbins);
+    if (n_hist) *n_hist = T.n_hist;
+    return pr_read_tally_range(c, tally, 0, (sw || sw2) ? T.nbins : 0, sw, sw2, stream);
+}
+
+extern "C" int pr_reset_tally(pr_ctx* c, int32_t tally, void* stream) {
+    if (!c) return PR_EINVAL;
+    if (tally < 0 || tally >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", tally);
+    Tally& T = c->tallies[tally];
+    int rc = set_device(c);
+    if (rc) return rc;
+    hipError_t e = zero_f64(T.dev, 2 * T.nbins, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(c, e, "zeroing tally");
+    T.n_hist = 0;
+    return PR_OK;
+}
+
+extern "C" int pr_read_stats(pr_ctx* c, pr_run_stats* out, void* stream) {
+    if (!c || !out) return fail(c, PR_EINVAL, "null argument");
+    int rc = set_device(c);
+    if (rc) return rc;
+    unsigned long long h[ST_N];
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    HIPCHK(c, hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
+    out->histories = h[ST_HIST];
+    out->escaped = h[ST_ESC];
+    out->absorbed = h[ST_ABS];
+    out->killed = h[ST_KILL];
+    out->detected = h[ST_DET];
+    out->capped = h[ST_CAP];
+    out->outside = h[ST_OUT];
+    out->steps = h[ST_STEPS];
+    out->draws = h[ST_DRAWS];
+    out->scatters = h[ST_SCAT];
+    return PR_OK;
+}
+
+extern "C" int pr_reset_stats(pr_ctx* c, void* stream) {
+    if (!c) return PR_EINVAL;
+    int rc = set_device(c);
+    if (rc) return rc;
+    hipError_t e = zero_u64(c->stats, ST_N, (hipStream_t)stream);
+    if (e != hipSuccess) return hipfail(c, e, "zeroing stats");
+    return PR_OK;
+}

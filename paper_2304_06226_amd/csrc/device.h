@@ -1,0 +1,760 @@
+// Internal device-side layout and history-step machinery of prompt_mi355x.
+//
+// One history = source sample, then steps until absorption, escape, a mirror
+// kill or detection.  A step locates the nearest boundary (own exit or daughter
+// entry), samples a biased free flight, moves, corrects the weight and either
+// collides or relocates.  The step is written once, templated on the real
+// type R (double for the plain policy, float for the mixed policy) and on a
+// scene view whose arrays live in global memory (plain) or LDS (mixed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/prompt_mi355x.h"
+
+namespace prk {
+
+constexpr int kMaxSteps = PR_MAX_STEPS;
+constexpr int kMaxTallies = PR_MAX_TALLIES;
+constexpr int kWave = 64;
+
+// -------------------------------------------------------------------------
+// Scene layout (host builds it once per geometry; arrays in device memory)
+// -------------------------------------------------------------------------
+
+// Volume with kind-specific sizes pre-digested:
+//   box: s = half sides; cylinder: s = {r, h/2, -}; cyl shell: {r_in, r_out, h/2};
+//   sphere: {r}; sph shell: {r_in, r_out}.
+template <class R>
+struct VolT {
+    R c[3];
+    R s[3];
+    int32_t kind, axis, parent, mat;
+    int32_t detector, mirror_mask, child_begin, child_count;
+    int32_t mirror_model, pad;
+    R R0, Qc, alpha, mQc, W;
+};
+
+// Material in macroscopic units (1/mm):
+//   Sigma_a = sa_per_lambda * lambda, Sigma_i = si, Sigma_c = sc_k * lambda^2 * C(lambda)
+// with C(lambda) = cum[J-1], J = number of Bragg edges 2d above lambda.
+template <class R>
+struct MatT {
+    R sa_per_lambda, si, sc_k, ga, gs;
+    int32_t fam_begin, nfam;
+};
+
+// Bragg family tables, all materials concatenated (canonical order per material)
+template <class R>
+struct FamT {
+    R edge;     // 2 d
+    R cum;      // prefix sum of m d F^2 within the material
+    R inv2d2;   // 1 / (2 d^2): cos(2 theta) = 1 - lambda^2 inv2d2
+    R pad;
+};
+
+template <class R>
+struct SceneT {
+    const VolT<R>* vols;
+    const MatT<R>* mats;
+    const FamT<R>* fams;
+    const int32_t* children;
+};
+
+struct SourceDev {
+    int32_t kind, spectrum;
+    double o[3], u[3];
+    double size[2];
+    double div_rad[2];
+    double lam0, lam_lo, lam_hi, kT;
+    double e_const;   // h^2 / (2 m_n) in eV A^2
+};
+
+struct TallyDev {
+    int32_t trigger, trigger_volume, filter, filter_arg, naxes, lds_offset;   // lds_offset in doubles, -1 = global
+    int32_t quantity[4];
+    int32_t nbins[4];
+    double lo[4], hi[4], scale[4];   // scale = nbins / (hi - lo)
+    double beam[3];                  // unit vector
+    double* sw;
+    double* sw2;
+    int64_t total;
+};
+
+enum : int { ST_HIST = 0, ST_ESC, ST_ABS, ST_KILL, ST_DET, ST_CAP, ST_OUT, ST_STEPS, ST_DRAWS, ST_SCAT, ST_N };
+
+struct Params {
+    // scene (both precisions; the mixed policy stages the float copy into LDS)
+    const VolT<double>* vols_d;
+    const MatT<double>* mats_d;
+    const FamT<double>* fams_d;
+    const VolT<float>* vols_f;
+    const MatT<float>* mats_f;
+    const FamT<float>* fams_f;
+    const int32_t* children;
+    int32_t n_vols, n_mats, n_fams, n_children;
+    SourceDev src;
+    int32_t n_tallies, lds_tally_doubles;
+    TallyDev tallies[kMaxTallies];
+    uint64_t seed, first, n;
+    pr_history_record* records;
+    unsigned long long* stats;
+    unsigned long long* counter;   // history counter of the persistent policy
+    int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
+    int32_t pad;
+};
+
+// -------------------------------------------------------------------------
+// Precision policies
+// -------------------------------------------------------------------------
+
+template <class R>
+struct M;
+
+template <>
+struct M<double> {
+    static __device__ __forceinline__ double log_(double x) { return ::log(x); }
+    static __device__ __forceinline__ double exp_(double x) { return ::exp(x); }
+    static __device__ __forceinline__ double sqrt_(double x) { return ::sqrt(x); }
+    static __device__ __forceinline__ double div_(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double tan_(double x) { return ::tan(x); }
+    static __device__ __forceinline__ double cos_(double x) { return ::cos(x); }
+    // phi = 2 pi u; (cos phi, sin phi)
+    static __device__ __forceinline__ void cs2pi(double u, double* c, double* s) {
+        double phi = 2.0 * 3.14159265358979323846 * u;
+        *c = ::cos(phi);
+        *s = ::sin(phi);
+    }
+    static __device__ __forceinline__ double acos_deg(double c) { return ::acos(c) * (180.0 / 3.14159265358979323846); }
+    static __device__ __forceinline__ double atan2_deg(double y, double x) {
+        return ::atan2(y, x) * (180.0 / 3.14159265358979323846);
+    }
+    static __device__ __forceinline__ double tanh_(double x) { return ::tanh(x); }
+    // 53-bit uniform in [0,1) from two Philox words
+    static __device__ __forceinline__ double uni(uint32_t a, uint32_t b) {
+        return (double)(a >> 5) * (1.0 / 134217728.0) + (double)(b >> 6) * (1.0 / 9007199254740992.0);
+    }
+};
+
+template <>
+struct M<float> {
+    static __device__ __forceinline__ float log_(float x) { return __logf(x); }
+    static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float tan_(float x) { return ::tanf(x); }
+    static __device__ __forceinline__ float cos_(float x) { return __cosf(x); }
+    // the hardware sine/cosine take their argument in revolutions: sin(2 pi u)
+    static __device__ __forceinline__ void cs2pi(float u, float* c, float* s) {
+        *c = __builtin_amdgcn_cosf(u);
+        *s = __builtin_amdgcn_sinf(u);
+    }
+    static __device__ __forceinline__ float acos_deg(float c) { return ::acosf(c) * (180.0f / 3.14159265f); }
+    static __device__ __forceinline__ float atan2_deg(float y, float x) { return ::atan2f(y, x) * (180.0f / 3.14159265f); }
+    static __device__ __forceinline__ float tanh_(float x) { return ::tanhf(x); }
+    // 24-bit uniform in [0,1) from the first word of the pair
+    static __device__ __forceinline__ float uni(uint32_t a, uint32_t) { return (float)(a >> 8) * (1.0f / 16777216.0f); }
+};
+
+// -------------------------------------------------------------------------
+// Philox4x32-10, counter = (block, history), key = seed
+// -------------------------------------------------------------------------
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
+        uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo1;
+        c2 = n2;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// -------------------------------------------------------------------------
+// Particle state (registers)
+// -------------------------------------------------------------------------
+
+template <class R>
+struct PState {
+    R p[3], u[3];
+    R lam;
+    double w;
+    uint64_t h;
+    uint64_t hash;
+    uint32_t k;          // next draw index
+    uint32_t c2, c3;     // words 2,3 of the current block (odd draws)
+    int32_t region, nscat, steps, term;
+    // cross sections cached for material xs_mat (lambda is constant per history)
+    int32_t xs_mat, nact;
+    R sa, si, sc, sig, sig_g, ga, gs, cl;
+};
+
+template <class R>
+__device__ __forceinline__ R draw(PState<R>& s, uint64_t seed) {
+    uint32_t a, b;
+    if ((s.k & 1u) == 0u) {
+        uint32_t blk = s.k >> 1;
+        U4 o = philox10(blk, 0u, (uint32_t)s.h, (uint32_t)(s.h >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
+        a = o.x;
+        b = o.y;
+        s.c2 = o.z;
+        s.c3 = o.w;
+    } else {
+        a = s.c2;
+        b = s.c3;
+    }
+    s.k++;
+    return M<R>::uni(a, b);
+}
+
+template <bool REC>
+__device__ __forceinline__ void hash_ev(uint64_t& h, int code, int arg) {
+    if (!REC) return;
+    uint32_t word = ((uint32_t)code << 24) | ((uint32_t)arg & 0xFFFFFFu);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        h ^= (word >> (8 * i)) & 0xFFu;
+        h *= 1099511628211ull;
+    }
+}
+
+enum : int { EV_SOURCE = 1, EV_ENTER = 2, EV_EXIT = 3, EV_MIRROR = 4, EV_ABS = 5, EV_INC = 6, EV_COH = 7,
+             EV_ESCAPE = 8, EV_KILL = 9, EV_DETECT = 10, EV_CAPPED = 11 };
+
+// -------------------------------------------------------------------------
+// Geometry: pieces of the ray inside a solid (at most two, for shells)
+// -------------------------------------------------------------------------
+
+template <class R>
+struct Pieces {
+    R a[2], b[2];
+    int8_t fa[2], fb[2];
+    int n;
+};
+
+template <class R>
+__device__ __forceinline__ R rinf() {
+    return (R)__builtin_huge_val();
+}
+
+// t-range where lo <= q + t u <= hi on one coordinate; returns false if empty
+template <class R>
+__device__ __forceinline__ bool slab1(R q, R u, R lo, R hi, int flo, int fhi, R& ta, R& tb, int& fa, int& fb) {
+    if (u == (R)0) {
+        if (q >= lo && q <= hi) {
+            ta = -rinf<R>();
+            tb = rinf<R>();
+            fa = fb = -1;
+            return true;
+        }
+        return false;
+    }
+    R t1 = M<R>::div_(lo - q, u), t2 = M<R>::div_(hi - q, u);
+    if (u > (R)0) {
+        ta = t1; tb = t2; fa = flo; fb = fhi;
+    } else {
+        ta = t2; tb = t1; fa = fhi; fb = flo;
+    }
+    return true;
+}
+
+// intersect [ta,tb] with [xa,xb] keeping faces; false if empty
+template <class R>
+__device__ __forceinline__ bool clip(R& ta, R& tb, int& fa, int& fb, R xa, R xb, int xfa, int xfb) {
+    if (xa > ta) { ta = xa; fa = xfa; }
+    if (xb < tb) { tb = xb; fb = xfb; }
+    return ta <= tb;
+}
+
+// |q_perp + t u_perp| <= r
+template <class R>
+__device__ __forceinline__ bool disc_range(R qb, R qc, R ub, R uc, R r, R& ta, R& tb) {
+    R A = ub * ub + uc * uc;
+    R B = qb * ub + qc * uc;
+    R C = qb * qb + qc * qc - r * r;
+    if (A == (R)0) {
+        if (C <= (R)0) { ta = -rinf<R>(); tb = rinf<R>(); return true; }
+        return false;
+    }
+    R D = B * B - A * C;
+    if (D < (R)0) return false;
+    R sq = M<R>::sqrt_(D);
+    ta = M<R>::div_(-B - sq, A);
+    tb = M<R>::div_(-B + sq, A);
+    return true;
+}
+
+template <class R>
+__device__ __forceinline__ bool ball_range(const R q[3], const R u[3], R r, R& ta, R& tb) {
+    R A = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    R B = q[0] * u[0] + q[1] * u[1] + q[2] * u[2];
+    R C = q[0] * q[0] + q[1] * q[1] + q[2] * q[2] - r * r;
+    R D = B * B - A * C;
+    if (D < (R)0) return false;
+    R sq = M<R>::sqrt_(D);
+    ta = M<R>::div_(-B - sq, A);
+    tb = M<R>::div_(-B + sq, A);
+    return true;
+}
+
+template <class R>
+__device__ __forceinline__ bool cyl_range(const R q[3], const R u[3], int ax, R r, R hh, int lat, R& ta, R& tb, int& fa,
+                                          int& fb) {
+    int b = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
+    int c = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
+    R ra, rb;
+    if (!disc_range<R>(q[b], q[c], u[b], u[c], r, ra, rb)) return false;
+    int za, zb;
+    R sa, sb;
+    if (!slab1<R>(q[ax], u[ax], -hh, hh, 1, 2, sa, sb, za, zb)) return false;
+    ta = ra; tb = rb; fa = lat; fb = lat;
+    if (ra == -rinf<R>()) { fa = -1; fb = -1; }
+    return clip<R>(ta, tb, fa, fb, sa, sb, za, zb);
+}
+
+// outer piece minus inner piece
+template <class R>
+__device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int ofb, bool has_in, R ia, R ib, int ifa,
+                                         int ifb) {
+    if (!has_in || ib <= oa || ia >= ob) {
+        P.a[0] = oa; P.b[0] = ob; P.fa[0] = (int8_t)ofa; P.fb[0] = (int8_t)ofb; P.n = 1;
+        return;
+    }
+    int n = 0;
+    if (ia > oa) { P.a[n] = oa; P.b[n] = ia; P.fa[n] = (int8_t)ofa; P.fb[n] = (int8_t)ifa; ++n; }
+    if (ib < ob) { P.a[n] = ib; P.b[n] = ob; P.fa[n] = (int8_t)ifb; P.fb[n] = (int8_t)ofb; ++n; }
+    P.n = n;
+}
+
+template <class R>
+__device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
+    R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
+    P.n = 0;
+    switch (V.kind) {
+    case PR_BOX: {
+        R ta = -rinf<R>(), tb = rinf<R>();
+        int fa = -1, fb = -1;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            R xa, xb;
+            int xfa, xfb;
+            if (!slab1<R>(q[k], u[k], -V.s[k], V.s[k], 2 * k, 2 * k + 1, xa, xb, xfa, xfb)) return;
+            if (!clip<R>(ta, tb, fa, fb, xa, xb, xfa, xfb)) return;
+        }
+        P.a[0] = ta; P.b[0] = tb; P.fa[0] = (int8_t)fa; P.fb[0] = (int8_t)fb; P.n = 1;
+        return;
+    }
+    case PR_CYLINDER: {
+        R ta, tb;
+        int fa, fb;
+        if (!cyl_range<R>(q, u, V.axis, V.s[0], V.s[1], 0, ta, tb, fa, fb)) return;
+        P.a[0] = ta; P.b[0] = tb; P.fa[0] = (int8_t)fa; P.fb[0] = (int8_t)fb; P.n = 1;
+        return;
+    }
+    case PR_CYL_SHELL: {
+        R oa, ob, ia, ib;
+        int ofa, ofb, ifa, ifb;
+        if (!cyl_range<R>(q, u, V.axis, V.s[1], V.s[2], 0, oa, ob, ofa, ofb)) return;
+        bool hin = cyl_range<R>(q, u, V.axis, V.s[0], V.s[2], 3, ia, ib, ifa, ifb);
+        subtract<R>(P, oa, ob, ofa, ofb, hin, ia, ib, ifa, ifb);
+        return;
+    }
+    case PR_SPHERE: {
+        R ta, tb;
+        if (!ball_range<R>(q, u, V.s[0], ta, tb)) return;
+        P.a[0] = ta; P.b[0] = tb; P.fa[0] = 0; P.fb[0] = 0; P.n = 1;
+        return;
+    }
+    default: {  // spherical shell
+        R oa, ob, ia, ib;
+        if (!ball_range<R>(q, u, V.s[1], oa, ob)) return;
+        bool hin = ball_range<R>(q, u, V.s[0], ia, ib);
+        subtract<R>(P, oa, ob, 0, 0, hin, ia, ib, 3, 3);
+        return;
+    }
+    }
+}
+
+template <class R>
+__device__ __forceinline__ bool contains(const VolT<R>& V, const R p[3]) {
+    R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
+    switch (V.kind) {
+    case PR_BOX:
+        return __builtin_fabs((double)q[0]) <= (double)V.s[0] && __builtin_fabs((double)q[1]) <= (double)V.s[1] &&
+               __builtin_fabs((double)q[2]) <= (double)V.s[2];
+    case PR_CYLINDER:
+    case PR_CYL_SHELL: {
+        int a = V.axis, b = (a + 1) % 3, c = (a + 2) % 3;
+        R rho2 = q[b] * q[b] + q[c] * q[c];
+        R hh = V.kind == PR_CYLINDER ? V.s[1] : V.s[2];
+        R ro = V.kind == PR_CYLINDER ? V.s[0] : V.s[1];
+        bool in = rho2 <= ro * ro && (q[a] <= hh && q[a] >= -hh);
+        if (V.kind == PR_CYL_SHELL) in = in && rho2 >= V.s[0] * V.s[0];
+        return in;
+    }
+    case PR_SPHERE:
+        return q[0] * q[0] + q[1] * q[1] + q[2] * q[2] <= V.s[0] * V.s[0];
+    default: {
+        R r2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+        return r2 >= V.s[0] * V.s[0] && r2 <= V.s[1] * V.s[1];
+    }
+    }
+}
+
+// outward normal of face f at point p
+template <class R>
+__device__ __forceinline__ void normal(const VolT<R>& V, int f, const R p[3], R n[3]) {
+    n[0] = n[1] = n[2] = (R)0;
+    if (V.kind == PR_BOX) {
+        n[f >> 1] = (f & 1) ? (R)1 : (R)-1;
+        return;
+    }
+    R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
+    if (V.kind == PR_CYLINDER || V.kind == PR_CYL_SHELL) {
+        int a = V.axis, b = (a + 1) % 3, c = (a + 2) % 3;
+        if (f == 1) { n[a] = (R)-1; return; }
+        if (f == 2) { n[a] = (R)1; return; }
+        R r = M<R>::sqrt_(q[b] * q[b] + q[c] * q[c]);
+        R sg = f == 3 ? (R)-1 : (R)1;
+        n[b] = sg * M<R>::div_(q[b], r);
+        n[c] = sg * M<R>::div_(q[c], r);
+        return;
+    }
+    R r = M<R>::sqrt_(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    R sg = f == 3 ? (R)-1 : (R)1;
+    for (int k = 0; k < 3; ++k) n[k] = sg * M<R>::div_(q[k], r);
+}
+
+template <class R>
+__device__ __forceinline__ R reflectivity(const VolT<R>& V, R Q) {
+    if (Q <= V.Qc) return V.R0;
+    R r;
+    if (V.mirror_model == PR_MIRROR_TANH) {
+        r = (R)0.5 * V.R0 * ((R)1 - V.alpha * (Q - V.Qc)) * ((R)1 - M<R>::tanh_(M<R>::div_(Q - V.mQc, V.W)));
+    } else {
+        if (Q > V.mQc) return (R)0;
+        r = V.R0 - V.alpha * (Q - V.Qc);
+    }
+    return r > (R)0 ? r : (R)0;
+}
+
+// innermost volume containing p, -1 outside the world
+template <class R>
+__device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3]) {
+    if (!contains<R>(S.vols[0], p)) return -1;
+    int cur = 0;
+    for (int depth = 0; depth < 64; ++depth) {
+        const VolT<R>& V = S.vols[cur];
+        int next = -1;
+        for (int i = 0; i < V.child_count; ++i) {
+            int c = S.children[V.child_begin + i];
+            if (contains<R>(S.vols[c], p)) { next = c; break; }
+        }
+        if (next < 0) break;
+        cur = next;
+    }
+    return cur;
+}
+
+// -------------------------------------------------------------------------
+// Source
+// -------------------------------------------------------------------------
+
+template <class R, bool REC>
+__device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h) {
+    s.h = h;
+    s.k = 0;
+    s.w = 1.0;
+    s.nscat = 0;
+    s.steps = 0;
+    s.term = 0;
+    s.xs_mat = -2;
+    s.hash = 14695981039346656037ull;
+    R p[3] = {(R)src.o[0], (R)src.o[1], (R)src.o[2]};
+    R u[3] = {(R)src.u[0], (R)src.u[1], (R)src.u[2]};
+    if (src.kind != PR_PENCIL) {
+        R a = draw<R>(s, seed);
+        R b = draw<R>(s, seed);
+        p[0] += (a - (R)0.5) * (R)src.size[0];
+        p[1] += (b - (R)0.5) * (R)src.size[1];
+    }
+    if (src.kind == PR_RECT_DIVERGENT) {
+        R ax = ((R)2 * draw<R>(s, seed) - (R)1) * (R)src.div_rad[0];
+        R ay = ((R)2 * draw<R>(s, seed) - (R)1) * (R)src.div_rad[1];
+        R tx = M<R>::tan_(ax), ty = M<R>::tan_(ay);
+        R nrm = M<R>::sqrt_(tx * tx + ty * ty + (R)1);
+        u[0] = M<R>::div_(tx, nrm);
+        u[1] = M<R>::div_(ty, nrm);
+        u[2] = M<R>::div_((R)1, nrm);
+    }
+    R lam = (R)src.lam0;
+    if (src.spectrum == PR_UNIFORM) {
+        lam = (R)src.lam_lo + draw<R>(s, seed) * (R)(src.lam_hi - src.lam_lo);
+    } else if (src.spectrum == PR_MAXWELL) {
+        // Gamma(3/2) energy in units of kT: exponential + half a squared normal
+        for (int t = 0; t < 64; ++t) {
+            R x1 = (R)1 - draw<R>(s, seed);
+            R x2 = (R)1 - draw<R>(s, seed);
+            R u3 = draw<R>(s, seed);
+            R c = M<R>::cos_((R)(0.5 * 3.14159265358979323846) * u3);
+            R e = (R)src.kT * (-M<R>::log_(x1) - M<R>::log_(x2) * c * c);
+            lam = M<R>::sqrt_(M<R>::div_((R)src.e_const, e));
+            if (lam >= (R)src.lam_lo && lam <= (R)src.lam_hi) break;
+            if (t == 63) lam = lam < (R)src.lam_lo ? (R)src.lam_lo : (R)src.lam_hi;
+        }
+    }
+    for (int i = 0; i < 3; ++i) {
+        s.p[i] = p[i];
+        s.u[i] = u[i];
+    }
+    s.lam = lam;
+    s.region = locate<R>(S, s.p);
+    hash_ev<REC>(s.hash, EV_SOURCE, s.region);
+    if (s.region < 0) s.term = PR_END_OUTSIDE;
+}
+
+// -------------------------------------------------------------------------
+// Cross sections at the history's wavelength (cached per material)
+// -------------------------------------------------------------------------
+
+template <class R>
+__device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int mat) {
+    const MatT<R>& Mt = S.mats[mat];
+    // J = number of edges 2d > lambda (edges non-increasing): binary search
+    int lo = 0, hi = Mt.nfam;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if (S.fams[Mt.fam_begin + mid].edge > s.lam) lo = mid + 1; else hi = mid;
+    }
+    s.nact = lo;
+    R cl = lo > 0 ? S.fams[Mt.fam_begin + lo - 1].cum : (R)0;
+    s.cl = cl;
+    s.ga = Mt.ga;
+    s.gs = Mt.gs;
+    s.sa = Mt.ga > (R)0 ? Mt.sa_per_lambda * s.lam : (R)0;
+    s.si = Mt.gs > (R)0 ? Mt.si : (R)0;
+    s.sc = Mt.gs > (R)0 ? Mt.sc_k * s.lam * s.lam * cl : (R)0;
+    s.sig = s.sa + s.si + s.sc;
+    s.sig_g = s.ga * s.sa + s.gs * (s.si + s.sc);
+    s.xs_mat = mat;
+}
+
+// -------------------------------------------------------------------------
+// One step of the history loop
+// -------------------------------------------------------------------------
+
+template <class R, bool REC>
+__device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
+    if (s.steps >= kMaxSteps) {
+        s.term = PR_END_CAPPED;
+        hash_ev<REC>(s.hash, EV_CAPPED, 0);
+        return;
+    }
+    s.steps++;
+    const VolT<R>& V = S.vols[s.region];
+
+    // nearest boundary: leave this volume, or enter a daughter
+    Pieces<R> P;
+    pieces<R>(V, s.p, s.u, P);
+    R d_exit = rinf<R>();
+    int face = -1;
+    for (int i = 0; i < P.n; ++i)
+        if (P.b[i] > (R)0 && P.b[i] < d_exit) { d_exit = P.b[i]; face = P.fb[i]; }
+    if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
+    R d_child = rinf<R>();
+    int child = -1;
+    for (int ci = 0; ci < V.child_count; ++ci) {
+        int c = S.children[V.child_begin + ci];
+        Pieces<R> Q;
+        pieces<R>(S.vols[c], s.p, s.u, Q);
+        for (int i = 0; i < Q.n; ++i)
+            if (Q.a[i] > (R)0 && Q.a[i] < d_child) { d_child = Q.a[i]; child = c; }
+    }
+    bool to_child = d_child < d_exit;
+    R d_b = to_child ? d_child : d_exit;
+
+    R sig = (R)0, sig_g = (R)0;
+    if (V.mat >= 0) {
+        if (s.xs_mat != V.mat) load_xs<R>(s, S, V.mat);
+        sig = s.sig;
+        sig_g = s.sig_g;
+    }
+
+    bool collide = false;
+    R x = d_b;
+    if (sig_g > (R)0) {
+        R xi = (R)1 - draw<R>(s, seed);
+        R l = M<R>::div_(-M<R>::log_(xi), sig_g);
+        if (l < d_b) { collide = true; x = l; }
+    }
+    s.p[0] += x * s.u[0];
+    s.p[1] += x * s.u[1];
+    s.p[2] += x * s.u[2];
+    if (sig_g > (R)0) s.w *= (double)M<R>::exp_((sig_g - sig) * x);
+
+    if (collide) {
+        R r = draw<R>(s, seed) * sig_g;
+        R wa = s.ga * s.sa, wi = s.gs * s.si, wc = s.gs * s.sc;
+        if (r < wa || wi + wc == (R)0) {
+            s.w *= 1.0 / (double)s.ga;
+            s.term = PR_END_ABSORB;
+            hash_ev<REC>(s.hash, EV_ABS, 0);
+            return;
+        }
+        s.w *= 1.0 / (double)s.gs;
+        bool inc = r < wa + wi || wc == (R)0 || s.nact == 0;
+        R u1 = draw<R>(s, seed);
+        R u2 = draw<R>(s, seed);
+        R c2t;
+        int fam = 0;
+        if (inc) {
+            c2t = (R)2 * u1 - (R)1;
+        } else {
+            // family j: first with cumulative m d F^2 above u1 * C(lambda)
+            const MatT<R>& Mt = S.mats[s.xs_mat];
+            R cut = u1 * s.cl;
+            int lo = 0, hi = s.nact - 1;
+            while (lo < hi) {
+                int mid = (lo + hi) >> 1;
+                if (S.fams[Mt.fam_begin + mid].cum > cut) hi = mid; else lo = mid + 1;
+            }
+            fam = lo;
+            c2t = (R)1 - s.lam * s.lam * S.fams[Mt.fam_begin + fam].inv2d2;
+        }
+        R s2t = M<R>::sqrt_((R)1 - c2t * c2t);
+        R cp, sp;
+        M<R>::cs2pi(u2, &cp, &sp);
+        R nu[3];
+        if (inc) {
+            // isotropic: polar axis z of the laboratory frame
+            nu[0] = s2t * cp;
+            nu[1] = s2t * sp;
+            nu[2] = c2t;
+            hash_ev<REC>(s.hash, EV_INC, 0);
+        } else {
+            // Debye-Scherrer cone about the incoming direction
+            R ax0 = __builtin_fabs((double)s.u[0]) < 0.9 ? (R)1 : (R)0;
+            R ax1 = (R)1 - ax0;
+            // e1 = u x a (a = x or y), normalised; e2 = u x e1
+            R e1[3] = {-s.u[2] * ax1, s.u[2] * ax0, s.u[0] * ax1 - s.u[1] * ax0};
+            R inv = M<R>::div_((R)1, M<R>::sqrt_(e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2]));
+            e1[0] *= inv; e1[1] *= inv; e1[2] *= inv;
+            R e2[3] = {s.u[1] * e1[2] - s.u[2] * e1[1], s.u[2] * e1[0] - s.u[0] * e1[2], s.u[0] * e1[1] - s.u[1] * e1[0]};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) nu[k] = c2t * s.u[k] + s2t * (cp * e1[k] + sp * e2[k]);
+            hash_ev<REC>(s.hash, EV_COH, fam);
+        }
+        s.u[0] = nu[0];
+        s.u[1] = nu[1];
+        s.u[2] = nu[2];
+        s.nscat++;
+        return;
+    }
+
+    if (to_child) {
+        s.region = child;
+        hash_ev<REC>(s.hash, EV_ENTER, child);
+        if (S.vols[child].detector) {
+            s.term = PR_END_DETECT;
+            hash_ev<REC>(s.hash, EV_DETECT, child);
+        }
+        return;
+    }
+    if (face >= 0 && ((V.mirror_mask >> face) & 1)) {
+        R n[3];
+        normal<R>(V, face, s.p, n);
+        R un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
+        R Q = M<R>::div_((R)(4.0 * 3.14159265358979323846) * (R)__builtin_fabs((double)un), s.lam);
+        R refl = reflectivity<R>(V, Q);
+        s.w *= (double)refl;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) s.u[k] = s.u[k] - (R)2 * n[k] * un;
+        hash_ev<REC>(s.hash, EV_MIRROR, face);
+        if (!(s.w > 0.0)) {
+            s.term = PR_END_KILL;
+            hash_ev<REC>(s.hash, EV_KILL, 0);
+        }
+        return;
+    }
+    if (s.region == 0) {
+        s.term = PR_END_ESCAPE;
+        hash_ev<REC>(s.hash, EV_ESCAPE, 0);
+        return;
+    }
+    s.region = V.parent;
+    hash_ev<REC>(s.hash, EV_EXIT, s.region);
+}
+
+// -------------------------------------------------------------------------
+// Tally bin of a finished history (-1: not scored)
+// -------------------------------------------------------------------------
+
+template <class R>
+__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s) {
+    if (T.trigger == PR_TRIG_ESCAPE && s.term != PR_END_ESCAPE) return -1;
+    if (T.trigger == PR_TRIG_ABSORB && s.term != PR_END_ABSORB) return -1;
+    if (T.trigger == PR_TRIG_DETECT) {
+        if (s.term != PR_END_DETECT) return -1;
+        if (T.trigger_volume >= 0 && T.trigger_volume != s.region) return -1;
+    }
+    if (T.filter == PR_FILT_UNSCATTERED && s.nscat != 0) return -1;
+    if (T.filter == PR_FILT_SCATTERED && s.nscat < 1) return -1;
+    if (T.filter == PR_FILT_NSCAT_EQ && s.nscat != T.filter_arg) return -1;
+    int64_t flat = 0;
+    for (int a = 0; a < T.naxes; ++a) {
+        R x;
+        switch (T.quantity[a]) {
+        case PR_Q_THETA2: {
+            R c = s.u[0] * (R)T.beam[0] + s.u[1] * (R)T.beam[1] + s.u[2] * (R)T.beam[2];
+            c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
+            x = M<R>::acos_deg(c);
+            break;
+        }
+        case PR_Q_LAMBDA: x = s.lam; break;
+        case PR_Q_X: x = s.p[0]; break;
+        case PR_Q_Y: x = s.p[1]; break;
+        case PR_Q_Z: x = s.p[2]; break;
+        case PR_Q_DIVX: x = M<R>::atan2_deg(s.u[0], s.u[2]); break;
+        case PR_Q_DIVY: x = M<R>::atan2_deg(s.u[1], s.u[2]); break;
+        default: x = (R)s.nscat; break;
+        }
+        R lo = (R)T.lo[a], hi = (R)T.hi[a];
+        if (!(x >= lo && x <= hi)) return -1;
+        int n = T.nbins[a];
+        int b = (int)__builtin_floor((double)((x - lo) * (R)T.scale[a]));
+        if (x == hi || b >= n) b = n - 1;
+        if (b < 0) b = 0;
+        flat = flat * n + b;
+    }
+    return flat;
+}
+
+template <class R>
+__device__ __forceinline__ void write_record(pr_history_record* rec, const PState<R>& s) {
+    rec->hash = s.hash;
+    rec->w = s.w;
+    for (int k = 0; k < 3; ++k) {
+        rec->pos[k] = (double)s.p[k];
+        rec->dir[k] = (double)s.u[k];
+    }
+    rec->lambda = (double)s.lam;
+    rec->term = s.term;
+    rec->n_scat = s.nscat;
+    rec->n_steps = s.steps;
+    rec->n_draws = (int32_t)s.k;
+    rec->region = s.region;
+    rec->pad = 0;
+}
+
+}  // namespace prk

@@ -1,0 +1,17 @@
+// Internal launcher interface between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace prk {
+
+hipError_t launch_plain(const Params& P, bool rec, hipStream_t st);
+hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStream_t st);
+int mixed_occupancy(const Params& P, int block);
+int mixed_lds_bytes(const Params& P);
+hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st);
+hipError_t zero_f64(double* p, uint64_t n, hipStream_t st);
+
+}  // namespace prk

@@ -1,0 +1,262 @@
+// HIP kernels of the history loop and their launchers.
+//
+// PR_FP64_PLAIN: one thread per history, FP64 throughout, scene read from
+//   global memory, tallies scored with global FP64 atomics.
+// PR_FP32_MIXED: persistent waves.  Each lane holds one live history; when
+//   enough lanes of a wave are idle the wave claims that many new history ids
+//   with one atomic and hands them out by lane rank (ballot / popcount /
+//   mbcnt), so lanes stay busy until the work runs out.  The scene (volumes,
+//   materials, Bragg tables) is staged into LDS as FP32; small tallies are
+//   privatised in LDS and merged into global memory once per block; the
+//   weight product and every tally accumulation stay FP64.
+#include "device.h"
+#include "launch.h"
+
+namespace prk {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// sum of a 64-bit value over the wave, result valid in every lane
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+struct Counters {
+    unsigned long long c[ST_N];
+};
+
+template <class R>
+__device__ __forceinline__ void count_end(Counters& k, const PState<R>& s) {
+    k.c[ST_HIST] += 1;
+    k.c[ST_STEPS] += (unsigned long long)s.steps;
+    k.c[ST_DRAWS] += (unsigned long long)s.k;
+    k.c[ST_SCAT] += (unsigned long long)s.nscat;
+    switch (s.term) {
+    case PR_END_ESCAPE: k.c[ST_ESC] += 1; break;
+    case PR_END_ABSORB: k.c[ST_ABS] += 1; break;
+    case PR_END_KILL: k.c[ST_KILL] += 1; break;
+    case PR_END_DETECT: k.c[ST_DET] += 1; break;
+    case PR_END_CAPPED: k.c[ST_CAP] += 1; break;
+    default: k.c[ST_OUT] += 1; break;
+    }
+}
+
+__device__ __forceinline__ void flush_counters(const Counters& k, unsigned long long* g) {
+#pragma unroll
+    for (int i = 0; i < ST_N; ++i) {
+        unsigned long long t = wave_sum(k.c[i]);
+        if (lane_id() == 0 && t) atomicAdd(g + i, t);
+    }
+}
+
+// ------------------------------------------------------------------------
+// FP64 plain
+// ------------------------------------------------------------------------
+
+template <bool REC>
+__global__ __launch_bounds__(256) void k_plain(Params P) {
+    const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children};
+    Counters cnt = {};
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < P.n) {
+        PState<double> s;
+        source<double, REC>(s, P.src, S, P.seed, P.first + i);
+        while (s.term == 0) step<double, REC>(s, S, P.seed);
+        if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+            for (int t = 0; t < P.n_tallies; ++t) {
+                const TallyDev& T = P.tallies[t];
+                int64_t b = tally_bin<double>(T, s);
+                if (b >= 0) {
+                    atomicAdd(T.sw + b, s.w);
+                    atomicAdd(T.sw2 + b, s.w * s.w);
+                }
+            }
+        }
+        if (REC) write_record<double>(P.records + i, s);
+        count_end<double>(cnt, s);
+    }
+    flush_counters(cnt, P.stats);
+}
+
+// ------------------------------------------------------------------------
+// FP32 mixed, persistent
+// ------------------------------------------------------------------------
+
+struct LdsLayout {
+    int vols, mats, fams, children, bytes;   // byte offsets after the tally doubles
+};
+
+__host__ __device__ inline LdsLayout lds_layout(int nv, int nm, int nf, int nc, int tally_doubles) {
+    LdsLayout L;
+    int off = tally_doubles * 8;
+    L.vols = off;
+    off += nv * (int)sizeof(VolT<float>);
+    off = (off + 15) & ~15;
+    L.mats = off;
+    off += nm * (int)sizeof(MatT<float>);
+    off = (off + 15) & ~15;
+    L.fams = off;
+    off += nf * (int)sizeof(FamT<float>);
+    off = (off + 15) & ~15;
+    L.children = off;
+    off += nc * 4;
+    L.bytes = (off + 15) & ~15;
+    return L;
+}
+
+__device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes) {
+    const uint32_t* s = (const uint32_t*)src;
+    uint32_t* d = (uint32_t*)dst;
+    for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) d[i] = s[i];
+}
+
+template <bool REC>
+__global__ __launch_bounds__(256) void k_mixed(Params P) {
+    extern __shared__ double lds[];
+    const LdsLayout L = lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles);
+    char* base = (char*)lds;
+    copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
+    copy_words(base + L.mats, P.mats_f, P.n_mats * (int)sizeof(MatT<float>));
+    copy_words(base + L.fams, P.fams_f, P.n_fams * (int)sizeof(FamT<float>));
+    copy_words(base + L.children, P.children, P.n_children * 4);
+    for (int i = threadIdx.x; i < P.lds_tally_doubles; i += blockDim.x) lds[i] = 0.0;
+    __syncthreads();
+    const SceneT<float> S{(const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
+                          (const FamT<float>*)(base + L.fams), (const int32_t*)(base + L.children)};
+
+    Counters cnt = {};
+    PState<float> s;
+    s.term = 1;   // idle
+    bool exhausted = false;
+    const int lane = lane_id();
+    for (;;) {
+        const bool idle = s.term != 0;
+        const unsigned long long idle_mask = __ballot(idle);
+        const int n_idle = __popcll(idle_mask);
+        if (!exhausted && (n_idle >= P.refill_threshold || n_idle == kWave)) {
+            const int leader = __ffsll((long long)idle_mask) - 1;
+            unsigned long long got = 0;
+            if (lane == leader) got = atomicAdd(P.counter, (unsigned long long)n_idle);
+            got = __shfl(got, leader, kWave);
+            if (got + (unsigned long long)n_idle >= P.n) exhausted = true;
+            if (idle) {
+                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+                const unsigned long long idx = got + (unsigned long long)rank;
+                if (idx < P.n) {
+                    source<float, REC>(s, P.src, S, P.seed, P.first + idx);
+                    if (s.term != 0) {   // born outside the world
+                        if (REC) write_record<float>(P.records + (s.h - P.first), s);
+                        count_end<float>(cnt, s);
+                    }
+                }
+            }
+        }
+        if (__ballot(s.term == 0) == 0ull) {
+            if (exhausted) break;
+            continue;
+        }
+        if (s.term == 0) {
+            step<float, REC>(s, S, P.seed);
+            if (s.term != 0) {
+                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+                    for (int t = 0; t < P.n_tallies; ++t) {
+                        const TallyDev& T = P.tallies[t];
+                        int64_t b = tally_bin<float>(T, s);
+                        if (b >= 0) {
+                            if (T.lds_offset >= 0) {
+                                atomicAdd(lds + T.lds_offset + b, s.w);
+                                atomicAdd(lds + T.lds_offset + T.total + b, s.w * s.w);
+                            } else {
+                                atomicAdd(T.sw + b, s.w);
+                                atomicAdd(T.sw2 + b, s.w * s.w);
+                            }
+                        }
+                    }
+                }
+                if (REC) write_record<float>(P.records + (s.h - P.first), s);
+                count_end<float>(cnt, s);
+            }
+        }
+    }
+    flush_counters(cnt, P.stats);
+    __syncthreads();
+    // merge the block's privatised tallies (non-zero bins only)
+    for (int t = 0; t < P.n_tallies; ++t) {
+        const TallyDev& T = P.tallies[t];
+        if (T.lds_offset < 0) continue;
+        for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
+            double a = lds[T.lds_offset + i];
+            double b = lds[T.lds_offset + T.total + i];
+            if (a != 0.0 || b != 0.0) {
+                atomicAdd(T.sw + i, a);
+                atomicAdd(T.sw2 + i, b);
+            }
+        }
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long* p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
+__global__ void k_zero_f64(double* p, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0;
+}
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+
+int mixed_lds_bytes(const Params& P) {
+    return lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles).bytes;
+}
+
+hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
+    if (P.n == 0) return hipSuccess;
+    const int block = 256;
+    uint64_t grid = (P.n + block - 1) / block;
+    if (rec)
+        hipLaunchKernelGGL(k_plain<true>, dim3((unsigned)grid), dim3(block), 0, st, P);
+    else
+        hipLaunchKernelGGL(k_plain<false>, dim3((unsigned)grid), dim3(block), 0, st, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStream_t st) {
+    if (P.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.counter, 1);
+    int lds = mixed_lds_bytes(P);
+    if (rec)
+        hipLaunchKernelGGL(k_mixed<true>, dim3(grid), dim3(block), lds, st, P);
+    else
+        hipLaunchKernelGGL(k_mixed<false>, dim3(grid), dim3(block), lds, st, P);
+    return hipGetLastError();
+}
+
+int mixed_occupancy(const Params& P, int block) {
+    int nb = 0;
+    int lds = mixed_lds_bytes(P);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false>, block, lds) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u64, dim3((n + 63) / 64), dim3(64), 0, st, p, n);
+    return hipGetLastError();
+}
+
+hipError_t zero_f64(double* p, uint64_t n, hipStream_t st) {
+    if (n == 0) return hipSuccess;
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+    return hipGetLastError();
+}
+
+}  // namespace prk
