@@ -217,6 +217,28 @@ int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
 int pr_run_histories(pr_ctx* ctx, int32_t geom, int32_t src, const int32_t* tallies, int32_t n_tallies,
                      uint64_t first_history, uint64_t n, int32_t precision, void* records_dev, void* stream);
 
+/* ---- launch tuning of PR_FP32_MIXED ---- */
+/* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
+ * blocks per compute unit of the persistent grid (0 = occupancy limit);
+ * refill_threshold: idle lanes of a wave that trigger a refill (1..64);
+ * lds_tally_bytes: LDS per block for privatised tallies (tallies are
+ * privatised in order while they fit); bin_cache_slots: LDS bin-cache slots
+ * given to each tally that is not privatised (0 or a power of two <= 4096);
+ * chunk: history indices a wave claims from the shared counter per atomic.
+ * Results do not depend on these settings beyond floating-point summation
+ * order. */
+typedef struct {
+    int32_t block;
+    int32_t blocks_per_cu;
+    int32_t refill_threshold;
+    int32_t lds_tally_bytes;
+    int32_t bin_cache_slots;
+    int32_t chunk;
+} pr_tuning;
+
+int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
+int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
+
 /* ---- results ---- */
 /* Synchronise `stream` and copy the tally into host arrays of nbins doubles
  * each (either may be NULL); *n_hist receives the histories run since the

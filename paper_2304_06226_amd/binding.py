@@ -41,7 +41,8 @@ RECORD_BYTES = 96
 
 EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_material", "pr_create_geometry",
            "pr_create_source", "pr_create_tally", "pr_tally_nbins", "pr_run_histories", "pr_read_tally",
-           "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats"]
+           "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats", "pr_set_tuning",
+           "pr_get_tuning"]
 
 
 class pr_material_desc(C.Structure):
@@ -76,6 +77,11 @@ class pr_tally_desc(C.Structure):
     _fields_ = [("trigger", C.c_int32), ("trigger_volume", C.c_int32), ("filter", C.c_int32),
                 ("filter_arg", C.c_int32), ("naxes", C.c_int32), ("accumulator", C.c_int32),
                 ("axes", pr_tally_axis * 4), ("beam", C.c_double * 3)]
+
+
+class pr_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_threshold", C.c_int32),
+                ("lds_tally_bytes", C.c_int32), ("bin_cache_slots", C.c_int32), ("chunk", C.c_int32)]
 
 
 class pr_run_stats(C.Structure):
@@ -113,6 +119,8 @@ def load():
     L.pr_reset_tally.argtypes = [vp, i32, vp]
     L.pr_read_stats.argtypes = [vp, C.POINTER(pr_run_stats), vp]
     L.pr_reset_stats.argtypes = [vp, vp]
+    L.pr_set_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
+    L.pr_get_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pr_destroy", "pr_last_error"):
@@ -282,6 +290,17 @@ class Context:
         st = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(self.lib.pr_read_stats(self.h, C.byref(s), st))
         return {name: getattr(s, name) for name, _ in pr_run_stats._fields_}
+
+    def get_tuning(self) -> dict:
+        t = pr_tuning()
+        self._check(self.lib.pr_get_tuning(self.h, C.byref(t)))
+        return {name: getattr(t, name) for name, _ in pr_tuning._fields_}
+
+    def set_tuning(self, **kw):
+        cur = self.get_tuning()
+        cur.update(kw)
+        t = pr_tuning(**cur)
+        self._check(self.lib.pr_set_tuning(self.h, C.byref(t)))
 
     def reset_stats(self, stream=None):
         st = _current_stream() if stream is None else C.c_void_p(stream)

@@ -63,6 +63,8 @@ struct pr_ctx {
     int mixed_blocks_per_cu = 0;        // 0 = occupancy limit
     int refill_threshold = 16;
     int lds_tally_budget = 32768;       // bytes of LDS per block for privatised tallies
+    int bin_cache_slots = 1024;         // LDS bin-cache slots per non-privatised tally (power of two, 0 = off)
+    int chunk = 256;                    // history indices a wave claims per atomic
 };
 
 namespace {
@@ -682,11 +684,27 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         o.sw2 = T.dev ? T.dev + T.nbins : nullptr;
         o.total = (int64_t)T.nbins;
         o.lds_offset = -1;
+        o.cache_base = -1;
+        o.cache_bits = 0;
         if ((int64_t)lds_doubles + 2 * (int64_t)T.nbins <= budget) {
             o.lds_offset = lds_doubles;
             lds_doubles += 2 * (int)T.nbins;
         }
     }
+    // tallies too large to privatise get an LDS bin cache (mixed policy)
+    int slots = 0;
+    if (precision == PR_FP32_MIXED && c->bin_cache_slots > 0) {
+        int bits = 0;
+        while ((1 << (bits + 1)) <= c->bin_cache_slots) ++bits;
+        for (int i = 0; i < nt; ++i) {
+            TallyDev& o = P.tallies[i];
+            if (o.lds_offset >= 0 || o.total >= (int64_t)0xFFFFFFFFll) continue;
+            o.cache_base = slots;
+            o.cache_bits = bits;
+            slots += 1 << bits;
+        }
+    }
+    P.cache_slots = slots;
     P.lds_tally_doubles = lds_doubles;
     P.seed = c->seed;
     P.first = first;
@@ -695,6 +713,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.stats = c->stats;
     P.counter = c->counter;
     P.refill_threshold = c->refill_threshold;
+    P.chunk = c->chunk;
     return PR_OK;
 }
 
@@ -792,5 +811,38 @@ extern "C" int pr_reset_stats(pr_ctx* c, void* stream) {
     if (rc) return rc;
     hipError_t e = zero_u64(c->stats, ST_N, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(c, e, "zeroing stats");
+    return PR_OK;
+}
+
+// =========================================================================
+// launch tuning of the mixed policy
+// =========================================================================
+
+extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
+    if (!c || !t) return fail(c, PR_EINVAL, "null argument");
+    if (t->block < 64 || t->block > 256 || t->block % 64) return fail(c, PR_EINVAL, "tuning.block must be 64, 128, 192 or 256");
+    if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(c, PR_EINVAL, "tuning.blocks_per_cu must be 0..64");
+    if (t->refill_threshold < 1 || t->refill_threshold > 64) return fail(c, PR_EINVAL, "tuning.refill_threshold must be 1..64");
+    if (t->lds_tally_bytes < 0 || t->lds_tally_bytes > 131072) return fail(c, PR_EINVAL, "tuning.lds_tally_bytes must be 0..131072");
+    if (t->bin_cache_slots < 0 || t->bin_cache_slots > 4096 || (t->bin_cache_slots & (t->bin_cache_slots - 1)))
+        return fail(c, PR_EINVAL, "tuning.bin_cache_slots must be 0 or a power of two up to 4096");
+    if (t->chunk < 1 || t->chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.chunk must be 1..2^20");
+    c->chunk = t->chunk;
+    c->mixed_block = t->block;
+    c->mixed_blocks_per_cu = t->blocks_per_cu;
+    c->refill_threshold = t->refill_threshold;
+    c->lds_tally_budget = t->lds_tally_bytes;
+    c->bin_cache_slots = t->bin_cache_slots;
+    return PR_OK;
+}
+
+extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
+    if (!c || !t) return fail(c, PR_EINVAL, "null argument");
+    t->block = c->mixed_block;
+    t->blocks_per_cu = c->mixed_blocks_per_cu;
+    t->refill_threshold = c->refill_threshold;
+    t->lds_tally_bytes = c->lds_tally_budget;
+    t->bin_cache_slots = c->bin_cache_slots;
+    t->chunk = c->chunk;
     return PR_OK;
 }

@@ -72,7 +72,10 @@ struct SourceDev {
 };
 
 struct TallyDev {
-    int32_t trigger, trigger_volume, filter, filter_arg, naxes, lds_offset;   // lds_offset in doubles, -1 = global
+    int32_t trigger, trigger_volume, filter, filter_arg, naxes;
+    int32_t lds_offset;   // privatised copy in LDS (offset in doubles), -1 = none
+    int32_t cache_base;   // first slot of this tally's LDS bin cache, -1 = none
+    int32_t cache_bits;   // log2 of its slot count
     int32_t quantity[4];
     int32_t nbins[4];
     double lo[4], hi[4], scale[4];   // scale = nbins / (hi - lo)
@@ -96,13 +99,15 @@ struct Params {
     int32_t n_vols, n_mats, n_fams, n_children;
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
+    int32_t cache_slots;           // LDS bin-cache slots over all cached tallies (mixed policy)
+    int32_t pad1;
     TallyDev tallies[kMaxTallies];
     uint64_t seed, first, n;
     pr_history_record* records;
     unsigned long long* stats;
     unsigned long long* counter;   // history counter of the persistent policy
     int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
-    int32_t pad;
+    int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
 };
 
 // -------------------------------------------------------------------------
@@ -238,10 +243,17 @@ enum : int { EV_SOURCE = 1, EV_ENTER = 2, EV_EXIT = 3, EV_MIRROR = 4, EV_ABS = 5
 
 template <class R>
 struct Pieces {
-    R a[2], b[2];
-    int8_t fa[2], fb[2];
+    // at most two pieces [a0,b0], [a1,b1] (shells); fa/fb are the face ids at the ends
+    R a0, b0, a1, b1;
+    int fa0, fb0, fa1, fb1;
     int n;
 };
+
+// component i of a 3-vector by selects (no dynamically indexed private array)
+template <class R>
+__device__ __forceinline__ R pick(const R v[3], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
 
 template <class R>
 __device__ __forceinline__ R rinf() {
@@ -311,13 +323,13 @@ __device__ __forceinline__ bool ball_range(const R q[3], const R u[3], R r, R& t
 template <class R>
 __device__ __forceinline__ bool cyl_range(const R q[3], const R u[3], int ax, R r, R hh, int lat, R& ta, R& tb, int& fa,
                                           int& fb) {
-    int b = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
-    int c = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
+    const int b = ax == 0 ? 1 : (ax == 1 ? 2 : 0);
+    const int c = ax == 0 ? 2 : (ax == 1 ? 0 : 1);
     R ra, rb;
-    if (!disc_range<R>(q[b], q[c], u[b], u[c], r, ra, rb)) return false;
+    if (!disc_range<R>(pick(q, b), pick(q, c), pick(u, b), pick(u, c), r, ra, rb)) return false;
     int za, zb;
     R sa, sb;
-    if (!slab1<R>(q[ax], u[ax], -hh, hh, 1, 2, sa, sb, za, zb)) return false;
+    if (!slab1<R>(pick(q, ax), pick(u, ax), -hh, hh, 1, 2, sa, sb, za, zb)) return false;
     ta = ra; tb = rb; fa = lat; fb = lat;
     if (ra == -rinf<R>()) { fa = -1; fb = -1; }
     return clip<R>(ta, tb, fa, fb, sa, sb, za, zb);
@@ -328,13 +340,14 @@ template <class R>
 __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int ofb, bool has_in, R ia, R ib, int ifa,
                                          int ifb) {
     if (!has_in || ib <= oa || ia >= ob) {
-        P.a[0] = oa; P.b[0] = ob; P.fa[0] = (int8_t)ofa; P.fb[0] = (int8_t)ofb; P.n = 1;
+        P.a0 = oa; P.b0 = ob; P.fa0 = ofa; P.fb0 = ofb; P.n = 1;
         return;
     }
-    int n = 0;
-    if (ia > oa) { P.a[n] = oa; P.b[n] = ia; P.fa[n] = (int8_t)ofa; P.fb[n] = (int8_t)ifa; ++n; }
-    if (ib < ob) { P.a[n] = ib; P.b[n] = ob; P.fa[n] = (int8_t)ifb; P.fb[n] = (int8_t)ofb; ++n; }
-    P.n = n;
+    const bool lo = ia > oa, hi = ib < ob;
+    // first piece: the part before the inner solid if any, else the part after it
+    P.a0 = lo ? oa : ib; P.b0 = lo ? ia : ob; P.fa0 = lo ? ofa : ifb; P.fb0 = lo ? ifa : ofb;
+    P.a1 = ib; P.b1 = ob; P.fa1 = ifb; P.fb1 = ofb;
+    P.n = (lo ? 1 : 0) + (hi ? 1 : 0);
 }
 
 template <class R>
@@ -352,14 +365,14 @@ __device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u
             if (!slab1<R>(q[k], u[k], -V.s[k], V.s[k], 2 * k, 2 * k + 1, xa, xb, xfa, xfb)) return;
             if (!clip<R>(ta, tb, fa, fb, xa, xb, xfa, xfb)) return;
         }
-        P.a[0] = ta; P.b[0] = tb; P.fa[0] = (int8_t)fa; P.fb[0] = (int8_t)fb; P.n = 1;
+        P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
         return;
     }
     case PR_CYLINDER: {
         R ta, tb;
         int fa, fb;
         if (!cyl_range<R>(q, u, V.axis, V.s[0], V.s[1], 0, ta, tb, fa, fb)) return;
-        P.a[0] = ta; P.b[0] = tb; P.fa[0] = (int8_t)fa; P.fb[0] = (int8_t)fb; P.n = 1;
+        P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
         return;
     }
     case PR_CYL_SHELL: {
@@ -373,7 +386,7 @@ __device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u
     case PR_SPHERE: {
         R ta, tb;
         if (!ball_range<R>(q, u, V.s[0], ta, tb)) return;
-        P.a[0] = ta; P.b[0] = tb; P.fa[0] = 0; P.fb[0] = 0; P.n = 1;
+        P.a0 = ta; P.b0 = tb; P.fa0 = 0; P.fb0 = 0; P.n = 1;
         return;
     }
     default: {  // spherical shell
@@ -395,11 +408,12 @@ __device__ __forceinline__ bool contains(const VolT<R>& V, const R p[3]) {
                __builtin_fabs((double)q[2]) <= (double)V.s[2];
     case PR_CYLINDER:
     case PR_CYL_SHELL: {
-        int a = V.axis, b = (a + 1) % 3, c = (a + 2) % 3;
-        R rho2 = q[b] * q[b] + q[c] * q[c];
+        const int a = V.axis, b = a == 0 ? 1 : (a == 1 ? 2 : 0), c = a == 0 ? 2 : (a == 1 ? 0 : 1);
+        const R qa = pick(q, a), qb = pick(q, b), qc = pick(q, c);
+        R rho2 = qb * qb + qc * qc;
         R hh = V.kind == PR_CYLINDER ? V.s[1] : V.s[2];
         R ro = V.kind == PR_CYLINDER ? V.s[0] : V.s[1];
-        bool in = rho2 <= ro * ro && (q[a] <= hh && q[a] >= -hh);
+        bool in = rho2 <= ro * ro && (qa <= hh && qa >= -hh);
         if (V.kind == PR_CYL_SHELL) in = in && rho2 >= V.s[0] * V.s[0];
         return in;
     }
@@ -415,24 +429,34 @@ __device__ __forceinline__ bool contains(const VolT<R>& V, const R p[3]) {
 // outward normal of face f at point p
 template <class R>
 __device__ __forceinline__ void normal(const VolT<R>& V, int f, const R p[3], R n[3]) {
-    n[0] = n[1] = n[2] = (R)0;
     if (V.kind == PR_BOX) {
-        n[f >> 1] = (f & 1) ? (R)1 : (R)-1;
+        const int k = f >> 1;
+        const R sg = (f & 1) ? (R)1 : (R)-1;
+        n[0] = k == 0 ? sg : (R)0;
+        n[1] = k == 1 ? sg : (R)0;
+        n[2] = k == 2 ? sg : (R)0;
         return;
     }
     R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
     if (V.kind == PR_CYLINDER || V.kind == PR_CYL_SHELL) {
-        int a = V.axis, b = (a + 1) % 3, c = (a + 2) % 3;
-        if (f == 1) { n[a] = (R)-1; return; }
-        if (f == 2) { n[a] = (R)1; return; }
-        R r = M<R>::sqrt_(q[b] * q[b] + q[c] * q[c]);
-        R sg = f == 3 ? (R)-1 : (R)1;
-        n[b] = sg * M<R>::div_(q[b], r);
-        n[c] = sg * M<R>::div_(q[c], r);
+        const int a = V.axis, b = a == 0 ? 1 : (a == 1 ? 2 : 0), c = a == 0 ? 2 : (a == 1 ? 0 : 1);
+        R na = (R)0, nb = (R)0, nc = (R)0;
+        if (f == 1 || f == 2) {
+            na = f == 2 ? (R)1 : (R)-1;
+        } else {
+            const R qb = pick(q, b), qc = pick(q, c);
+            R r = M<R>::sqrt_(qb * qb + qc * qc);
+            R sg = f == 3 ? (R)-1 : (R)1;
+            nb = sg * M<R>::div_(qb, r);
+            nc = sg * M<R>::div_(qc, r);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) n[k] = k == a ? na : (k == b ? nb : nc);
         return;
     }
     R r = M<R>::sqrt_(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
     R sg = f == 3 ? (R)-1 : (R)1;
+#pragma unroll
     for (int k = 0; k < 3; ++k) n[k] = sg * M<R>::div_(q[k], r);
 }
 
@@ -569,8 +593,8 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     pieces<R>(V, s.p, s.u, P);
     R d_exit = rinf<R>();
     int face = -1;
-    for (int i = 0; i < P.n; ++i)
-        if (P.b[i] > (R)0 && P.b[i] < d_exit) { d_exit = P.b[i]; face = P.fb[i]; }
+    if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
+    if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
     R d_child = rinf<R>();
     int child = -1;
@@ -578,8 +602,8 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         int c = S.children[V.child_begin + ci];
         Pieces<R> Q;
         pieces<R>(S.vols[c], s.p, s.u, Q);
-        for (int i = 0; i < Q.n; ++i)
-            if (Q.a[i] > (R)0 && Q.a[i] < d_child) { d_child = Q.a[i]; child = c; }
+        if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
+        if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
     }
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;

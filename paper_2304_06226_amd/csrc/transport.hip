@@ -33,14 +33,13 @@ __device__ __forceinline__ void count_end(Counters& k, const PState<R>& s) {
     k.c[ST_STEPS] += (unsigned long long)s.steps;
     k.c[ST_DRAWS] += (unsigned long long)s.k;
     k.c[ST_SCAT] += (unsigned long long)s.nscat;
-    switch (s.term) {
-    case PR_END_ESCAPE: k.c[ST_ESC] += 1; break;
-    case PR_END_ABSORB: k.c[ST_ABS] += 1; break;
-    case PR_END_KILL: k.c[ST_KILL] += 1; break;
-    case PR_END_DETECT: k.c[ST_DET] += 1; break;
-    case PR_END_CAPPED: k.c[ST_CAP] += 1; break;
-    default: k.c[ST_OUT] += 1; break;
-    }
+    // one add per class with constant indices (a switch here becomes an indexed private array)
+    k.c[ST_ESC] += s.term == PR_END_ESCAPE ? 1ull : 0ull;
+    k.c[ST_ABS] += s.term == PR_END_ABSORB ? 1ull : 0ull;
+    k.c[ST_KILL] += s.term == PR_END_KILL ? 1ull : 0ull;
+    k.c[ST_DET] += s.term == PR_END_DETECT ? 1ull : 0ull;
+    k.c[ST_CAP] += s.term == PR_END_CAPPED ? 1ull : 0ull;
+    k.c[ST_OUT] += s.term == PR_END_OUTSIDE ? 1ull : 0ull;
 }
 
 __device__ __forceinline__ void flush_counters(const Counters& k, unsigned long long* g) {
@@ -84,13 +83,21 @@ __global__ __launch_bounds__(256) void k_plain(Params P) {
 // FP32 mixed, persistent
 // ------------------------------------------------------------------------
 
+// LDS of a mixed-policy block: [privatised tallies (doubles)] [bin-cache values
+// (2 doubles per slot)] [bin-cache keys (u32 per slot)] [scene: volumes,
+// materials, Bragg tables, daughter lists]
 struct LdsLayout {
-    int vols, mats, fams, children, bytes;   // byte offsets after the tally doubles
+    int cache_vals, cache_keys, vols, mats, fams, children, bytes;   // byte offsets
 };
 
-__host__ __device__ inline LdsLayout lds_layout(int nv, int nm, int nf, int nc, int tally_doubles) {
+__host__ __device__ inline LdsLayout lds_layout(int nv, int nm, int nf, int nc, int tally_doubles, int cache_slots) {
     LdsLayout L;
     int off = tally_doubles * 8;
+    L.cache_vals = off;
+    off += cache_slots * 16;
+    L.cache_keys = off;
+    off += cache_slots * 4;
+    off = (off + 15) & ~15;
     L.vols = off;
     off += nv * (int)sizeof(VolT<float>);
     off = (off + 15) & ~15;
@@ -106,6 +113,41 @@ __host__ __device__ inline LdsLayout lds_layout(int nv, int nm, int nf, int nc, 
     return L;
 }
 
+constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
+
+// Score w into bin b of tally T from a mixed-policy lane: the block's
+// privatised copy if there is one, else the block's LDS bin cache (a slot is
+// claimed by the first bin that hashes to it; two probes), else global atomics.
+__device__ __forceinline__ void score_mixed(const TallyDev& T, int64_t b, double w, double* lds, double* cvals,
+                                            uint32_t* ckeys) {
+    if (T.lds_offset >= 0) {
+        atomicAdd(lds + T.lds_offset + b, w);
+        atomicAdd(lds + T.lds_offset + T.total + b, w * w);
+        return;
+    }
+    if (T.cache_base >= 0 && b < (int64_t)kEmptyKey) {
+        const uint32_t key = (uint32_t)b;
+        const uint32_t h = (key * 2654435761u) >> (32 - T.cache_bits);
+        const uint32_t mask = (1u << T.cache_bits) - 1u;
+#pragma unroll
+        for (int probe = 0; probe < 2; ++probe) {
+            const uint32_t slot = (uint32_t)T.cache_base + ((h ^ (uint32_t)probe) & mask);
+            uint32_t k = __hip_atomic_load(ckeys + slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (k == kEmptyKey) {
+                k = atomicCAS(ckeys + slot, kEmptyKey, key);
+                if (k == kEmptyKey) k = key;
+            }
+            if (k == key) {
+                atomicAdd(cvals + 2 * slot, w);
+                atomicAdd(cvals + 2 * slot + 1, w * w);
+                return;
+            }
+        }
+    }
+    atomicAdd(T.sw + b, w);
+    atomicAdd(T.sw2 + b, w * w);
+}
+
 __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes) {
     const uint32_t* s = (const uint32_t*)src;
     uint32_t* d = (uint32_t*)dst;
@@ -115,13 +157,16 @@ __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes
 template <bool REC>
 __global__ __launch_bounds__(256) void k_mixed(Params P) {
     extern __shared__ double lds[];
-    const LdsLayout L = lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles);
+    const LdsLayout L = lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles, P.cache_slots);
     char* base = (char*)lds;
+    double* cvals = (double*)(base + L.cache_vals);
+    uint32_t* ckeys = (uint32_t*)(base + L.cache_keys);
     copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
     copy_words(base + L.mats, P.mats_f, P.n_mats * (int)sizeof(MatT<float>));
     copy_words(base + L.fams, P.fams_f, P.n_fams * (int)sizeof(FamT<float>));
     copy_words(base + L.children, P.children, P.n_children * 4);
-    for (int i = threadIdx.x; i < P.lds_tally_doubles; i += blockDim.x) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < P.lds_tally_doubles + 2 * P.cache_slots; i += blockDim.x) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < P.cache_slots; i += blockDim.x) ckeys[i] = kEmptyKey;
     __syncthreads();
     const SceneT<float> S{(const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
                           (const FamT<float>*)(base + L.fams), (const int32_t*)(base + L.children)};
@@ -130,28 +175,41 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
     PState<float> s;
     s.term = 1;   // idle
     bool exhausted = false;
+    // the wave's current chunk of history indices [cnext, cend), claimed with one
+    // atomic per chunk; values are wave-uniform
+    unsigned long long cnext = 0, cend = 0;
+    const unsigned long long chunk = (unsigned long long)P.chunk;
     const int lane = lane_id();
     for (;;) {
         const bool idle = s.term != 0;
         const unsigned long long idle_mask = __ballot(idle);
         const int n_idle = __popcll(idle_mask);
         if (!exhausted && (n_idle >= P.refill_threshold || n_idle == kWave)) {
-            const int leader = __ffsll((long long)idle_mask) - 1;
-            unsigned long long got = 0;
-            if (lane == leader) got = atomicAdd(P.counter, (unsigned long long)n_idle);
-            got = __shfl(got, leader, kWave);
-            if (got + (unsigned long long)n_idle >= P.n) exhausted = true;
-            if (idle) {
-                const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
-                                                          __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
-                const unsigned long long idx = got + (unsigned long long)rank;
-                if (idx < P.n) {
-                    source<float, REC>(s, P.src, S, P.seed, P.first + idx);
-                    if (s.term != 0) {   // born outside the world
-                        if (REC) write_record<float>(P.records + (s.h - P.first), s);
-                        count_end<float>(cnt, s);
+            if (cnext >= cend) {
+                const int leader = __ffsll((long long)idle_mask) - 1;
+                unsigned long long got = 0;
+                if (lane == leader) got = atomicAdd(P.counter, chunk);
+                got = __shfl(got, leader, kWave);
+                cnext = got;
+                cend = got + chunk < P.n ? got + chunk : P.n;
+                if (got >= P.n) exhausted = true;
+            }
+            if (!exhausted) {
+                const unsigned long long avail = cend - cnext;
+                const unsigned long long take = (unsigned long long)n_idle < avail ? (unsigned long long)n_idle : avail;
+                if (idle) {
+                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+                    if ((unsigned long long)rank < take) {
+                        source<float, REC>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank);
+                        if (s.term != 0) {   // born outside the world
+                            if (REC) write_record<float>(P.records + (s.h - P.first), s);
+                            count_end<float>(cnt, s);
+                        }
                     }
                 }
+                cnext += take;
+                if (cnext >= cend && cend >= P.n) exhausted = true;
             }
         }
         if (__ballot(s.term == 0) == 0ull) {
@@ -165,15 +223,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
                     for (int t = 0; t < P.n_tallies; ++t) {
                         const TallyDev& T = P.tallies[t];
                         int64_t b = tally_bin<float>(T, s);
-                        if (b >= 0) {
-                            if (T.lds_offset >= 0) {
-                                atomicAdd(lds + T.lds_offset + b, s.w);
-                                atomicAdd(lds + T.lds_offset + T.total + b, s.w * s.w);
-                            } else {
-                                atomicAdd(T.sw + b, s.w);
-                                atomicAdd(T.sw2 + b, s.w * s.w);
-                            }
-                        }
+                        if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
                     }
                 }
                 if (REC) write_record<float>(P.records + (s.h - P.first), s);
@@ -183,9 +233,20 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
     }
     flush_counters(cnt, P.stats);
     __syncthreads();
-    // merge the block's privatised tallies (non-zero bins only)
+    // merge the block's privatised tallies and cached bins (non-zero bins only)
     for (int t = 0; t < P.n_tallies; ++t) {
         const TallyDev& T = P.tallies[t];
+        if (T.cache_base >= 0) {
+            const int ns = 1 << T.cache_bits;
+            for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+                const int slot = T.cache_base + i;
+                const uint32_t key = ckeys[slot];
+                if (key != kEmptyKey) {
+                    atomicAdd(T.sw + key, cvals[2 * slot]);
+                    atomicAdd(T.sw2 + key, cvals[2 * slot + 1]);
+                }
+            }
+        }
         if (T.lds_offset < 0) continue;
         for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
             double a = lds[T.lds_offset + i];
@@ -214,7 +275,7 @@ __global__ void k_zero_f64(double* p, uint64_t n) {
 // ------------------------------------------------------------------------
 
 int mixed_lds_bytes(const Params& P) {
-    return lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles).bytes;
+    return lds_layout(P.n_vols, P.n_mats, P.n_fams, P.n_children, P.lds_tally_doubles, P.cache_slots).bytes;
 }
 
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {

@@ -153,3 +153,32 @@ def test_config2_fp32_tally_agreement(ctx):
 
 def test_config3_fp32_tally_agreement(ctx):
     _fp32_case(ctx, W.config3(nbins_xy=50, nbins_div=20), 300_000)
+
+
+def test_fp32_results_independent_of_launch_tuning(ctx):
+    """Each history's outcome depends only on (seed, history id), not on which
+    lane or block runs it: tallies agree across launch tunings up to the
+    order of floating-point summation."""
+    import torch
+    prob = W.config1(n=300_000)
+    base = ctx.get_tuning()
+    results = []
+    tunings = [dict(), dict(refill_threshold=1, chunk=64, block=64), dict(bin_cache_slots=0, lds_tally_bytes=0),
+               dict(refill_threshold=64, chunk=4096, blocks_per_cu=1, bin_cache_slots=4096)]
+    try:
+        for t in tunings:
+            ctx.set_tuning(**{**base, **t})
+            sim = B.Simulation(ctx, prob)
+            ctx.reset_stats()
+            sim.run(first=0, n=prob.n_histories, precision="fp32")
+            torch.cuda.synchronize()
+            results.append((sim.results(), ctx.read_stats()))
+    finally:
+        ctx.set_tuning(**base)
+    ref, ref_st = results[0]
+    for res, st in results[1:]:
+        assert st == ref_st
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(res, ref):
+            assert nh == rn
+            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
