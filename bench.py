@@ -40,6 +40,22 @@ OPS_PER_HISTORY = 60
 # VALU issue peak: 256 CUs x 64 lanes x 2.4 GHz, one lane-instruction per lane per clock
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
+# HBM bytes per launch of the dominant kernels from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE passes (scaled by a 256 MiB copy: fetch x2.000, write x1.000), valid
+# only for the kernel sources they were taken on (hash of transport.hip + device.h);
+# profiles/history_kernels_biased_sample_1e7.txt holds the summary.
+MEASURED_TRAFFIC = {"source_hash": "90cbc28edb72854f",
+                    "k_mixed": 0.434e6 + 192.272e6, "k_plain": 0.521e6 + 669.999e6}
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paper_2304_06226_amd/csrc/transport.hip", "paper_2304_06226_amd/csrc/device.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def algorithmic_ops(stats: dict) -> float:
     return (OPS_PER_DRAW * stats["draws"] + OPS_PER_STEP * stats["steps"] + OPS_PER_SCATTER * stats["scatters"]
@@ -126,10 +142,11 @@ def main():
     out["dtype"] = "f32" if fp32 else "f64"
     per_launch_ops = algorithmic_ops(head_st) / max(1, head_st["histories"]) * n
     achieved = per_launch_ops / (head_ms * 1e-3) / 1e12
+    kname = "k_mixed" if fp32 else "k_plain"
+    traffic = MEASURED_TRAFFIC[kname] if kernel_source_hash() == MEASURED_TRAFFIC["source_hash"] else None
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-                       "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                       "kernel": "k_mixed" if fp32 else "k_plain",
-                       "ops_per_history": per_launch_ops / n}
+                       "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                       "kernel": kname, "ops_per_history": per_launch_ops / n}
     if fp32 and fp64:
         out["fp64_plain"] = {"value": n / fp64[0] * 1e3, "ms_per_step": fp64[0]}
         out["speedup_vs_fp64_plain"] = fp64[0] / fp32[0]

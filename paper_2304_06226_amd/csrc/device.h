@@ -144,7 +144,9 @@ struct M<double> {
 
 template <>
 struct M<float> {
-    static __device__ __forceinline__ float log_(float x) { return __logf(x); }
+    // natural log from the hardware log2: arguments here are uniforms in
+    // [2^-24, 1] or positive energies, never denormal
+    static __device__ __forceinline__ float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
     static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
     static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
@@ -173,13 +175,15 @@ struct U4 {
 __device__ __forceinline__ U4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        uint32_t lo0 = c0 * 0xD2511F53u, hi0 = __umulhi(c0, 0xD2511F53u);
-        uint32_t lo1 = c2 * 0xCD9E8D57u, hi1 = __umulhi(c2, 0xCD9E8D57u);
-        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        // one 32x32->64 multiply-add per product gives both halves
+        // (v_mad_u64_u32 instead of a mul_lo/mul_hi pair)
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -197,16 +201,19 @@ struct PState {
     double w;
     uint64_t h;
     uint64_t hash;
-    uint32_t k;          // next draw index
-    uint32_t c2, c3;     // words 2,3 of the current block (odd draws)
+    uint32_t k;          // draws consumed so far (the draw index of the next draw)
+    uint32_t c2, c3;     // FP64 draws: words 2,3 of the current block (odd draws)
+    R ub0, ub1, ub2, ub3, ub4;   // FP32 draws: buffered uniforms for draws k .. k+nbuf-1
+    int32_t nbuf;
     int32_t region, nscat, steps, term;
     // cross sections cached for material xs_mat (lambda is constant per history)
     int32_t xs_mat, nact;
     R sa, si, sc, sig, sig_g, ga, gs, cl;
 };
 
-template <class R>
-__device__ __forceinline__ R draw(PState<R>& s, uint64_t seed) {
+// FP64 draws: the block of draw k is computed when k is even, its second word
+// pair kept for the odd draw that follows.
+__device__ __forceinline__ double draw(PState<double>& s, uint64_t seed) {
     uint32_t a, b;
     if ((s.k & 1u) == 0u) {
         uint32_t blk = s.k >> 1;
@@ -220,7 +227,60 @@ __device__ __forceinline__ R draw(PState<R>& s, uint64_t seed) {
         b = s.c3;
     }
     s.k++;
-    return M<R>::uni(a, b);
+    return M<double>::uni(a, b);
+}
+
+// FP32 draws are buffered: one generation site per step fills the buffer with
+// the uniforms of the next draw indices (word 0 of a block for its even draw,
+// word 2 for its odd draw), so a wave runs the Philox rounds once per step
+// instead of once per draw site.  Values depend only on the draw index.
+__device__ __forceinline__ void push_u(PState<float>& s, float v) {
+    s.ub0 = s.nbuf == 0 ? v : s.ub0;
+    s.ub1 = s.nbuf == 1 ? v : s.ub1;
+    s.ub2 = s.nbuf == 2 ? v : s.ub2;
+    s.ub3 = s.nbuf == 3 ? v : s.ub3;
+    s.ub4 = s.nbuf == 4 ? v : s.ub4;
+    s.nbuf++;
+}
+
+__device__ __forceinline__ void gen_block(PState<float>& s, uint64_t seed) {
+    const uint32_t idx = s.k + (uint32_t)s.nbuf;
+    U4 o = philox10(idx >> 1, 0u, (uint32_t)s.h, (uint32_t)(s.h >> 32), (uint32_t)seed, (uint32_t)(seed >> 32));
+    if ((idx & 1u) == 0u) push_u(s, M<float>::uni(o.x, 0u));
+    push_u(s, M<float>::uni(o.z, 0u));
+}
+
+__device__ __forceinline__ float draw(PState<float>& s, uint64_t seed) {
+    if (s.nbuf == 0) gen_block(s, seed);
+    const float v = s.ub0;
+    s.ub0 = s.ub1;
+    s.ub1 = s.ub2;
+    s.ub2 = s.ub3;
+    s.ub3 = s.ub4;
+    s.nbuf--;
+    s.k++;
+    return v;
+}
+
+// next draw after prefetch() guaranteed it is buffered (FP32: no generation
+// code at the call site); FP64 draws are generated at use
+__device__ __forceinline__ double draw_ready(PState<double>& s, uint64_t seed) { return draw(s, seed); }
+__device__ __forceinline__ float draw_ready(PState<float>& s, uint64_t) {
+    const float v = s.ub0;
+    s.ub0 = s.ub1;
+    s.ub1 = s.ub2;
+    s.ub2 = s.ub3;
+    s.ub3 = s.ub4;
+    s.nbuf--;
+    s.k++;
+    return v;
+}
+
+// make at least `need` draws available without further generation (FP32);
+// FP64 draws are generated at use
+__device__ __forceinline__ void prefetch(PState<double>&, uint64_t, int) {}
+__device__ __forceinline__ void prefetch(PState<float>& s, uint64_t seed, int need) {
+    while (s.nbuf < need) gen_block(s, seed);
 }
 
 template <bool REC>
@@ -499,6 +559,7 @@ template <class R, bool REC>
 __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h) {
     s.h = h;
     s.k = 0;
+    s.nbuf = 0;
     s.w = 1.0;
     s.nscat = 0;
     s.steps = 0;
@@ -508,14 +569,14 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     R p[3] = {(R)src.o[0], (R)src.o[1], (R)src.o[2]};
     R u[3] = {(R)src.u[0], (R)src.u[1], (R)src.u[2]};
     if (src.kind != PR_PENCIL) {
-        R a = draw<R>(s, seed);
-        R b = draw<R>(s, seed);
+        R a = draw(s, seed);
+        R b = draw(s, seed);
         p[0] += (a - (R)0.5) * (R)src.size[0];
         p[1] += (b - (R)0.5) * (R)src.size[1];
     }
     if (src.kind == PR_RECT_DIVERGENT) {
-        R ax = ((R)2 * draw<R>(s, seed) - (R)1) * (R)src.div_rad[0];
-        R ay = ((R)2 * draw<R>(s, seed) - (R)1) * (R)src.div_rad[1];
+        R ax = ((R)2 * draw(s, seed) - (R)1) * (R)src.div_rad[0];
+        R ay = ((R)2 * draw(s, seed) - (R)1) * (R)src.div_rad[1];
         R tx = M<R>::tan_(ax), ty = M<R>::tan_(ay);
         R nrm = M<R>::sqrt_(tx * tx + ty * ty + (R)1);
         u[0] = M<R>::div_(tx, nrm);
@@ -524,13 +585,13 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     }
     R lam = (R)src.lam0;
     if (src.spectrum == PR_UNIFORM) {
-        lam = (R)src.lam_lo + draw<R>(s, seed) * (R)(src.lam_hi - src.lam_lo);
+        lam = (R)src.lam_lo + draw(s, seed) * (R)(src.lam_hi - src.lam_lo);
     } else if (src.spectrum == PR_MAXWELL) {
         // Gamma(3/2) energy in units of kT: exponential + half a squared normal
         for (int t = 0; t < 64; ++t) {
-            R x1 = (R)1 - draw<R>(s, seed);
-            R x2 = (R)1 - draw<R>(s, seed);
-            R u3 = draw<R>(s, seed);
+            R x1 = (R)1 - draw(s, seed);
+            R x2 = (R)1 - draw(s, seed);
+            R u3 = draw(s, seed);
             R c = M<R>::cos_((R)(0.5 * 3.14159265358979323846) * u3);
             R e = (R)src.kT * (-M<R>::log_(x1) - M<R>::log_(x2) * c * c);
             lam = M<R>::sqrt_(M<R>::div_((R)src.e_const, e));
@@ -618,7 +679,8 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     bool collide = false;
     R x = d_b;
     if (sig_g > (R)0) {
-        R xi = (R)1 - draw<R>(s, seed);
+        prefetch(s, seed, 4);   // flight, process and two scattering draws
+        R xi = (R)1 - draw_ready(s, seed);
         R l = M<R>::div_(-M<R>::log_(xi), sig_g);
         if (l < d_b) { collide = true; x = l; }
     }
@@ -628,7 +690,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     if (sig_g > (R)0) s.w *= (double)M<R>::exp_((sig_g - sig) * x);
 
     if (collide) {
-        R r = draw<R>(s, seed) * sig_g;
+        R r = draw_ready(s, seed) * sig_g;
         R wa = s.ga * s.sa, wi = s.gs * s.si, wc = s.gs * s.sc;
         if (r < wa || wi + wc == (R)0) {
             s.w *= 1.0 / (double)s.ga;
@@ -638,8 +700,8 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         }
         s.w *= 1.0 / (double)s.gs;
         bool inc = r < wa + wi || wc == (R)0 || s.nact == 0;
-        R u1 = draw<R>(s, seed);
-        R u2 = draw<R>(s, seed);
+        R u1 = draw_ready(s, seed);
+        R u2 = draw_ready(s, seed);
         R c2t;
         int fam = 0;
         if (inc) {

@@ -23,29 +23,31 @@ __device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
     return v;
 }
 
+// per-lane end-of-history counters; 32 bits per lane (a lane runs far fewer than
+// 2^32 / 10^4 histories per launch), summed over the wave in 64 bits at the end
 struct Counters {
-    unsigned long long c[ST_N];
+    uint32_t c[ST_N];
 };
 
 template <class R>
 __device__ __forceinline__ void count_end(Counters& k, const PState<R>& s) {
-    k.c[ST_HIST] += 1;
-    k.c[ST_STEPS] += (unsigned long long)s.steps;
-    k.c[ST_DRAWS] += (unsigned long long)s.k;
-    k.c[ST_SCAT] += (unsigned long long)s.nscat;
+    k.c[ST_HIST] += 1u;
+    k.c[ST_STEPS] += (uint32_t)s.steps;
+    k.c[ST_DRAWS] += s.k;
+    k.c[ST_SCAT] += (uint32_t)s.nscat;
     // one add per class with constant indices (a switch here becomes an indexed private array)
-    k.c[ST_ESC] += s.term == PR_END_ESCAPE ? 1ull : 0ull;
-    k.c[ST_ABS] += s.term == PR_END_ABSORB ? 1ull : 0ull;
-    k.c[ST_KILL] += s.term == PR_END_KILL ? 1ull : 0ull;
-    k.c[ST_DET] += s.term == PR_END_DETECT ? 1ull : 0ull;
-    k.c[ST_CAP] += s.term == PR_END_CAPPED ? 1ull : 0ull;
-    k.c[ST_OUT] += s.term == PR_END_OUTSIDE ? 1ull : 0ull;
+    k.c[ST_ESC] += s.term == PR_END_ESCAPE ? 1u : 0u;
+    k.c[ST_ABS] += s.term == PR_END_ABSORB ? 1u : 0u;
+    k.c[ST_KILL] += s.term == PR_END_KILL ? 1u : 0u;
+    k.c[ST_DET] += s.term == PR_END_DETECT ? 1u : 0u;
+    k.c[ST_CAP] += s.term == PR_END_CAPPED ? 1u : 0u;
+    k.c[ST_OUT] += s.term == PR_END_OUTSIDE ? 1u : 0u;
 }
 
 __device__ __forceinline__ void flush_counters(const Counters& k, unsigned long long* g) {
 #pragma unroll
     for (int i = 0; i < ST_N; ++i) {
-        unsigned long long t = wave_sum(k.c[i]);
+        unsigned long long t = wave_sum((unsigned long long)k.c[i]);
         if (lane_id() == 0 && t) atomicAdd(g + i, t);
     }
 }
@@ -173,7 +175,8 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
 
     Counters cnt = {};
     PState<float> s;
-    s.term = 1;   // idle
+    s.term = 1;            // idle, no history
+    bool pending = false;  // finished history not yet scored
     bool exhausted = false;
     // the wave's current chunk of history indices [cnext, cend), claimed with one
     // atomic per chunk; values are wave-uniform
@@ -184,8 +187,21 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
         const bool idle = s.term != 0;
         const unsigned long long idle_mask = __ballot(idle);
         const int n_idle = __popcll(idle_mask);
-        if (!exhausted && (n_idle >= P.refill_threshold || n_idle == kWave)) {
-            if (cnext >= cend) {
+        if (n_idle >= P.refill_threshold || n_idle == kWave) {
+            // score the histories that ended since the last refill, all together
+            if (pending) {
+                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+                    for (int t = 0; t < P.n_tallies; ++t) {
+                        const TallyDev& T = P.tallies[t];
+                        int64_t b = tally_bin<float>(T, s);
+                        if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
+                    }
+                }
+                if (REC) write_record<float>(P.records + (s.h - P.first), s);
+                count_end<float>(cnt, s);
+                pending = false;
+            }
+            if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
                 unsigned long long got = 0;
                 if (lane == leader) got = atomicAdd(P.counter, chunk);
@@ -202,10 +218,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
                         source<float, REC>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank);
-                        if (s.term != 0) {   // born outside the world
-                            if (REC) write_record<float>(P.records + (s.h - P.first), s);
-                            count_end<float>(cnt, s);
-                        }
+                        pending = s.term != 0;   // born outside the world: counted at the next refill
                     }
                 }
                 cnext += take;
@@ -213,22 +226,12 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
             }
         }
         if (__ballot(s.term == 0) == 0ull) {
-            if (exhausted) break;
+            if (exhausted && __ballot(pending) == 0ull) break;
             continue;
         }
         if (s.term == 0) {
             step<float, REC>(s, S, P.seed);
-            if (s.term != 0) {
-                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
-                    for (int t = 0; t < P.n_tallies; ++t) {
-                        const TallyDev& T = P.tallies[t];
-                        int64_t b = tally_bin<float>(T, s);
-                        if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
-                    }
-                }
-                if (REC) write_record<float>(P.records + (s.h - P.first), s);
-                count_end<float>(cnt, s);
-            }
+            pending = s.term != 0;
         }
     }
     flush_counters(cnt, P.stats);

@@ -1,0 +1,127 @@
+"""The C-ABI library loads on a machine without a GPU, exports every function
+declared in include/*.h, and validates descriptors (device-less context:
+hip_device = -1) with the documented error codes."""
+import ctypes as C
+import dataclasses
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2304_06226_amd import binding as B
+from paper_2304_06226_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:int|void|const char\*)\s+\**(pr_\w+)\s*\(", text, flags=re.M):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = B.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.EXPORTS)
+
+
+def test_struct_sizes_match_header():
+    # pr_history_record is 96 bytes; descriptor layouts as laid out by the binding
+    assert C.sizeof(B.pr_volume_desc) == 6 * 4 + 6 * 8 + C.sizeof(B.pr_mirror_desc)
+    assert C.sizeof(B.pr_mirror_desc) == 8 + 5 * 8
+    assert B.RECORD_DTYPE.itemsize == 96
+    assert C.sizeof(B.pr_tally_desc) == 6 * 4 + 4 * 24 + 24
+
+
+@pytest.fixture
+def ctx():
+    c = B.Context(device=-1)
+    yield c
+    c.close()
+
+
+def code_of(fn):
+    with pytest.raises(B.PromptError) as e:
+        fn()
+    return e.value.code
+
+
+def test_material_validation(ctx):
+    m = W.sample_material()
+    assert ctx.create_material(m) == 0
+    assert code_of(lambda: ctx.create_material(dataclasses.replace(m, number_density=-1.0))) == -1
+    assert code_of(lambda: ctx.create_material(dataclasses.replace(m, scatter_bias=-2.0))) == -1
+    assert code_of(lambda: ctx.create_material(dataclasses.replace(m, d=m.d[::-1].copy()))) == -1
+    assert code_of(lambda: ctx.create_material(dataclasses.replace(m, cell_volume=0.0))) == -1
+    # a bias factor of 0 is allowed: it removes the process
+    assert ctx.create_material(m.biased(abs_bias=0.0)) == 1
+
+
+def test_geometry_validation(ctx):
+    p = W.config2()
+    ids = [ctx.create_material(m) for m in p.materials]
+    assert ctx.create_geometry(p.volumes, ids) == 0
+    # sample touching the vessel's bore
+    bad = list(p.volumes)
+    bad[2] = dataclasses.replace(bad[2], size=(10.0, 20.0))
+    assert code_of(lambda: ctx.create_geometry(bad, ids)) == -3
+    # daughter leaving the world
+    bad = list(p.volumes)
+    bad[2] = dataclasses.replace(bad[2], center=(0.0, 0.0, 995.0))
+    assert code_of(lambda: ctx.create_geometry(bad, ids)) == -3
+    # shell with r_in >= r_out, negative size, parent after child, unknown material
+    assert code_of(lambda: ctx.create_geometry([p.volumes[0], dataclasses.replace(p.volumes[1], size=(11.0, 10.0, 40.0))], ids)) == -1
+    assert code_of(lambda: ctx.create_geometry([p.volumes[0], dataclasses.replace(p.volumes[2], size=(-1.0, 20.0))], ids)) == -1
+    assert code_of(lambda: ctx.create_geometry([p.volumes[0], dataclasses.replace(p.volumes[2], parent=1)], ids)) == -1
+    assert code_of(lambda: ctx.create_geometry([p.volumes[0], dataclasses.replace(p.volumes[2], material=7)], [0, 1, 2, 3, 4, 5, 6, 99])) == -2
+    # world must have parent -1
+    assert code_of(lambda: ctx.create_geometry([dataclasses.replace(p.volumes[0], parent=0)], ids)) == -1
+    # overlapping boxes
+    world = W.Volume("box", (0, 0, 0), (100, 100, 100))
+    a = W.Volume("box", (0, 0, 0), (10, 10, 10), parent=0)
+    b = W.Volume("box", (9, 0, 0), (10, 10, 10), parent=0)
+    c = W.Volume("box", (20, 0, 0), (10, 10, 10), parent=0)
+    assert code_of(lambda: ctx.create_geometry([world, a, b], [])) == -3
+    assert ctx.create_geometry([world, a, c], []) >= 0
+
+
+def test_source_and_tally_validation(ctx):
+    s = W.config3().source
+    assert ctx.create_source(s) == 0
+    assert code_of(lambda: ctx.create_source(dataclasses.replace(s, direction=(0.0, 1.0, 1.0)))) == -1
+    assert code_of(lambda: ctx.create_source(dataclasses.replace(s, lam_lo=5.0, lam_hi=1.0))) == -1
+    assert code_of(lambda: ctx.create_source(dataclasses.replace(s, direction=(0.0, 0.0, 0.0)))) == -1
+    t = W.Tally(axes=[W.Axis("theta2", 0, 180, 1800)])
+    assert ctx.create_tally(t) == 0
+    assert ctx.tally_nbins(0) == 1800
+    assert code_of(lambda: ctx.create_tally(W.Tally(axes=[W.Axis("theta2", 10, 10, 5)]))) == -1
+    assert code_of(lambda: ctx.create_tally(W.Tally(axes=[W.Axis("theta2", 0, 1, 0)]))) == -1
+    assert code_of(lambda: ctx.tally_nbins(5)) == -2
+
+
+def test_run_needs_a_device(ctx):
+    p = W.config0()
+    sim = B.Simulation(ctx, p)
+    with pytest.raises(B.PromptError) as e:
+        ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, "fp64", None, 0)
+    assert e.value.code == -5
+
+
+def test_tuning_validation(ctx):
+    t = ctx.get_tuning()
+    assert t["block"] == 256 and t["chunk"] >= 1
+    assert code_of(lambda: ctx.set_tuning(block=512)) == -1
+    assert code_of(lambda: ctx.set_tuning(bin_cache_slots=1000)) == -1
+    assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
+    ctx.set_tuning(refill_threshold=8)
+    assert ctx.get_tuning()["refill_threshold"] == 8
