@@ -217,6 +217,30 @@ int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
 int pr_run_histories(pr_ctx* ctx, int32_t geom, int32_t src, const int32_t* tallies, int32_t n_tallies,
                      uint64_t first_history, uint64_t n, int32_t precision, void* records_dev, void* stream);
 
+/* ---- batched runs ---- */
+/* One simulation of a batch: geometry, source, up to PR_MAX_TALLIES tallies and
+ * its history range [first_history, first_history + n).  Give the simulations
+ * of a batch disjoint history ranges (e.g. consecutive ones) so that their
+ * random-number streams are disjoint. */
+typedef struct {
+    int32_t geom;
+    int32_t src;
+    int32_t n_tallies;
+    int32_t tallies[PR_MAX_TALLIES];
+    int32_t pad;
+    uint64_t first_history;
+    uint64_t n;
+} pr_sim;
+
+/* Run nsims independent simulations of uneven size and geometry in one
+ * persistent launch of the PR_FP32_MIXED policy (the only policy accepted).
+ * Waves claim chunks of one simulation at a time from a shared chunk space
+ * spanning all simulations; each lane carries its history's simulation.
+ * Asynchronous on `stream`; each simulation's histories are exactly those of
+ * pr_run_histories over the same range.  The descriptors are copied: sims may
+ * be reused as soon as the call returns. */
+int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream);
+
 /* ---- launch tuning of PR_FP32_MIXED ---- */
 /* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
  * blocks per compute unit of the persistent grid (0 = occupancy limit);

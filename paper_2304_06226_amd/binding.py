@@ -42,7 +42,7 @@ RECORD_BYTES = 96
 EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_material", "pr_create_geometry",
            "pr_create_source", "pr_create_tally", "pr_tally_nbins", "pr_run_histories", "pr_read_tally",
            "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats", "pr_set_tuning",
-           "pr_get_tuning"]
+           "pr_get_tuning", "pr_run_batch"]
 
 
 class pr_material_desc(C.Structure):
@@ -84,6 +84,11 @@ class pr_tuning(C.Structure):
                 ("lds_tally_bytes", C.c_int32), ("bin_cache_slots", C.c_int32), ("chunk", C.c_int32)]
 
 
+class pr_sim(C.Structure):
+    _fields_ = [("geom", C.c_int32), ("src", C.c_int32), ("n_tallies", C.c_int32), ("tallies", C.c_int32 * 8),
+                ("pad", C.c_int32), ("first_history", C.c_uint64), ("n", C.c_uint64)]
+
+
 class pr_run_stats(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in ("histories", "escaped", "absorbed", "killed", "detected", "capped",
                                           "outside", "steps", "draws", "scatters")]
@@ -120,6 +125,7 @@ def load():
     L.pr_read_stats.argtypes = [vp, C.POINTER(pr_run_stats), vp]
     L.pr_reset_stats.argtypes = [vp, vp]
     L.pr_set_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
+    L.pr_run_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, vp]
     L.pr_get_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -291,6 +297,18 @@ class Context:
         self._check(self.lib.pr_read_stats(self.h, C.byref(s), st))
         return {name: getattr(s, name) for name, _ in pr_run_stats._fields_}
 
+    def run_batch(self, sims, precision="fp32", stream=None):
+        """sims: list of (geom, src, tallies, first, n)."""
+        arr = (pr_sim * len(sims))()
+        for i, (g, sr, ts, first, n) in enumerate(sims):
+            arr[i].geom, arr[i].src, arr[i].n_tallies = g, sr, len(ts)
+            for j, t in enumerate(ts):
+                arr[i].tallies[j] = t
+            arr[i].first_history, arr[i].n = first, n
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        st = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(self.lib.pr_run_batch(self.h, arr, len(sims), prec, st))
+
     def get_tuning(self) -> dict:
         t = pr_tuning()
         self._check(self.lib.pr_get_tuning(self.h, C.byref(t)))
@@ -344,3 +362,30 @@ def records_to_numpy(records, n: int) -> np.ndarray:
     """Copy a device record buffer (torch uint8 tensor) to a structured numpy array."""
     host = records[: n * RECORD_BYTES].cpu().numpy()
     return host.view(RECORD_DTYPE)
+
+
+class BatchRun:
+    """A batch of workloads instantiated in one context; simulation i covers the
+    history ids [offset_i, offset_i + n_i) with consecutive offsets, so the
+    random-number streams of different simulations are disjoint."""
+
+    def __init__(self, ctx: Context, batch: "W.Batch", base: int = 0):
+        self.ctx = ctx
+        self.batch = batch
+        self.sims = [Simulation(ctx, p) for p in batch.problems]
+        self.offsets = []
+        off = base
+        for p in batch.problems:
+            self.offsets.append(off)
+            off += p.n_histories
+        self.span = off - base
+
+    def descriptors(self, shift: int = 0):
+        return [(s.geom, s.src, s.tallies, o + shift, s.prob.n_histories) for s, o in zip(self.sims, self.offsets)]
+
+    def run(self, shift: int = 0, stream=None):
+        self.ctx.run_batch(self.descriptors(shift), "fp32", stream)
+
+    def reset(self):
+        for s in self.sims:
+            s.reset()

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -28,6 +29,16 @@ struct Material {
 
 struct Geometry {
     std::vector<pr_volume_desc> vols;
+    // host copies of the device scene (batched runs concatenate them)
+    std::vector<VolT<double>> vd;
+    std::vector<VolT<float>> vf;
+    std::vector<MatT<double>> md;
+    std::vector<MatT<float>> mf;
+    std::vector<FamT<double>> fd;
+    std::vector<FamT<float>> ff;
+    std::vector<int32_t> children, cell_start, cell_items;
+    std::vector<GridT<double>> gd;
+    std::vector<GridT<float>> gf;
     int nv = 0, nm = 0, nf = 0, nc = 0;
     void* vols_d = nullptr;
     void* mats_d = nullptr;
@@ -35,7 +46,12 @@ struct Geometry {
     void* vols_f = nullptr;
     void* mats_f = nullptr;
     void* fams_f = nullptr;
-    void* children = nullptr;
+    void* children_d = nullptr;
+    void* grids_d = nullptr;
+    void* grids_f = nullptr;
+    void* cell_start_d = nullptr;
+    void* cell_items_d = nullptr;
+    int scene_f_bytes = 0;   // FP32 scene size (LDS staging decision)
 };
 
 struct Tally {
@@ -43,6 +59,30 @@ struct Tally {
     uint64_t nbins = 0;
     double* dev = nullptr;   // [sum_w | sum_w2]
     uint64_t n_hist = 0;
+};
+
+// Concatenated FP32 scene of the geometries of a batch (volume, material,
+// family, daughter, grid and cell indices rebased), cached per geometry list.
+struct BatchScene {
+    std::vector<int32_t> vol_offset;   // per geometry of the list
+    void* vols = nullptr;
+    void* mats = nullptr;
+    void* fams = nullptr;
+    void* children = nullptr;
+    void* grids = nullptr;
+    void* cell_start = nullptr;
+    void* cell_items = nullptr;
+};
+
+// Per-call batch descriptors (simulations, tallies, key bases): a small ring of
+// device buffers filled from pinned host staging, each reused only after the
+// event recorded behind its last launch has completed.
+struct DescSlot {
+    void* dev = nullptr;
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
 };
 
 }  // namespace
@@ -65,6 +105,10 @@ struct pr_ctx {
     int lds_tally_budget = 32768;       // bytes of LDS per block for privatised tallies
     int bin_cache_slots = 1024;         // LDS bin-cache slots per non-privatised tally (power of two, 0 = off)
     int chunk = 256;                    // history indices a wave claims per atomic
+    int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
+    std::map<std::vector<int32_t>, BatchScene> batch_scenes;
+    DescSlot slots[4];
+    int next_slot = 0;
 };
 
 namespace {
@@ -236,11 +280,79 @@ int upload(pr_ctx* c, void** dst, const std::vector<T>& v) {
 }
 
 void free_geometry(Geometry& g) {
-    void* ps[] = {g.vols_d, g.mats_d, g.fams_d, g.vols_f, g.mats_f, g.fams_f, g.children};
-    for (void* p : ps)
-        if (p) (void)hipFree(p);
-    g.vols_d = g.mats_d = g.fams_d = g.vols_f = g.mats_f = g.fams_f = g.children = nullptr;
+    void** ps[] = {&g.vols_d, &g.mats_d, &g.fams_d, &g.vols_f, &g.mats_f, &g.fams_f, &g.children_d,
+                   &g.grids_d, &g.grids_f, &g.cell_start_d, &g.cell_items_d};
+    for (void** p : ps) {
+        if (*p) (void)hipFree(*p);
+        *p = nullptr;
+    }
 }
+
+// Uniform grid over the daughters of volume `v` (bounding boxes padded so that
+// cell assignment is conservative against rounding of the cell index).
+void build_grid(const pr_volume_desc* vols, const std::vector<int32_t>& kids, Geometry& g, int v) {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    std::vector<Box3> bb;
+    for (int c : kids) {
+        Box3 b = aabb(vols[c]);
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = std::min(lo[k], b.lo[k]);
+            hi[k] = std::max(hi[k], b.hi[k]);
+        }
+        bb.push_back(b);
+    }
+    double ext[3], vol = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        ext[k] = std::max(hi[k] - lo[k], 1e-6);
+        vol *= ext[k];
+    }
+    const double target = 4.0 * (double)kids.size();
+    const double h = std::cbrt(vol / target);
+    GridT<double> G{};
+    for (int k = 0; k < 3; ++k) {
+        int n = (int)std::ceil(ext[k] / h);
+        n = std::max(1, std::min(n, 128));
+        G.n[k] = n;
+        G.cell[k] = ext[k] / n;
+        G.inv_cell[k] = 1.0 / G.cell[k];
+        G.lo[k] = lo[k];
+        G.hi[k] = lo[k] + n * G.cell[k];
+    }
+    const int ncell = G.n[0] * G.n[1] * G.n[2];
+    std::vector<std::vector<int32_t>> cells(ncell);
+    for (size_t i = 0; i < kids.size(); ++i) {
+        int r0[3], r1[3];
+        for (int k = 0; k < 3; ++k) {
+            const double pad = 1e-4 * G.cell[k];
+            r0[k] = std::max(0, std::min(G.n[k] - 1, (int)std::floor((bb[i].lo[k] - pad - G.lo[k]) * G.inv_cell[k])));
+            r1[k] = std::max(0, std::min(G.n[k] - 1, (int)std::floor((bb[i].hi[k] + pad - G.lo[k]) * G.inv_cell[k])));
+        }
+        for (int a = r0[0]; a <= r1[0]; ++a)
+            for (int b = r0[1]; b <= r1[1]; ++b)
+                for (int c = r0[2]; c <= r1[2]; ++c) cells[(a * G.n[1] + b) * G.n[2] + c].push_back(kids[i]);
+    }
+    if (g.cell_start.empty()) g.cell_start.push_back(0);
+    G.cells_off = (int32_t)g.cell_start.size() - 1;
+    for (auto& cl : cells) {
+        g.cell_items.insert(g.cell_items.end(), cl.begin(), cl.end());
+        g.cell_start.push_back((int32_t)g.cell_items.size());
+    }
+    g.gd.push_back(G);
+    GridT<float> F{};
+    for (int k = 0; k < 3; ++k) {
+        F.lo[k] = (float)G.lo[k];
+        F.hi[k] = (float)G.hi[k];
+        F.cell[k] = (float)G.cell[k];
+        F.inv_cell[k] = (float)G.inv_cell[k];
+        F.n[k] = G.n[k];
+    }
+    F.cells_off = G.cells_off;
+    g.gf.push_back(F);
+    g.vd[v].grid = (int32_t)g.gd.size() - 1;
+    g.vf[v].grid = g.vd[v].grid;
+}
+
+constexpr int kGridMinDaughters = 8;
 
 int set_device(pr_ctx* c) {
     if (c->device < 0) return fail(c, PR_EDEVICE, "context has no device (created with hip_device = -1)");
@@ -299,6 +411,17 @@ extern "C" void pr_destroy(pr_ctx* c) {
             if (t.dev) (void)hipFree(t.dev);
         if (c->stats) (void)hipFree(c->stats);
         if (c->counter) (void)hipFree(c->counter);
+        for (auto& kv : c->batch_scenes) {
+            BatchScene& b = kv.second;
+            void* ps[] = {b.vols, b.mats, b.fams, b.children, b.grids, b.cell_start, b.cell_items};
+            for (void* p : ps)
+                if (p) (void)hipFree(p);
+        }
+        for (auto& sl : c->slots) {
+            if (sl.dev) (void)hipFree(sl.dev);
+            if (sl.host) (void)hipHostFree(sl.host);
+            if (sl.done) (void)hipEventDestroy(sl.done);
+        }
     }
     delete c;
 }
@@ -470,6 +593,7 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         o.child_begin = cbeg[i];
         o.child_count = ccnt[i];
         o.mirror_model = v.mirror.model;
+        o.grid = -1;
         o.R0 = v.mirror.R0;
         o.Qc = v.mirror.Qc;
         o.alpha = v.mirror.alpha;
@@ -481,6 +605,7 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         f.kind = o.kind; f.axis = o.axis; f.parent = o.parent; f.mat = o.mat; f.detector = o.detector;
         f.mirror_mask = o.mirror_mask; f.child_begin = o.child_begin; f.child_count = o.child_count;
         f.mirror_model = o.mirror_model;
+        f.grid = -1;
         f.R0 = (float)o.R0; f.Qc = (float)o.Qc; f.alpha = (float)o.alpha; f.mQc = (float)o.mQc; f.W = (float)o.W;
         vf[i] = f;
     }
@@ -510,16 +635,31 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         mf.push_back(MatT<float>{(float)o.sa_per_lambda, (float)o.si, (float)o.sc_k, (float)o.ga, (float)o.gs,
                                  o.fam_begin, o.nfam});
     }
+    g.vd = std::move(vd);
+    g.vf = std::move(vf);
+    g.md = std::move(md);
+    g.mf = std::move(mf);
+    g.fd = std::move(fd);
+    g.ff = std::move(ff);
+    g.children = std::move(children);
+    for (int i = 0; i < n; ++i)
+        if ((int)kids[i].size() >= kGridMinDaughters) build_grid(vols, kids[i], g, i);
     g.nv = n;
-    g.nm = (int)md.size();
-    g.nf = (int)fd.size();
-    g.nc = (int)children.size();
+    g.nm = (int)g.md.size();
+    g.nf = (int)g.fd.size();
+    g.nc = (int)g.children.size();
+    g.scene_f_bytes = (int)(g.vf.size() * sizeof(VolT<float>) + g.mf.size() * sizeof(MatT<float>) +
+                            g.ff.size() * sizeof(FamT<float>) + g.children.size() * 4 +
+                            g.gf.size() * sizeof(GridT<float>) + g.cell_start.size() * 4 + g.cell_items.size() * 4) +
+                      7 * 16;
     if (c->device >= 0) {
         int rc = set_device(c);
         if (rc) return rc;
-        if ((rc = upload(c, &g.vols_d, vd)) || (rc = upload(c, &g.vols_f, vf)) || (rc = upload(c, &g.mats_d, md)) ||
-            (rc = upload(c, &g.mats_f, mf)) || (rc = upload(c, &g.fams_d, fd)) || (rc = upload(c, &g.fams_f, ff)) ||
-            (rc = upload(c, &g.children, children))) {
+        if ((rc = upload(c, &g.vols_d, g.vd)) || (rc = upload(c, &g.vols_f, g.vf)) || (rc = upload(c, &g.mats_d, g.md)) ||
+            (rc = upload(c, &g.mats_f, g.mf)) || (rc = upload(c, &g.fams_d, g.fd)) || (rc = upload(c, &g.fams_f, g.ff)) ||
+            (rc = upload(c, &g.children_d, g.children)) || (rc = upload(c, &g.grids_d, g.gd)) ||
+            (rc = upload(c, &g.grids_f, g.gf)) || (rc = upload(c, &g.cell_start_d, g.cell_start)) ||
+            (rc = upload(c, &g.cell_items_d, g.cell_items))) {
             free_geometry(g);
             return rc;
         }
@@ -614,6 +754,51 @@ extern "C" int pr_tally_nbins(pr_ctx* c, int32_t tally, uint64_t* nbins) {
 // run
 // =========================================================================
 
+static void make_source_dev(const pr_source_desc& s, SourceDev& d) {
+    memset(&d, 0, sizeof(d));
+    d.kind = s.kind;
+    d.spectrum = s.spectrum;
+    double nd = std::sqrt(s.dir[0] * s.dir[0] + s.dir[1] * s.dir[1] + s.dir[2] * s.dir[2]);
+    for (int k = 0; k < 3; ++k) {
+        d.o[k] = s.origin[k];
+        d.u[k] = s.dir[k] / nd;
+    }
+    d.size[0] = s.size[0];
+    d.size[1] = s.size[1];
+    d.div_rad[0] = s.div_deg[0] * 3.14159265358979323846 / 180.0;
+    d.div_rad[1] = s.div_deg[1] * 3.14159265358979323846 / 180.0;
+    d.lam0 = s.lam0;
+    d.lam_lo = s.lam_lo;
+    d.lam_hi = s.lam_hi;
+    d.kT = s.kT;
+    d.e_const = ev_angstrom2();
+}
+
+static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
+    memset(&o, 0, sizeof(o));
+    const pr_tally_desc& td = T.desc;
+    o.trigger = td.trigger;
+    o.trigger_volume = td.trigger_volume >= 0 ? td.trigger_volume + vol_offset : -1;
+    o.filter = td.filter;
+    o.filter_arg = td.filter_arg;
+    o.naxes = td.naxes;
+    for (int a = 0; a < td.naxes; ++a) {
+        o.quantity[a] = td.axes[a].quantity;
+        o.nbins[a] = td.axes[a].nbins;
+        o.lo[a] = td.axes[a].lo;
+        o.hi[a] = td.axes[a].hi;
+        o.scale[a] = td.axes[a].nbins / (td.axes[a].hi - td.axes[a].lo);
+    }
+    double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
+    for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
+    o.sw = T.dev;
+    o.sw2 = T.dev ? T.dev + T.nbins : nullptr;
+    o.total = (int64_t)T.nbins;
+    o.lds_offset = -1;
+    o.cache_base = -1;
+    o.cache_bits = 0;
+}
+
 static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
                         uint64_t n, int32_t precision, void* records, Params& P) {
     if (geom < 0 || geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "geometry %d unknown", geom);
@@ -630,11 +815,19 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.vols_f = (const VolT<float>*)g.vols_f;
     P.mats_f = (const MatT<float>*)g.mats_f;
     P.fams_f = (const FamT<float>*)g.fams_f;
-    P.children = (const int32_t*)g.children;
+    P.children = (const int32_t*)g.children_d;
+    P.grids_d = (const GridT<double>*)g.grids_d;
+    P.grids_f = (const GridT<float>*)g.grids_f;
+    P.cell_start = (const int32_t*)g.cell_start_d;
+    P.cell_items = (const int32_t*)g.cell_items_d;
     P.n_vols = g.nv;
     P.n_mats = g.nm;
     P.n_fams = g.nf;
     P.n_children = g.nc;
+    P.n_grids = (int)g.gd.size();
+    P.n_cell_start = (int)g.cell_start.size();
+    P.n_cell_items = (int)g.cell_items.size();
+    P.scene_in_lds = g.scene_f_bytes <= c->lds_scene_budget ? 1 : 0;
     const pr_source_desc& s = c->srcs[src];
     SourceDev& d = P.src;
     d.kind = s.kind;
@@ -844,5 +1037,181 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->lds_tally_bytes = c->lds_tally_budget;
     t->bin_cache_slots = c->bin_cache_slots;
     t->chunk = c->chunk;
+    return PR_OK;
+}
+
+// =========================================================================
+// batched runs
+// =========================================================================
+
+static int get_batch_scene(pr_ctx* c, const std::vector<int32_t>& geoms, BatchScene** out) {
+    auto it = c->batch_scenes.find(geoms);
+    if (it != c->batch_scenes.end()) {
+        *out = &it->second;
+        return PR_OK;
+    }
+    std::vector<VolT<float>> vf;
+    std::vector<MatT<float>> mf;
+    std::vector<FamT<float>> ff;
+    std::vector<int32_t> children, cell_items, cell_start(1, 0);
+    std::vector<GridT<float>> gf;
+    BatchScene b;
+    for (int32_t gid : geoms) {
+        const Geometry& g = c->geoms[gid];
+        const int vo = (int)vf.size(), mo = (int)mf.size(), fo = (int)ff.size(), co = (int)children.size();
+        const int go = (int)gf.size(), cso = (int)cell_start.size() - 1, cio = (int)cell_items.size();
+        b.vol_offset.push_back(vo);
+        for (VolT<float> v : g.vf) {
+            if (v.parent >= 0) v.parent += vo;
+            if (v.mat >= 0) v.mat += mo;
+            if (v.grid >= 0) v.grid += go;
+            v.child_begin += co;
+            vf.push_back(v);
+        }
+        for (MatT<float> m : g.mf) {
+            m.fam_begin += fo;
+            mf.push_back(m);
+        }
+        ff.insert(ff.end(), g.ff.begin(), g.ff.end());
+        for (int32_t ch : g.children) children.push_back(ch + vo);
+        for (GridT<float> G : g.gf) {
+            G.cells_off += cso;
+            gf.push_back(G);
+        }
+        for (size_t j = 1; j < g.cell_start.size(); ++j) cell_start.push_back(g.cell_start[j] + cio);
+        for (int32_t it2 : g.cell_items) cell_items.push_back(it2 + vo);
+    }
+    int rc;
+    if ((rc = upload(c, &b.vols, vf)) || (rc = upload(c, &b.mats, mf)) || (rc = upload(c, &b.fams, ff)) ||
+        (rc = upload(c, &b.children, children)) || (rc = upload(c, &b.grids, gf)) ||
+        (rc = upload(c, &b.cell_start, cell_start)) || (rc = upload(c, &b.cell_items, cell_items))) {
+        void* ps[] = {b.vols, b.mats, b.fams, b.children, b.grids, b.cell_start, b.cell_items};
+        for (void* p : ps)
+            if (p) (void)hipFree(p);
+        return rc;
+    }
+    auto res = c->batch_scenes.emplace(geoms, b);
+    *out = &res.first->second;
+    return PR_OK;
+}
+
+extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream) {
+    if (!c || !sims) return fail(c, PR_EINVAL, "null argument");
+    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
+    if (precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "batched runs use the PR_FP32_MIXED policy");
+    int rc = set_device(c);
+    if (rc) return rc;
+    // geometries in order of first use
+    std::vector<int32_t> geoms;
+    std::vector<int> gindex(nsims);
+    for (int i = 0; i < nsims; ++i) {
+        const pr_sim& sm = sims[i];
+        if (sm.geom < 0 || sm.geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "sims[%d].geom unknown", i);
+        if (sm.src < 0 || sm.src >= (int)c->srcs.size()) return fail(c, PR_ENOTFOUND, "sims[%d].src unknown", i);
+        if (sm.n_tallies < 0 || sm.n_tallies > PR_MAX_TALLIES) return fail(c, PR_EINVAL, "sims[%d].n_tallies out of range", i);
+        if (sm.n > (1ull << 48) || sm.first_history > (1ull << 62)) return fail(c, PR_EINVAL, "sims[%d] history range too large", i);
+        for (int t = 0; t < sm.n_tallies; ++t) {
+            const int tid = sm.tallies[t];
+            if (tid < 0 || tid >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "sims[%d].tallies[%d] unknown", i, t);
+            for (int u = 0; u < t; ++u)
+                if (sm.tallies[u] == tid) return fail(c, PR_EINVAL, "sims[%d] lists tally %d twice", i, tid);
+            const pr_tally_desc& td = c->tallies[tid].desc;
+            if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= c->geoms[sm.geom].nv)
+                return fail(c, PR_EINVAL, "sims[%d]: tally %d trigger_volume beyond its geometry", i, tid);
+        }
+        auto f = std::find(geoms.begin(), geoms.end(), sm.geom);
+        gindex[i] = (int)(f - geoms.begin());
+        if (f == geoms.end()) geoms.push_back(sm.geom);
+    }
+    BatchScene* bs = nullptr;
+    if ((rc = get_batch_scene(c, geoms, &bs))) return rc;
+
+    // simulations, tally table and bin-cache key bases
+    std::vector<SimDev> sd(nsims);
+    std::vector<TallyDev> td;
+    std::vector<uint64_t> kb(1, 0);
+    const uint64_t chunk = (uint64_t)c->chunk;
+    uint64_t chunks = 0;
+    for (int i = 0; i < nsims; ++i) {
+        const pr_sim& sm = sims[i];
+        SimDev& o = sd[i];
+        memset(&o, 0, sizeof(o));
+        const int vo = bs->vol_offset[gindex[i]];
+        o.root = vo;
+        o.tally_begin = (int32_t)td.size();
+        o.tally_count = sm.n_tallies;
+        o.first = sm.first_history;
+        o.n = sm.n;
+        o.chunk_begin = chunks;
+        chunks += (sm.n + chunk - 1) / chunk;
+        make_source_dev(c->srcs[sm.src], o.src);
+        for (int t = 0; t < sm.n_tallies; ++t) {
+            TallyDev T;
+            make_tally_dev(c->tallies[sm.tallies[t]], vo, T);
+            td.push_back(T);
+            kb.push_back(kb.back() + (uint64_t)T.total);
+        }
+    }
+    if (chunks == 0) return PR_OK;
+    // descriptor slot: [sims | tallies | key bases], 256-byte aligned parts
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t b_sims = al(sd.size() * sizeof(SimDev)), b_tal = al(std::max<size_t>(1, td.size()) * sizeof(TallyDev));
+    const size_t b_kb = al(kb.size() * sizeof(uint64_t)), total = b_sims + b_tal + b_kb;
+    DescSlot& sl = c->slots[c->next_slot];
+    c->next_slot = (c->next_slot + 1) % 4;
+    if (sl.used) HIPCHK(c, hipEventSynchronize(sl.done));
+    if (sl.bytes < total) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.dev = sl.host = nullptr;
+        sl.bytes = 0;
+        HIPCHK(c, hipMalloc(&sl.dev, total));
+        HIPCHK(c, hipHostMalloc(&sl.host, total, hipHostMallocDefault));
+        sl.bytes = total;
+    }
+    if (!sl.done) HIPCHK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    char* h = (char*)sl.host;
+    memcpy(h, sd.data(), sd.size() * sizeof(SimDev));
+    if (!td.empty()) memcpy(h + b_sims, td.data(), td.size() * sizeof(TallyDev));
+    memcpy(h + b_sims + b_tal, kb.data(), kb.size() * sizeof(uint64_t));
+    hipStream_t st = (hipStream_t)stream;
+    HIPCHK(c, hipMemcpyAsync(sl.dev, sl.host, total, hipMemcpyHostToDevice, st));
+
+    BatchParams B;
+    memset(&B, 0, sizeof(B));
+    B.vols = (const VolT<float>*)bs->vols;
+    B.mats = (const MatT<float>*)bs->mats;
+    B.fams = (const FamT<float>*)bs->fams;
+    B.children = (const int32_t*)bs->children;
+    B.grids = (const GridT<float>*)bs->grids;
+    B.cell_start = (const int32_t*)bs->cell_start;
+    B.cell_items = (const int32_t*)bs->cell_items;
+    B.sims = (const SimDev*)sl.dev;
+    B.tallies = (const TallyDev*)((char*)sl.dev + b_sims);
+    B.tally_key_base = (const uint64_t*)((char*)sl.dev + b_sims + b_tal);
+    B.nsims = nsims;
+    B.ntallies = (int32_t)td.size();
+    int bits = 0;
+    if (c->bin_cache_slots > 0 && !td.empty())
+        while ((1 << (bits + 1)) <= c->bin_cache_slots) ++bits;
+    B.cache_bits = bits;
+    B.refill_threshold = c->refill_threshold;
+    B.total_chunks = chunks;
+    B.chunk = chunk;
+    B.seed = c->seed;
+    B.stats = c->stats;
+    B.counter = c->counter;
+    const int block = c->mixed_block;
+    const int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, block);
+    uint64_t total_hist = 0;
+    for (int i = 0; i < nsims; ++i) total_hist += sims[i].n;
+    uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, (total_hist + block - 1) / block);
+    if (grid < 1) grid = 1;
+    hipError_t e = launch_batch(B, (int)grid, block, st);
+    if (e != hipSuccess) return hipfail(c, e, "batch kernel launch");
+    HIPCHK(c, hipEventRecord(sl.done, st));
+    sl.used = true;
+    for (int i = 0; i < nsims; ++i)
+        for (int t = 0; t < sims[i].n_tallies; ++t) c->tallies[sims[i].tallies[t]].n_hist += sims[i].n;
     return PR_OK;
 }

@@ -32,8 +32,18 @@ struct VolT {
     R s[3];
     int32_t kind, axis, parent, mat;
     int32_t detector, mirror_mask, child_begin, child_count;
-    int32_t mirror_model, pad;
+    int32_t mirror_model, grid;   // grid: index of the daughter grid, -1 = scan the daughter list
     R R0, Qc, alpha, mQc, W;
+};
+
+// Uniform grid over the daughters of a volume with many daughters: cell c holds
+// the daughters whose (padded) bounding boxes overlap it, cell_items[cell_start[
+// cells_off + c] .. cell_start[cells_off + c + 1]).
+template <class R>
+struct GridT {
+    R lo[3], hi[3], cell[3], inv_cell[3];
+    int32_t n[3];
+    int32_t cells_off;
 };
 
 // Material in macroscopic units (1/mm):
@@ -60,6 +70,9 @@ struct SceneT {
     const MatT<R>* mats;
     const FamT<R>* fams;
     const int32_t* children;
+    const GridT<R>* grids;
+    const int32_t* cell_start;
+    const int32_t* cell_items;
 };
 
 struct SourceDev {
@@ -96,7 +109,13 @@ struct Params {
     const MatT<float>* mats_f;
     const FamT<float>* fams_f;
     const int32_t* children;
+    const GridT<double>* grids_d;
+    const GridT<float>* grids_f;
+    const int32_t* cell_start;
+    const int32_t* cell_items;
     int32_t n_vols, n_mats, n_fams, n_children;
+    int32_t n_grids, n_cell_start, n_cell_items;
+    int32_t scene_in_lds;          // mixed policy: stage the FP32 scene into LDS (else read it from global memory)
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
     int32_t cache_slots;           // LDS bin-cache slots over all cached tallies (mixed policy)
@@ -108,6 +127,38 @@ struct Params {
     unsigned long long* counter;   // history counter of the persistent policy
     int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
+};
+
+// Batched runs: many simulations (each its own world volume, source and
+// tallies) in one launch.  Their scenes are concatenated (indices rebased) and
+// the history indices of all simulations form one chunk space.
+struct SimDev {
+    int32_t root;                  // world volume of this simulation in the batch scene
+    int32_t tally_begin, tally_count;
+    int32_t pad;
+    uint64_t first;                // history id of the simulation's first history
+    uint64_t n;                    // histories
+    uint64_t chunk_begin;          // first chunk of this simulation in the batch chunk space
+    SourceDev src;
+};
+
+struct BatchParams {
+    const VolT<float>* vols;
+    const MatT<float>* mats;
+    const FamT<float>* fams;
+    const int32_t* children;
+    const GridT<float>* grids;
+    const int32_t* cell_start;
+    const int32_t* cell_items;
+    const SimDev* sims;
+    const TallyDev* tallies;       // all tallies of the batch
+    const uint64_t* tally_key_base;   // prefix sums of tally bins: bin-cache key = base + bin
+    int32_t nsims, ntallies;
+    int32_t cache_bits;            // LDS bin cache of 2^cache_bits slots (0 = none)
+    int32_t refill_threshold;
+    uint64_t total_chunks, chunk, seed;
+    unsigned long long* stats;
+    unsigned long long* counter;
 };
 
 // -------------------------------------------------------------------------
@@ -533,17 +584,38 @@ __device__ __forceinline__ R reflectivity(const VolT<R>& V, R Q) {
     return r > (R)0 ? r : (R)0;
 }
 
-// innermost volume containing p, -1 outside the world
+// innermost volume containing p below the world volume `root`, -1 outside it
 template <class R>
-__device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3]) {
-    if (!contains<R>(S.vols[0], p)) return -1;
-    int cur = 0;
+__device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root) {
+    if (!contains<R>(S.vols[root], p)) return -1;
+    int cur = root;
     for (int depth = 0; depth < 64; ++depth) {
         const VolT<R>& V = S.vols[cur];
         int next = -1;
-        for (int i = 0; i < V.child_count; ++i) {
-            int c = S.children[V.child_begin + i];
-            if (contains<R>(S.vols[c], p)) { next = c; break; }
+        if (V.grid >= 0) {
+            // only the daughters listed in the grid cell holding p can contain it
+            const GridT<R>& G = S.grids[V.grid];
+            bool in = true;
+            int cell = 0;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                in = in && p[k] >= G.lo[k] && p[k] <= G.hi[k];
+                int i = (int)__builtin_floor((double)((p[k] - G.lo[k]) * G.inv_cell[k]));
+                i = i < 0 ? 0 : (i >= G.n[k] ? G.n[k] - 1 : i);
+                cell = cell * G.n[k] + i;
+            }
+            if (in) {
+                const int je = S.cell_start[G.cells_off + cell + 1];
+                for (int j = S.cell_start[G.cells_off + cell]; j < je; ++j) {
+                    const int c = S.cell_items[j];
+                    if (contains<R>(S.vols[c], p)) { next = c; break; }
+                }
+            }
+        } else {
+            for (int i = 0; i < V.child_count; ++i) {
+                int c = S.children[V.child_begin + i];
+                if (contains<R>(S.vols[c], p)) { next = c; break; }
+            }
         }
         if (next < 0) break;
         cur = next;
@@ -556,7 +628,8 @@ __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3]) {
 // -------------------------------------------------------------------------
 
 template <class R, bool REC>
-__device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h) {
+__device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h,
+                                       int root) {
     s.h = h;
     s.k = 0;
     s.nbuf = 0;
@@ -604,7 +677,7 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
         s.u[i] = u[i];
     }
     s.lam = lam;
-    s.region = locate<R>(S, s.p);
+    s.region = locate<R>(S, s.p, root);
     hash_ev<REC>(s.hash, EV_SOURCE, s.region);
     if (s.region < 0) s.term = PR_END_OUTSIDE;
 }
@@ -636,6 +709,73 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
 }
 
 // -------------------------------------------------------------------------
+// Nearest daughter entry through a uniform grid (3-D DDA over the cells the
+// ray crosses inside the grid box, up to tmax; stops once the best entry found
+// lies within the cells already visited)
+// -------------------------------------------------------------------------
+
+template <class R>
+__device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>& G, const R p[3], const R u[3], R tmax,
+                                             R& d_child, int& child) {
+    R t0 = (R)0, t1 = tmax;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        if (u[k] == (R)0) {
+            if (p[k] < G.lo[k] || p[k] > G.hi[k]) return;
+        } else {
+            R ta = M<R>::div_(G.lo[k] - p[k], u[k]), tb = M<R>::div_(G.hi[k] - p[k], u[k]);
+            if (ta > tb) { R t = ta; ta = tb; tb = t; }
+            t0 = ta > t0 ? ta : t0;
+            t1 = tb < t1 ? tb : t1;
+        }
+    }
+    if (t0 > t1) return;
+    int ix[3], st[3];
+    R tn[3], td[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R x = p[k] + t0 * u[k];
+        int i = (int)__builtin_floor((double)((x - G.lo[k]) * G.inv_cell[k]));
+        i = i < 0 ? 0 : (i >= G.n[k] ? G.n[k] - 1 : i);
+        ix[k] = i;
+        if (u[k] > (R)0) {
+            st[k] = 1;
+            tn[k] = M<R>::div_(G.lo[k] + (R)(i + 1) * G.cell[k] - p[k], u[k]);
+            td[k] = M<R>::div_(G.cell[k], u[k]);
+        } else if (u[k] < (R)0) {
+            st[k] = -1;
+            tn[k] = M<R>::div_(G.lo[k] + (R)i * G.cell[k] - p[k], u[k]);
+            td[k] = M<R>::div_(-G.cell[k], u[k]);
+        } else {
+            st[k] = 0;
+            tn[k] = rinf<R>();
+            td[k] = rinf<R>();
+        }
+    }
+    const int max_cells = G.n[0] + G.n[1] + G.n[2] + 3;
+    for (int it = 0; it < max_cells; ++it) {
+        const int cell = (ix[0] * G.n[1] + ix[1]) * G.n[2] + ix[2];
+        const int jb = S.cell_start[G.cells_off + cell], je = S.cell_start[G.cells_off + cell + 1];
+        for (int j = jb; j < je; ++j) {
+            const int c = S.cell_items[j];
+            Pieces<R> Q;
+            pieces<R>(S.vols[c], p, u, Q);
+            if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
+            if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
+        }
+        // leave through the nearest cell wall (selects, no indexed private arrays)
+        const bool ax0 = tn[0] <= tn[1] && tn[0] <= tn[2];
+        const bool ax1 = !ax0 && tn[1] <= tn[2];
+        const R tc = ax0 ? tn[0] : (ax1 ? tn[1] : tn[2]);
+        if (d_child <= tc || tc > t1) break;
+        if (ax0) { ix[0] += st[0]; tn[0] += td[0]; }
+        else if (ax1) { ix[1] += st[1]; tn[1] += td[1]; }
+        else { ix[2] += st[2]; tn[2] += td[2]; }
+        if (ix[0] < 0 || ix[0] >= G.n[0] || ix[1] < 0 || ix[1] >= G.n[1] || ix[2] < 0 || ix[2] >= G.n[2]) break;
+    }
+}
+
+// -------------------------------------------------------------------------
 // One step of the history loop
 // -------------------------------------------------------------------------
 
@@ -659,12 +799,16 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
     R d_child = rinf<R>();
     int child = -1;
-    for (int ci = 0; ci < V.child_count; ++ci) {
-        int c = S.children[V.child_begin + ci];
-        Pieces<R> Q;
-        pieces<R>(S.vols[c], s.p, s.u, Q);
-        if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
-        if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
+    if (V.grid >= 0) {
+        grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child);
+    } else {
+        for (int ci = 0; ci < V.child_count; ++ci) {
+            int c = S.children[V.child_begin + ci];
+            Pieces<R> Q;
+            pieces<R>(S.vols[c], s.p, s.u, Q);
+            if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
+            if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
+        }
     }
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
@@ -773,7 +917,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         }
         return;
     }
-    if (s.region == 0) {
+    if (V.parent < 0) {   // leaving a world volume
         s.term = PR_END_ESCAPE;
         hash_ev<REC>(s.hash, EV_ESCAPE, 0);
         return;

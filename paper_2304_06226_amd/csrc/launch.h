@@ -11,6 +11,9 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st);
 hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStream_t st);
 int mixed_occupancy(const Params& P, int block);
 int mixed_lds_bytes(const Params& P);
+hipError_t launch_batch(const BatchParams& B, int grid, int block, hipStream_t st);
+int batch_occupancy(const BatchParams& B, int block);
+int batch_lds_bytes(const BatchParams& B);
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t zero_f64(double* p, uint64_t n, hipStream_t st);
 

@@ -269,3 +269,95 @@ def with_histories(p: Problem, n: int) -> Problem:
 
 
 CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3}
+
+
+# --------------------------------------------------------------------------
+# batched workload: many small powder simulations plus an imaging setup
+# --------------------------------------------------------------------------
+
+@dataclass
+class Batch:
+    problems: List[Problem]          # one per simulation; n_histories each
+    name: str = "batch"
+
+    @property
+    def total_histories(self) -> int:
+        return int(sum(p.n_histories for p in self.problems))
+
+
+def batch_sample_sims(n_sims: int = 256, scale: float = 1.0, rng: Optional[np.random.Generator] = None) -> List[Problem]:
+    """Independent powder simulations: cylinder r ~ U[1,20] mm (h 20 mm, axis y),
+    odd ones inside an Al-like vessel wall (r_in = r + 5, r_out = r_in + 1, h 40 mm);
+    fcc a ~ U[3.5,6] A with n = 4/a^3, sigma_inc 5 b, sigma_abs 2 b; mono pencil
+    lambda ~ U[1,5] A; scattering bias g in {1,2,4,8}; N ~ 10^U[4,6] (times scale);
+    2theta(1800) of scattered escapes and a transmitted counter."""
+    rng = setup_rng(4) if rng is None else rng
+    vessel = vessel_material()
+    sims = []
+    for i in range(n_sims):
+        r = rng.uniform(1.0, 20.0)
+        lam = rng.uniform(1.0, 5.0)
+        a = rng.uniform(3.5, 6.0)
+        g = float(rng.choice([1.0, 2.0, 4.0, 8.0]))
+        n = int(round(10 ** rng.uniform(4.0, 6.0) * scale))
+        mat = fcc_material(a, 4.0 / a ** 3, 5.0, 2.0, rng).biased(scatter_bias=g)
+        vols = [Volume("sphere", (0.0, 0.0, 0.0), (1000.0,)),
+                Volume("cylinder", (0.0, 0.0, 0.0), (r, 20.0), axis=1, parent=0, material=0)]
+        mats = [mat]
+        if i % 2 == 1:
+            mats.append(vessel)
+            vols.append(Volume("cyl_shell", (0.0, 0.0, 0.0), (r + 5.0, r + 6.0, 40.0), axis=1, parent=0, material=1))
+        src = Source("pencil", origin=(0.0, 0.0, -100.0), direction=(0.0, 0.0, 1.0), spectrum="mono", lam0=lam)
+        tallies = [_angle_tally_2theta(), Tally(trigger="escape", filter="unscattered")]
+        sims.append(Problem(mats, vols, src, tallies, n_histories=max(n, 1), name=f"sim{i}"))
+    return sims
+
+
+def imaging_problem(n: int = 10_000_000, n_boxes: int = 1000, rng: Optional[np.random.Generator] = None) -> Problem:
+    """Imaging: n_boxes non-overlapping axis-aligned boxes (sides U[5,50] mm, placed
+    by rejection with a 0.5 mm gap in 500x500x300 mm) of the powder-sample and vessel
+    materials alternately, a parallel 2 A beam over 500x500 mm along +z and a 512x512
+    pixel detector (500x500 mm) behind them."""
+    rng = setup_rng(5) if rng is None else rng
+    lo = np.array([-250.0, -250.0, -150.0])
+    hi = np.array([250.0, 250.0, 150.0])
+    centers, halves = [], []
+    gap = 0.5
+    attempts = 0
+    while len(centers) < n_boxes:
+        attempts += 1
+        if attempts > 2_000_000:
+            raise RuntimeError("could not place the imaging boxes")
+        h = rng.uniform(5.0, 50.0, 3) / 2
+        c = rng.uniform(lo + h, hi - h)
+        if centers:
+            C = np.asarray(centers)
+            H = np.asarray(halves)
+            sep = np.abs(C - c) - (H + h)
+            if np.any(np.all(sep < gap, axis=1)):
+                continue
+        centers.append(c)
+        halves.append(h)
+    mats = [sample_material(), vessel_material()]
+    vols = [Volume("box", (0.0, 0.0, 0.0), (700.0, 700.0, 600.0))]
+    for i, (c, h) in enumerate(zip(centers, halves)):
+        vols.append(Volume("box", tuple(c), tuple(2 * h), parent=0, material=i % 2))
+    vols.append(Volume("box", (0.0, 0.0, 200.0), (520.0, 520.0, 2.0), parent=0, detector=True))
+    det = len(vols) - 1
+    src = Source("rect", origin=(0.0, 0.0, -250.0), direction=(0.0, 0.0, 1.0), size=(500.0, 500.0),
+                 spectrum="mono", lam0=2.0)
+    tallies = [Tally(trigger="detect", trigger_volume=det,
+                     axes=[Axis("x", -250.0, 250.0, 512), Axis("y", -250.0, 250.0, 512)]),
+               Tally(trigger="detect", trigger_volume=det, filter="unscattered",
+                     axes=[Axis("x", -250.0, 250.0, 512), Axis("y", -250.0, 250.0, 512)])]
+    return Problem(mats, vols, src, tallies, n_histories=n, name="imaging")
+
+
+def config4(scale: float = 1.0, imaging_histories: int = 10_000_000, n_sims: int = 256) -> Batch:
+    """Batched: 256 uneven powder simulations plus the 1000-box imaging setup."""
+    sims = batch_sample_sims(n_sims, scale)
+    sims.append(imaging_problem(int(imaging_histories)))
+    return Batch(sims, name="config4")
+
+
+CONFIGS[4] = config4

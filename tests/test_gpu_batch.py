@@ -1,0 +1,130 @@
+"""GPU parity of the uniform-grid navigation and of batched runs.
+
+* The 1000-box imaging problem in FP64 is compared history by history with the
+  oracle, which scans every box (the GPU walks a uniform grid).
+* A batch of uneven simulations in one persistent launch reproduces, per
+  simulation and per tally bin, the same simulations run one by one (up to the
+  order of floating-point summation), and agrees statistically with the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2304_06226_amd import binding as B
+from paper_2304_06226_amd import workloads as W
+
+from parity import compare_records_fp64, compare_tallies_fp64, gpu_run, tally_stat_test
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    c = B.Context(device=0, seed=4096)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def imaging():
+    return W.imaging_problem(n=20_000)
+
+
+def test_imaging_grid_fp64_elementwise(ctx, imaging):
+    print("[case] imaging fp64 n=20000", flush=True)
+    gres, grec, gst = gpu_run(ctx, imaging, first=0, n=20_000, precision="fp64")
+    ores = O.run(imaging, first=0, n=20_000, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+    assert (grec["term"] == B.END_DETECT).mean() > 0.2
+
+
+def test_imaging_fp32_tally_agreement(ctx, imaging):
+    print("[case] imaging fp32 n=200000", flush=True)
+    prob = W.imaging_problem(n=200_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
+    ores = O.run(prob, first=0, n=200_000, threads=8)
+    for t, (sw, sw2, nh) in enumerate(gres):
+        # coarse 32x32 pixels: sums of 16x16 detector pixels
+        def coarse(a):
+            return a.reshape(32, 16, 32, 16).sum(axis=(1, 3)).ravel()
+        p, z = tally_stat_test(coarse(sw), coarse(sw2), nh, coarse(ores.sumw[t]), coarse(ores.sumw2[t]), ores.n)
+        assert p > 1e-3
+
+
+def _small_batch():
+    return W.config4(scale=0.01, imaging_histories=50_000, n_sims=24)
+
+
+def test_batch_equals_individual_runs(ctx):
+    import torch
+    batch = _small_batch()
+    print(f"[case] batch of {len(batch.problems)} sims, {batch.total_histories} histories", flush=True)
+    br = B.BatchRun(ctx, batch)
+    ctx.reset_stats()
+    br.run()
+    torch.cuda.synchronize()
+    st_batch = ctx.read_stats()
+    got = [s.results() for s in br.sims]
+    # the same simulations one by one (fresh tallies)
+    single = B.BatchRun(ctx, batch)
+    ctx.reset_stats()
+    for s, (g, sr, ts, first, n) in zip(single.sims, single.descriptors()):
+        s.run(first=first, n=n, precision="fp32")
+    torch.cuda.synchronize()
+    st_single = ctx.read_stats()
+    assert st_batch == st_single
+    for a, b in zip(got, [s.results() for s in single.sims]):
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+            assert nh == rn
+            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+
+
+def test_batch_against_oracle(ctx):
+    import torch
+    batch = _small_batch()
+    br = B.BatchRun(ctx, batch, base=10_000_000)
+    br.run()
+    torch.cuda.synchronize()
+    pvals = []
+    for i in list(range(0, 24, 5)) + [24]:
+        s = br.sims[i]
+        prob = batch.problems[i]
+        o = O.run(prob, first=br.offsets[i], n=prob.n_histories, threads=8)
+        for t, (sw, sw2, nh) in enumerate(s.results()):
+            if prob.name == "imaging":
+                def coarse(a):
+                    return a.reshape(32, 16, 32, 16).sum(axis=(1, 3)).ravel()
+                sw, sw2, ow, ow2 = coarse(sw), coarse(sw2), coarse(o.sumw[t]), coarse(o.sumw2[t])
+            else:
+                ow, ow2 = o.sumw[t], o.sumw2[t]
+            p, z = tally_stat_test(sw, sw2, nh, ow, ow2, o.n)
+            pvals.append(p)
+    assert min(pvals) > 1e-4, pvals
+
+
+def test_batch_tuning_and_validation(ctx):
+    import torch
+    batch = W.config4(scale=0.003, imaging_histories=20_000, n_sims=8)
+    base = ctx.get_tuning()
+    res = []
+    try:
+        for t in (dict(), dict(chunk=64, refill_threshold=4, bin_cache_slots=0), dict(chunk=1024, bin_cache_slots=4096)):
+            ctx.set_tuning(**{**base, **t})
+            br = B.BatchRun(ctx, batch)
+            br.run()
+            torch.cuda.synchronize()
+            res.append([s.results() for s in br.sims])
+    finally:
+        ctx.set_tuning(**base)
+    for other in res[1:]:
+        for a, b in zip(res[0], other):
+            for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+                np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+    with pytest.raises(B.PromptError):
+        ctx.run_batch([(0, 0, [0], 0, 10)], precision="fp64")
+    with pytest.raises(B.PromptError):
+        ctx.run_batch([(999, 0, [], 0, 10)])

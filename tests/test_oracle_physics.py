@@ -413,3 +413,43 @@ def test_split_resume_and_threads_identical():
     assert (both == full.records).all()
     for t in range(len(p.tallies)):
         assert np.allclose(a.sumw[t] + b.sumw[t], full.sumw[t], rtol=1e-12, atol=1e-300)
+
+
+# --------------------------------------------------------------------------
+# imaging: unscattered transmission through axis-aligned boxes
+# --------------------------------------------------------------------------
+
+def test_imaging_unscattered_transmission_closed_form():
+    """A parallel beam along z through axis-aligned boxes: the probability of
+    reaching the detector unscattered is exp(-sum_i Sigma_i dz_i) over the boxes
+    whose xy-extent covers the source point (Beer-Lambert per chord)."""
+    p = W.imaging_problem(n=40_000, n_boxes=300)
+    n = 40_000
+    r = O.run(p, n=n, threads=8, records=True)
+    rec = r.records
+    seed = 4096
+    x0 = np.array([(O.uniform(seed, h, 0) - 0.5) * 500.0 for h in range(n)])
+    y0 = np.array([(O.uniform(seed, h, 1) - 0.5) * 500.0 for h in range(n)])
+    sig = []
+    for m in p.materials:
+        xs = O.macro_xs(m, 2.0)
+        sig.append(xs[0] + xs[1] + xs[2])
+    tau = np.zeros(n)
+    for v in p.volumes[1:-1]:
+        cx, cy, _ = v.center
+        sx, sy, sz = v.size
+        inside = (np.abs(x0 - cx) <= sx / 2) & (np.abs(y0 - cy) <= sy / 2)
+        tau += inside * sig[v.material] * sz
+    expect = np.exp(-tau)
+    det = len(p.volumes) - 1
+    got = ((rec["term"] == O.END_DETECT) & (rec["n_scat"] == 0) & (rec["region"] == det)).astype(float)
+    # per history the unscattered outcome is Bernoulli(expect): z-test of the total and of 16 groups
+    z = (got.sum() - expect.sum()) / np.sqrt((expect * (1 - expect)).sum())
+    assert abs(z) < 4, z
+    grp = np.argsort(expect)
+    for g in np.array_split(grp, 16):
+        v = (expect[g] * (1 - expect[g])).sum()
+        if v > 10:
+            assert abs((got[g].sum() - expect[g].sum()) / np.sqrt(v)) < 4.5
+    # the tally's unscattered image holds exactly those weights
+    assert r.sumw[1].sum() == pytest.approx(got.sum())
