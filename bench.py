@@ -104,6 +104,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the history range would be "
@@ -127,6 +130,8 @@ def main():
                                   "2theta(1800) x lambda(100) + transmitted + absorbed tallies",
                       "histories_per_step": n, "seed": W.RUN_SEED}}
     fp32 = fp64 = None
+    if args.only in ("fp32", "both") and not args.no_autotune:
+        out["tuning"] = ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=0.2)
     if args.only in ("fp32", "both"):
         ms, st = time_policy(torch, sim, n, "fp32", args.steps, args.warmup)
         fp32 = (ms, st)
@@ -153,6 +158,30 @@ def main():
     out["events_per_history"] = {"steps": head_st["steps"] / head_st["histories"],
                                  "draws": head_st["draws"] / head_st["histories"],
                                  "scatters": head_st["scatters"] / head_st["histories"]}
+    if not args.no_batch:
+        # the batched workload: 256 uneven powder simulations + the 1000-box imaging setup
+        batch = W.config4()
+        br = B.BatchRun(ctx, batch, base=1 << 40)
+        tuned = ctx.autotune(br.descriptors(), sample_fraction=0.05)
+        br.run()
+        torch.cuda.synchronize()
+        ctx.reset_stats()
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record()
+        for k in range(args.batch_steps):
+            br.run(shift=(k + 1) * br.span)
+        t1.record()
+        torch.cuda.synchronize()
+        bms = t0.elapsed_time(t1) / args.batch_steps
+        bst = ctx.read_stats()
+        out["batched"] = {"value": batch.total_histories / bms * 1e3, "unit": "histories/s", "ms_per_step": bms,
+                          "histories_per_step": batch.total_histories, "simulations": len(batch.problems),
+                          "steps_per_history": bst["steps"] / max(1, bst["histories"]), "tuning": tuned,
+                          "workload": "256 powder simulations (r 1-20 mm, a 3.5-6 A, lambda 1-5 A, bias 1/2/4/8, "
+                                      "1e4-1e6 histories each, odd ones in a vessel) + 1000-box imaging, 1e7 histories"}
+        print(f"[bench] batched {bms:.3f} ms/step, {batch.total_histories / bms * 1e3:.4g} histories/s",
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

@@ -248,7 +248,9 @@ int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precisi
  * lds_tally_bytes: LDS per block for privatised tallies (tallies are
  * privatised in order while they fit); bin_cache_slots: LDS bin-cache slots
  * given to each tally that is not privatised (0 or a power of two <= 4096);
- * chunk: history indices a wave claims from the shared counter per atomic.
+ * chunk: history indices a wave claims from the shared counter per atomic;
+ * superchunk: histories of one simulation a block claims per visit in
+ * pr_run_batch (the block stages that simulation's scene and tallies in LDS).
  * Results do not depend on these settings beyond floating-point summation
  * order. */
 typedef struct {
@@ -258,10 +260,23 @@ typedef struct {
     int32_t lds_tally_bytes;
     int32_t bin_cache_slots;
     int32_t chunk;
+    int32_t superchunk;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
 int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
+
+/* Pick the launch tuning for a workload by measurement: coordinate descent
+ * (two passes) over refill threshold, chunk, resident blocks per CU, bin-cache
+ * slots and, for batches, super-chunk, each candidate timed with HIP events on
+ * `stream` over a sample of the workload (every simulation's history count
+ * times sample_fraction, at least 1).  nsims = 1 tunes pr_run_histories'
+ * PR_FP32_MIXED policy, nsims > 1 tunes pr_run_batch.  Trial runs score into
+ * a context-owned scratch buffer and scratch statistics: the caller's tallies
+ * and run statistics are untouched.  The best tuning is set on the context and
+ * written to *best.  Synchronises `stream`. */
+int pr_autotune(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, double sample_fraction, pr_tuning* best,
+                void* stream);
 
 /* ---- results ---- */
 /* Synchronise `stream` and copy the tally into host arrays of nbins doubles

@@ -42,7 +42,7 @@ RECORD_BYTES = 96
 EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_material", "pr_create_geometry",
            "pr_create_source", "pr_create_tally", "pr_tally_nbins", "pr_run_histories", "pr_read_tally",
            "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats", "pr_set_tuning",
-           "pr_get_tuning", "pr_run_batch"]
+           "pr_get_tuning", "pr_run_batch", "pr_autotune"]
 
 
 class pr_material_desc(C.Structure):
@@ -81,7 +81,8 @@ class pr_tally_desc(C.Structure):
 
 class pr_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_threshold", C.c_int32),
-                ("lds_tally_bytes", C.c_int32), ("bin_cache_slots", C.c_int32), ("chunk", C.c_int32)]
+                ("lds_tally_bytes", C.c_int32), ("bin_cache_slots", C.c_int32), ("chunk", C.c_int32),
+                ("superchunk", C.c_int32)]
 
 
 class pr_sim(C.Structure):
@@ -126,6 +127,7 @@ def load():
     L.pr_reset_stats.argtypes = [vp, vp]
     L.pr_set_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     L.pr_run_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, vp]
+    L.pr_autotune.argtypes = [vp, C.POINTER(pr_sim), i32, C.c_double, C.POINTER(pr_tuning), vp]
     L.pr_get_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     for name in EXPORTS:
         f = getattr(L, name)
@@ -296,6 +298,24 @@ class Context:
         st = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(self.lib.pr_read_stats(self.h, C.byref(s), st))
         return {name: getattr(s, name) for name, _ in pr_run_stats._fields_}
+
+    @staticmethod
+    def _sims(sims):
+        arr = (pr_sim * len(sims))()
+        for i, (g, sr, ts, first, n) in enumerate(sims):
+            arr[i].geom, arr[i].src, arr[i].n_tallies = g, sr, len(ts)
+            for j, t in enumerate(ts):
+                arr[i].tallies[j] = t
+            arr[i].first_history, arr[i].n = first, n
+        return arr
+
+    def autotune(self, sims, sample_fraction=0.1, stream=None) -> dict:
+        """Measure and set the launch tuning for a workload (list of (geom, src, tallies, first, n))."""
+        arr = self._sims(sims)
+        t = pr_tuning()
+        st = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(self.lib.pr_autotune(self.h, arr, len(sims), sample_fraction, C.byref(t), st))
+        return {name: getattr(t, name) for name, _ in pr_tuning._fields_}
 
     def run_batch(self, sims, precision="fp32", stream=None):
         """sims: list of (geom, src, tallies, first, n)."""

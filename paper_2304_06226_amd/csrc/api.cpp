@@ -61,19 +61,6 @@ struct Tally {
     uint64_t n_hist = 0;
 };
 
-// Concatenated FP32 scene of the geometries of a batch (volume, material,
-// family, daughter, grid and cell indices rebased), cached per geometry list.
-struct BatchScene {
-    std::vector<int32_t> vol_offset;   // per geometry of the list
-    void* vols = nullptr;
-    void* mats = nullptr;
-    void* fams = nullptr;
-    void* children = nullptr;
-    void* grids = nullptr;
-    void* cell_start = nullptr;
-    void* cell_items = nullptr;
-};
-
 // Per-call batch descriptors (simulations, tallies, key bases): a small ring of
 // device buffers filled from pinned host staging, each reused only after the
 // event recorded behind its last launch has completed.
@@ -106,8 +93,11 @@ struct pr_ctx {
     int bin_cache_slots = 1024;         // LDS bin-cache slots per non-privatised tally (power of two, 0 = off)
     int chunk = 256;                    // history indices a wave claims per atomic
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
-    std::map<std::vector<int32_t>, BatchScene> batch_scenes;
     DescSlot slots[4];
+    int superchunk = 2048;              // batched runs: histories a block claims per simulation visit
+    double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
+    uint64_t scratch_bins = 0;
+    unsigned long long* scratch_stats = nullptr;
     int next_slot = 0;
 };
 
@@ -411,12 +401,8 @@ extern "C" void pr_destroy(pr_ctx* c) {
             if (t.dev) (void)hipFree(t.dev);
         if (c->stats) (void)hipFree(c->stats);
         if (c->counter) (void)hipFree(c->counter);
-        for (auto& kv : c->batch_scenes) {
-            BatchScene& b = kv.second;
-            void* ps[] = {b.vols, b.mats, b.fams, b.children, b.grids, b.cell_start, b.cell_items};
-            for (void* p : ps)
-                if (p) (void)hipFree(p);
-        }
+        if (c->scratch) (void)hipFree(c->scratch);
+        if (c->scratch_stats) (void)hipFree(c->scratch_stats);
         for (auto& sl : c->slots) {
             if (sl.dev) (void)hipFree(sl.dev);
             if (sl.host) (void)hipHostFree(sl.host);
@@ -828,6 +814,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n_cell_start = (int)g.cell_start.size();
     P.n_cell_items = (int)g.cell_items.size();
     P.scene_in_lds = g.scene_f_bytes <= c->lds_scene_budget ? 1 : 0;
+    P.has_grid = g.gd.empty() ? 0 : 1;
     const pr_source_desc& s = c->srcs[src];
     SourceDev& d = P.src;
     d.kind = s.kind;
@@ -910,14 +897,20 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     return PR_OK;
 }
 
-extern "C" int pr_run_histories(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt,
-                                uint64_t first, uint64_t n, int32_t precision, void* records, void* stream) {
-    if (!c) return PR_EINVAL;
+// Launch one history range.  trial: autotuner run scoring into scratch.
+static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
+                      uint64_t n, int32_t precision, void* records, hipStream_t st, bool trial) {
     Params P;
     int rc = build_params(c, geom, src, tallies, nt, first, n, precision, records, P);
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
-    hipStream_t st = (hipStream_t)stream;
+    if (trial) {
+        for (int i = 0; i < nt; ++i) {
+            P.tallies[i].sw = c->scratch;
+            P.tallies[i].sw2 = c->scratch + c->scratch_bins;
+        }
+        P.stats = c->scratch_stats;
+    }
     hipError_t e;
     if (precision == PR_FP64_PLAIN) {
         e = launch_plain(P, records != nullptr, st);
@@ -932,6 +925,14 @@ extern "C" int pr_run_histories(pr_ctx* c, int32_t geom, int32_t src, const int3
         e = launch_mixed(P, records != nullptr, (int)grid, block, st);
     }
     if (e != hipSuccess) return hipfail(c, e, "kernel launch");
+    return PR_OK;
+}
+
+extern "C" int pr_run_histories(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt,
+                                uint64_t first, uint64_t n, int32_t precision, void* records, void* stream) {
+    if (!c) return PR_EINVAL;
+    int rc = run_single(c, geom, src, tallies, nt, first, n, precision, records, (hipStream_t)stream, false);
+    if (rc) return rc;
     for (int i = 0; i < nt; ++i) c->tallies[tallies[i]].n_hist += n;
     return PR_OK;
 }
@@ -1020,7 +1021,9 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
     if (t->bin_cache_slots < 0 || t->bin_cache_slots > 4096 || (t->bin_cache_slots & (t->bin_cache_slots - 1)))
         return fail(c, PR_EINVAL, "tuning.bin_cache_slots must be 0 or a power of two up to 4096");
     if (t->chunk < 1 || t->chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.chunk must be 1..2^20");
+    if (t->superchunk < 1 || t->superchunk > (1 << 30)) return fail(c, PR_EINVAL, "tuning.superchunk must be 1..2^30");
     c->chunk = t->chunk;
+    c->superchunk = t->superchunk;
     c->mixed_block = t->block;
     c->mixed_blocks_per_cu = t->blocks_per_cu;
     c->refill_threshold = t->refill_threshold;
@@ -1037,6 +1040,7 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->lds_tally_bytes = c->lds_tally_budget;
     t->bin_cache_slots = c->bin_cache_slots;
     t->chunk = c->chunk;
+    t->superchunk = c->superchunk;
     return PR_OK;
 }
 
@@ -1044,115 +1048,81 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
 // batched runs
 // =========================================================================
 
-static int get_batch_scene(pr_ctx* c, const std::vector<int32_t>& geoms, BatchScene** out) {
-    auto it = c->batch_scenes.find(geoms);
-    if (it != c->batch_scenes.end()) {
-        *out = &it->second;
-        return PR_OK;
-    }
-    std::vector<VolT<float>> vf;
-    std::vector<MatT<float>> mf;
-    std::vector<FamT<float>> ff;
-    std::vector<int32_t> children, cell_items, cell_start(1, 0);
-    std::vector<GridT<float>> gf;
-    BatchScene b;
-    for (int32_t gid : geoms) {
-        const Geometry& g = c->geoms[gid];
-        const int vo = (int)vf.size(), mo = (int)mf.size(), fo = (int)ff.size(), co = (int)children.size();
-        const int go = (int)gf.size(), cso = (int)cell_start.size() - 1, cio = (int)cell_items.size();
-        b.vol_offset.push_back(vo);
-        for (VolT<float> v : g.vf) {
-            if (v.parent >= 0) v.parent += vo;
-            if (v.mat >= 0) v.mat += mo;
-            if (v.grid >= 0) v.grid += go;
-            v.child_begin += co;
-            vf.push_back(v);
-        }
-        for (MatT<float> m : g.mf) {
-            m.fam_begin += fo;
-            mf.push_back(m);
-        }
-        ff.insert(ff.end(), g.ff.begin(), g.ff.end());
-        for (int32_t ch : g.children) children.push_back(ch + vo);
-        for (GridT<float> G : g.gf) {
-            G.cells_off += cso;
-            gf.push_back(G);
-        }
-        for (size_t j = 1; j < g.cell_start.size(); ++j) cell_start.push_back(g.cell_start[j] + cio);
-        for (int32_t it2 : g.cell_items) cell_items.push_back(it2 + vo);
-    }
-    int rc;
-    if ((rc = upload(c, &b.vols, vf)) || (rc = upload(c, &b.mats, mf)) || (rc = upload(c, &b.fams, ff)) ||
-        (rc = upload(c, &b.children, children)) || (rc = upload(c, &b.grids, gf)) ||
-        (rc = upload(c, &b.cell_start, cell_start)) || (rc = upload(c, &b.cell_items, cell_items))) {
-        void* ps[] = {b.vols, b.mats, b.fams, b.children, b.grids, b.cell_start, b.cell_items};
-        for (void* p : ps)
-            if (p) (void)hipFree(p);
-        return rc;
-    }
-    auto res = c->batch_scenes.emplace(geoms, b);
-    *out = &res.first->second;
-    return PR_OK;
-}
-
-extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream) {
-    if (!c || !sims) return fail(c, PR_EINVAL, "null argument");
-    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
-    if (precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "batched runs use the PR_FP32_MIXED policy");
-    int rc = set_device(c);
-    if (rc) return rc;
-    // geometries in order of first use
-    std::vector<int32_t> geoms;
-    std::vector<int> gindex(nsims);
-    for (int i = 0; i < nsims; ++i) {
-        const pr_sim& sm = sims[i];
-        if (sm.geom < 0 || sm.geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "sims[%d].geom unknown", i);
-        if (sm.src < 0 || sm.src >= (int)c->srcs.size()) return fail(c, PR_ENOTFOUND, "sims[%d].src unknown", i);
-        if (sm.n_tallies < 0 || sm.n_tallies > PR_MAX_TALLIES) return fail(c, PR_EINVAL, "sims[%d].n_tallies out of range", i);
-        if (sm.n > (1ull << 48) || sm.first_history > (1ull << 62)) return fail(c, PR_EINVAL, "sims[%d] history range too large", i);
-        for (int t = 0; t < sm.n_tallies; ++t) {
-            const int tid = sm.tallies[t];
-            if (tid < 0 || tid >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "sims[%d].tallies[%d] unknown", i, t);
-            for (int u = 0; u < t; ++u)
-                if (sm.tallies[u] == tid) return fail(c, PR_EINVAL, "sims[%d] lists tally %d twice", i, tid);
-            const pr_tally_desc& td = c->tallies[tid].desc;
-            if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= c->geoms[sm.geom].nv)
-                return fail(c, PR_EINVAL, "sims[%d]: tally %d trigger_volume beyond its geometry", i, tid);
-        }
-        auto f = std::find(geoms.begin(), geoms.end(), sm.geom);
-        gindex[i] = (int)(f - geoms.begin());
-        if (f == geoms.end()) geoms.push_back(sm.geom);
-    }
-    BatchScene* bs = nullptr;
-    if ((rc = get_batch_scene(c, geoms, &bs))) return rc;
-
-    // simulations, tally table and bin-cache key bases
-    std::vector<SimDev> sd(nsims);
+// One persistent launch over the simulations idx of one class.
+static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>& idx, bool slds, bool grid_nav,
+                           hipStream_t st, bool trial = false) {
+    // LDS budgets: a simulation's tallies are privatised when they fit the tally
+    // region, else they go through the bin cache whose values share that region
+    const int priv_cap = c->lds_tally_budget / 8;
+    int cache_bits = 0;
+    if (c->bin_cache_slots > 0)
+        while ((1 << (cache_bits + 1)) <= c->bin_cache_slots) ++cache_bits;
+    const int nslots = c->bin_cache_slots > 0 ? (1 << cache_bits) : 0;
+    const int ns = (int)idx.size();
+    std::vector<SimDev> sd(ns);
     std::vector<TallyDev> td;
-    std::vector<uint64_t> kb(1, 0);
-    const uint64_t chunk = (uint64_t)c->chunk;
-    uint64_t chunks = 0;
-    for (int i = 0; i < nsims; ++i) {
-        const pr_sim& sm = sims[i];
-        SimDev& o = sd[i];
+    std::vector<uint64_t> kb;
+    const uint64_t sc_size = (uint64_t)c->superchunk;
+    uint64_t scs = 0;
+    int tally_doubles = 0, scene_bytes = 0;
+    bool any_cache = false;
+    for (int q = 0; q < ns; ++q) {
+        const pr_sim& sm = sims[idx[q]];
+        const Geometry& g = c->geoms[sm.geom];
+        SimDev& o = sd[q];
         memset(&o, 0, sizeof(o));
-        const int vo = bs->vol_offset[gindex[i]];
-        o.root = vo;
+        o.vols = (const VolT<float>*)g.vols_f;
+        o.mats = (const MatT<float>*)g.mats_f;
+        o.fams = (const FamT<float>*)g.fams_f;
+        o.children = (const int32_t*)g.children_d;
+        o.grids = (const GridT<float>*)g.grids_f;
+        o.cell_start = (const int32_t*)g.cell_start_d;
+        o.cell_items = (const int32_t*)g.cell_items_d;
+        o.n_vols = g.nv;
+        o.n_mats = g.nm;
+        o.n_fams = g.nf;
+        o.n_children = g.nc;
+        o.n_grids = (int)g.gf.size();
+        o.n_cell_start = (int)g.cell_start.size();
+        o.n_cell_items = (int)g.cell_items.size();
+        o.scene_in_lds = slds ? 1 : 0;
+        if (slds)
+            scene_bytes = std::max(scene_bytes, batch_scene_lds_bytes(o.n_vols, o.n_mats, o.n_fams, o.n_children,
+                                                                      o.n_grids, o.n_cell_start, o.n_cell_items));
         o.tally_begin = (int32_t)td.size();
         o.tally_count = sm.n_tallies;
-        o.first = sm.first_history;
-        o.n = sm.n;
-        o.chunk_begin = chunks;
-        chunks += (sm.n + chunk - 1) / chunk;
-        make_source_dev(c->srcs[sm.src], o.src);
+        int64_t need = 0;
+        for (int t = 0; t < sm.n_tallies; ++t) need += 2 * (int64_t)c->tallies[sm.tallies[t]].nbins;
+        o.privatised = need <= priv_cap ? 1 : 0;
+        if (o.privatised) tally_doubles = std::max<int>(tally_doubles, (int)need);
+        else any_cache = true;
+        uint64_t key = 0;
+        int64_t loff = 0;
         for (int t = 0; t < sm.n_tallies; ++t) {
             TallyDev T;
-            make_tally_dev(c->tallies[sm.tallies[t]], vo, T);
+            make_tally_dev(c->tallies[sm.tallies[t]], 0, T);
+            if (trial) {   // autotuner trials score into scratch, never into the caller's tallies
+                T.sw = c->scratch;
+                T.sw2 = c->scratch + c->scratch_bins;
+            }
+            if (o.privatised) {
+                T.lds_offset = (int32_t)loff;
+                loff += 2 * T.total;
+            }
             td.push_back(T);
-            kb.push_back(kb.back() + (uint64_t)T.total);
+            kb.push_back(key);
+            key += (uint64_t)T.total;
         }
+        o.first = sm.first_history;
+        o.n = sm.n;
+        o.sc_begin = scs;
+        scs += (sm.n + sc_size - 1) / sc_size;
+        make_source_dev(c->srcs[sm.src], o.src);
     }
-    if (chunks == 0) return PR_OK;
+    if (scs == 0) return PR_OK;
+    if (any_cache) tally_doubles = std::max(tally_doubles, 2 * nslots);
+    if (td.empty()) kb.push_back(0);
+
     // descriptor slot: [sims | tallies | key bases], 256-byte aligned parts
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t b_sims = al(sd.size() * sizeof(SimDev)), b_tal = al(std::max<size_t>(1, td.size()) * sizeof(TallyDev));
@@ -1174,44 +1144,186 @@ extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_
     memcpy(h, sd.data(), sd.size() * sizeof(SimDev));
     if (!td.empty()) memcpy(h + b_sims, td.data(), td.size() * sizeof(TallyDev));
     memcpy(h + b_sims + b_tal, kb.data(), kb.size() * sizeof(uint64_t));
-    hipStream_t st = (hipStream_t)stream;
     HIPCHK(c, hipMemcpyAsync(sl.dev, sl.host, total, hipMemcpyHostToDevice, st));
 
     BatchParams B;
     memset(&B, 0, sizeof(B));
-    B.vols = (const VolT<float>*)bs->vols;
-    B.mats = (const MatT<float>*)bs->mats;
-    B.fams = (const FamT<float>*)bs->fams;
-    B.children = (const int32_t*)bs->children;
-    B.grids = (const GridT<float>*)bs->grids;
-    B.cell_start = (const int32_t*)bs->cell_start;
-    B.cell_items = (const int32_t*)bs->cell_items;
     B.sims = (const SimDev*)sl.dev;
     B.tallies = (const TallyDev*)((char*)sl.dev + b_sims);
     B.tally_key_base = (const uint64_t*)((char*)sl.dev + b_sims + b_tal);
-    B.nsims = nsims;
+    B.nsims = ns;
     B.ntallies = (int32_t)td.size();
-    int bits = 0;
-    if (c->bin_cache_slots > 0 && !td.empty())
-        while ((1 << (bits + 1)) <= c->bin_cache_slots) ++bits;
-    B.cache_bits = bits;
+    B.lds_tally_doubles = tally_doubles;
+    B.cache_bits = any_cache ? cache_bits : 0;
+    B.lds_scene_bytes = scene_bytes;
     B.refill_threshold = c->refill_threshold;
-    B.total_chunks = chunks;
-    B.chunk = chunk;
+    B.total_superchunks = scs;
+    B.superchunk = sc_size;
+    B.chunk = (uint64_t)c->chunk;
     B.seed = c->seed;
-    B.stats = c->stats;
+    B.stats = trial ? c->scratch_stats : c->stats;
     B.counter = c->counter;
+    const int lds = batch_lds_bytes(B);
+    if (lds > 160 * 1024) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
     const int block = c->mixed_block;
-    const int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, block);
-    uint64_t total_hist = 0;
-    for (int i = 0; i < nsims; ++i) total_hist += sims[i].n;
-    uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, (total_hist + block - 1) / block);
+    const int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, block);
+    uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, scs);
     if (grid < 1) grid = 1;
-    hipError_t e = launch_batch(B, (int)grid, block, st);
+    hipError_t e = launch_batch(B, slds, grid_nav, (int)grid, block, st);
     if (e != hipSuccess) return hipfail(c, e, "batch kernel launch");
     HIPCHK(c, hipEventRecord(sl.done, st));
     sl.used = true;
+    return PR_OK;
+}
+
+static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream_t stream, bool trial);
+
+static int validate_sims(pr_ctx* c, const pr_sim* sims, int32_t nsims) {
+    for (int i = 0; i < nsims; ++i) {
+        const pr_sim& sm = sims[i];
+        if (sm.geom < 0 || sm.geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "sims[%d].geom unknown", i);
+        if (sm.src < 0 || sm.src >= (int)c->srcs.size()) return fail(c, PR_ENOTFOUND, "sims[%d].src unknown", i);
+        if (sm.n_tallies < 0 || sm.n_tallies > PR_MAX_TALLIES) return fail(c, PR_EINVAL, "sims[%d].n_tallies out of range", i);
+        if (sm.n > (1ull << 48) || sm.first_history > (1ull << 62)) return fail(c, PR_EINVAL, "sims[%d] history range too large", i);
+        for (int t = 0; t < sm.n_tallies; ++t) {
+            const int tid = sm.tallies[t];
+            if (tid < 0 || tid >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "sims[%d].tallies[%d] unknown", i, t);
+            for (int u = 0; u < t; ++u)
+                if (sm.tallies[u] == tid) return fail(c, PR_EINVAL, "sims[%d] lists tally %d twice", i, tid);
+            const pr_tally_desc& td = c->tallies[tid].desc;
+            if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= c->geoms[sm.geom].nv)
+                return fail(c, PR_EINVAL, "sims[%d]: tally %d trigger_volume beyond its geometry", i, tid);
+        }
+    }
+    return PR_OK;
+}
+
+extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream) {
+    if (!c || !sims) return fail(c, PR_EINVAL, "null argument");
+    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
+    if (precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "batched runs use the PR_FP32_MIXED policy");
+    int rc = set_device(c);
+    if (rc) return rc;
+    if ((rc = validate_sims(c, sims, nsims))) return rc;
+    if ((rc = run_batch_all(c, sims, nsims, (hipStream_t)stream, false))) return rc;
     for (int i = 0; i < nsims; ++i)
         for (int t = 0; t < sims[i].n_tallies; ++t) c->tallies[sims[i].tallies[t]].n_hist += sims[i].n;
     return PR_OK;
+}
+
+// simulations fall into classes by scene placement (LDS or global) and grid
+// navigation; each non-empty class runs as one persistent launch
+static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream_t stream, bool trial) {
+    int rc;
+    std::vector<int> cls(nsims);
+    for (int i = 0; i < nsims; ++i) {
+        const Geometry& g = c->geoms[sims[i].geom];
+        const int sb = batch_scene_lds_bytes(g.nv, g.nm, g.nf, g.nc, (int)g.gf.size(), (int)g.cell_start.size(),
+                                             (int)g.cell_items.size());
+        cls[i] = (sb <= c->lds_scene_budget ? 1 : 0) + (g.gd.empty() ? 0 : 2);
+    }
+    for (int k = 0; k < 4; ++k) {
+        std::vector<int> idx;
+        for (int i = 0; i < nsims; ++i)
+            if (cls[i] == k) idx.push_back(i);
+        if (idx.empty()) continue;
+        if ((rc = run_batch_class(c, sims, idx, (k & 1) != 0, (k & 2) != 0, stream, trial))) return rc;
+    }
+    return PR_OK;
+}
+
+// =========================================================================
+// autotuner
+// =========================================================================
+
+// Time `reps` runs of the sampled workload with the context's current tuning
+// (after one warm-up); returns the fastest, in ms.
+static int trial_ms(pr_ctx* c, const std::vector<pr_sim>& sample, bool batched, hipStream_t st, hipEvent_t e0,
+                    hipEvent_t e1, int reps, float* best) {
+    *best = 1e30f;
+    for (int r = 0; r <= reps; ++r) {
+        HIPCHK(c, hipEventRecord(e0, st));
+        int rc;
+        if (batched) {
+            rc = run_batch_all(c, sample.data(), (int32_t)sample.size(), st, true);
+        } else {
+            const pr_sim& s = sample[0];
+            rc = run_single(c, s.geom, s.src, s.tallies, s.n_tallies, s.first_history, s.n, PR_FP32_MIXED, nullptr,
+                            st, true);
+        }
+        if (rc) return rc;
+        HIPCHK(c, hipEventRecord(e1, st));
+        HIPCHK(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+        if (r > 0 && ms < *best) *best = ms;
+    }
+    return PR_OK;
+}
+
+extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double sample_fraction, pr_tuning* best,
+                           void* stream) {
+    if (!c || !sims || !best) return fail(c, PR_EINVAL, "null argument");
+    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
+    if (!(sample_fraction > 0.0 && sample_fraction <= 1.0)) return fail(c, PR_EINVAL, "sample_fraction must be in (0, 1]");
+    int rc = set_device(c);
+    if (rc) return rc;
+    if ((rc = validate_sims(c, sims, nsims))) return rc;
+    const bool batched = nsims > 1;
+    std::vector<pr_sim> sample(sims, sims + nsims);
+    uint64_t maxbins = 1;
+    for (auto& s : sample) {
+        s.n = std::max<uint64_t>(1, (uint64_t)std::llround((double)s.n * sample_fraction));
+        for (int t = 0; t < s.n_tallies; ++t) maxbins = std::max(maxbins, c->tallies[s.tallies[t]].nbins);
+    }
+    if (c->scratch_bins < maxbins) {
+        if (c->scratch) (void)hipFree(c->scratch);
+        c->scratch = nullptr;
+        c->scratch_bins = 0;
+        HIPCHK(c, hipMalloc((void**)&c->scratch, 2 * maxbins * sizeof(double)));
+        c->scratch_bins = maxbins;
+    }
+    if (!c->scratch_stats) HIPCHK(c, hipMalloc((void**)&c->scratch_stats, ST_N * sizeof(unsigned long long)));
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    // coordinate descent over the launch parameters, two passes
+    struct Knob {
+        int* field;
+        std::vector<int> values;
+    };
+    std::vector<Knob> knobs = {
+        {&c->refill_threshold, {4, 8, 16, 24, 32, 48}},
+        {&c->chunk, {64, 128, 256, 512, 1024}},
+        {&c->mixed_blocks_per_cu, {0, 2, 3}},
+        {&c->bin_cache_slots, {256, 1024, 2048}},
+    };
+    if (batched) knobs.push_back({&c->superchunk, {512, 1024, 2048, 4096, 8192}});
+    float cur = 0.f;
+    rc = trial_ms(c, sample, batched, st, e0, e1, 2, &cur);
+    for (int pass = 0; pass < 2 && rc == PR_OK; ++pass) {
+        for (auto& k : knobs) {
+            const int keep = *k.field;
+            int bestv = keep;
+            float bestt = cur;
+            for (int v : k.values) {
+                if (v == keep) continue;
+                *k.field = v;
+                float t = 0.f;
+                if ((rc = trial_ms(c, sample, batched, st, e0, e1, 2, &t))) break;
+                if (t < bestt * 0.98f) {
+                    bestt = t;
+                    bestv = v;
+                }
+            }
+            *k.field = bestv;
+            cur = bestt;
+            if (rc) break;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    return pr_get_tuning(c, best);
 }

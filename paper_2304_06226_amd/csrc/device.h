@@ -116,6 +116,8 @@ struct Params {
     int32_t n_vols, n_mats, n_fams, n_children;
     int32_t n_grids, n_cell_start, n_cell_items;
     int32_t scene_in_lds;          // mixed policy: stage the FP32 scene into LDS (else read it from global memory)
+    int32_t has_grid;              // some volume navigates its daughters through a grid
+    int32_t pad2;
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
     int32_t cache_slots;           // LDS bin-cache slots over all cached tallies (mixed policy)
@@ -129,20 +131,14 @@ struct Params {
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
 };
 
-// Batched runs: many simulations (each its own world volume, source and
-// tallies) in one launch.  Their scenes are concatenated (indices rebased) and
-// the history indices of all simulations form one chunk space.
+// Batched runs: many simulations (each its own geometry, source and tallies)
+// in one launch.  A block works on one simulation at a time: it claims a
+// super-chunk of that simulation's histories, stages the simulation's FP32
+// scene and tallies into LDS (when they fit) and hands sub-chunks to its
+// waves through an LDS counter; it flushes and restages only when the next
+// super-chunk belongs to another simulation.
 struct SimDev {
-    int32_t root;                  // world volume of this simulation in the batch scene
-    int32_t tally_begin, tally_count;
-    int32_t pad;
-    uint64_t first;                // history id of the simulation's first history
-    uint64_t n;                    // histories
-    uint64_t chunk_begin;          // first chunk of this simulation in the batch chunk space
-    SourceDev src;
-};
-
-struct BatchParams {
+    // the simulation's own FP32 scene (local indices; world = volume 0)
     const VolT<float>* vols;
     const MatT<float>* mats;
     const FamT<float>* fams;
@@ -150,13 +146,27 @@ struct BatchParams {
     const GridT<float>* grids;
     const int32_t* cell_start;
     const int32_t* cell_items;
+    int32_t n_vols, n_mats, n_fams, n_children, n_grids, n_cell_start, n_cell_items;
+    int32_t scene_in_lds;          // stage the scene into LDS (else read it from global memory)
+    int32_t tally_begin, tally_count;
+    int32_t privatised;            // 1: tallies privatised in LDS at TallyDev::lds_offset; 0: LDS bin cache
+    int32_t pad;
+    uint64_t first;                // history id of the simulation's first history
+    uint64_t n;                    // histories
+    uint64_t sc_begin;             // first super-chunk of this simulation
+    SourceDev src;
+};
+
+struct BatchParams {
     const SimDev* sims;
-    const TallyDev* tallies;       // all tallies of the batch
-    const uint64_t* tally_key_base;   // prefix sums of tally bins: bin-cache key = base + bin
+    const TallyDev* tallies;          // per-simulation tally entries
+    const uint64_t* tally_key_base;   // per entry: bin-cache key base within its simulation
     int32_t nsims, ntallies;
-    int32_t cache_bits;            // LDS bin cache of 2^cache_bits slots (0 = none)
+    int32_t lds_tally_doubles;        // LDS tally region (privatised tallies, or bin-cache values)
+    int32_t cache_bits;               // bin cache of 2^cache_bits slots (values in the tally region)
+    int32_t lds_scene_bytes;          // LDS scene region
     int32_t refill_threshold;
-    uint64_t total_chunks, chunk, seed;
+    uint64_t total_superchunks, superchunk, chunk, seed;
     unsigned long long* stats;
     unsigned long long* counter;
 };
@@ -585,14 +595,14 @@ __device__ __forceinline__ R reflectivity(const VolT<R>& V, R Q) {
 }
 
 // innermost volume containing p below the world volume `root`, -1 outside it
-template <class R>
+template <class R, bool GRID>
 __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root) {
     if (!contains<R>(S.vols[root], p)) return -1;
     int cur = root;
     for (int depth = 0; depth < 64; ++depth) {
         const VolT<R>& V = S.vols[cur];
         int next = -1;
-        if (V.grid >= 0) {
+        if (GRID && V.grid >= 0) {
             // only the daughters listed in the grid cell holding p can contain it
             const GridT<R>& G = S.grids[V.grid];
             bool in = true;
@@ -627,7 +637,7 @@ __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root
 // Source
 // -------------------------------------------------------------------------
 
-template <class R, bool REC>
+template <class R, bool REC, bool GRID>
 __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h,
                                        int root) {
     s.h = h;
@@ -677,7 +687,7 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
         s.u[i] = u[i];
     }
     s.lam = lam;
-    s.region = locate<R>(S, s.p, root);
+    s.region = locate<R, GRID>(S, s.p, root);
     hash_ev<REC>(s.hash, EV_SOURCE, s.region);
     if (s.region < 0) s.term = PR_END_OUTSIDE;
 }
@@ -779,7 +789,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 // One step of the history loop
 // -------------------------------------------------------------------------
 
-template <class R, bool REC>
+template <class R, bool REC, bool GRID>
 __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
     if (s.steps >= kMaxSteps) {
         s.term = PR_END_CAPPED;
@@ -799,7 +809,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
     R d_child = rinf<R>();
     int child = -1;
-    if (V.grid >= 0) {
+    if (GRID && V.grid >= 0) {
         grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child);
     } else {
         for (int ci = 0; ci < V.child_count; ++ci) {

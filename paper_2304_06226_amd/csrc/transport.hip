@@ -60,15 +60,15 @@ __device__ __forceinline__ void flush_counters(const Counters& k, unsigned long 
 // FP64 plain
 // ------------------------------------------------------------------------
 
-template <bool REC>
+template <bool REC, bool GRID>
 __global__ __launch_bounds__(256) void k_plain(Params P) {
     const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items};
     Counters cnt = {};
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < P.n) {
         PState<double> s;
-        source<double, REC>(s, P.src, S, P.seed, P.first + i, 0);
-        while (s.term == 0) step<double, REC>(s, S, P.seed);
+        source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
+        while (s.term == 0) step<double, REC, GRID>(s, S, P.seed);
         if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
@@ -165,7 +165,7 @@ __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes
     for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) d[i] = s[i];
 }
 
-template <bool REC, bool SLDS>
+template <bool REC, bool SLDS, bool GRID>
 __global__ __launch_bounds__(256) void k_mixed(Params P) {
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<float, REC>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0);
+                        source<float, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0);
                         pending = s.term != 0;   // born outside the world: counted at the next refill
                     }
                 }
@@ -248,7 +248,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
             continue;
         }
         if (s.term == 0) {
-            step<float, REC>(s, S, P.seed);
+            step<float, REC, GRID>(s, S, P.seed);
             pending = s.term != 0;
         }
     }
@@ -284,19 +284,61 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
 // Batched FP32 mixed: many simulations in one persistent launch
 // ------------------------------------------------------------------------
 
-// tally whose key range [base[t], base[t+1]) holds key
-__device__ __forceinline__ int tally_of_key(const uint64_t* base, int nt, uint64_t key) {
-    int lo = 0, hi = nt - 1;
+// LDS of a batch block: [tally region (doubles): privatised tallies of the
+// staged simulation, or bin-cache values] [bin-cache keys] [staged scene]
+struct SceneLds {
+    int vols, mats, fams, children, grids, cell_start, cell_items, bytes;
+};
+
+__host__ __device__ inline SceneLds scene_lds_layout(int nv, int nm, int nf, int nc, int ng, int ncs, int nci) {
+    SceneLds L;
+    int off = 0;
+    L.vols = off;
+    off = align16(off + nv * (int)sizeof(VolT<float>));
+    L.mats = off;
+    off = align16(off + nm * (int)sizeof(MatT<float>));
+    L.fams = off;
+    off = align16(off + nf * (int)sizeof(FamT<float>));
+    L.children = off;
+    off = align16(off + nc * 4);
+    L.grids = off;
+    off = align16(off + ng * (int)sizeof(GridT<float>));
+    L.cell_start = off;
+    off = align16(off + ncs * 4);
+    L.cell_items = off;
+    off = align16(off + nci * 4);
+    L.bytes = off;
+    return L;
+}
+
+int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci) {
+    return scene_lds_layout(nv, nm, nf, nc, ng, ncs, nci).bytes;
+}
+
+struct BlockCtl {
+    unsigned long long next;   // sub-chunk counter within the current super-chunk
+    unsigned long long end;    // end of the current super-chunk (local history index)
+    unsigned long long sc;     // current super-chunk (>= total: no more work)
+    int sim;
+};
+
+__device__ __forceinline__ int sim_of_superchunk(const BatchParams& B, unsigned long long j) {
+    int lo = 0, hi = B.nsims - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (base[mid] <= key) lo = mid; else hi = mid - 1;
+        if (B.sims[mid].sc_begin <= j) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
 
-__device__ __forceinline__ void score_batch(const BatchParams& B, int t, int64_t b, double w, double* cvals,
-                                            uint32_t* ckeys) {
+__device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& sd, int t, int64_t b, double w,
+                                            double* ltal, uint32_t* ckeys) {
     const TallyDev& T = B.tallies[t];
+    if (sd.privatised) {
+        atomicAdd(ltal + T.lds_offset + b, w);
+        atomicAdd(ltal + T.lds_offset + T.total + b, w * w);
+        return;
+    }
     const uint64_t key64 = B.tally_key_base[t] + (uint64_t)b;
     if (B.cache_bits > 0 && key64 < (uint64_t)kEmptyKey) {
         const uint32_t key = (uint32_t)key64;
@@ -311,8 +353,8 @@ __device__ __forceinline__ void score_batch(const BatchParams& B, int t, int64_t
                 if (k == kEmptyKey) k = key;
             }
             if (k == key) {
-                atomicAdd(cvals + 2 * slot, w);
-                atomicAdd(cvals + 2 * slot + 1, w * w);
+                atomicAdd(ltal + 2 * slot, w);
+                atomicAdd(ltal + 2 * slot + 1, w * w);
                 return;
             }
         }
@@ -321,25 +363,58 @@ __device__ __forceinline__ void score_batch(const BatchParams& B, int t, int64_t
     atomicAdd(T.sw2 + b, w * w);
 }
 
-__global__ __launch_bounds__(256) void k_batch(BatchParams B) {
-    extern __shared__ double lds[];
-    const int nslots = B.cache_bits > 0 ? (1 << B.cache_bits) : 0;
-    double* cvals = lds;
-    uint32_t* ckeys = (uint32_t*)(lds + 2 * nslots);
-    for (int i = threadIdx.x; i < 2 * nslots; i += blockDim.x) cvals[i] = 0.0;
-    for (int i = threadIdx.x; i < nslots; i += blockDim.x) ckeys[i] = kEmptyKey;
-    __syncthreads();
-    const SceneT<float> S{B.vols, B.mats, B.fams, B.children, B.grids, B.cell_start, B.cell_items};
+// merge the staged simulation's LDS tallies into global memory (whole block)
+__device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& sd, const double* ltal,
+                                            const uint32_t* ckeys) {
+    if (sd.privatised) {
+        for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
+            const TallyDev& T = B.tallies[t];
+            for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
+                const double a = ltal[T.lds_offset + i], b = ltal[T.lds_offset + T.total + i];
+                if (a != 0.0 || b != 0.0) {
+                    atomicAdd(T.sw + i, a);
+                    atomicAdd(T.sw2 + i, b);
+                }
+            }
+        }
+    } else if (B.cache_bits > 0) {
+        const int nslots = 1 << B.cache_bits;
+        for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
+            const uint32_t key = ckeys[i];
+            if (key == kEmptyKey) continue;
+            int t = sd.tally_begin;
+            while (t + 1 < sd.tally_begin + sd.tally_count && B.tally_key_base[t + 1] <= key) ++t;
+            const TallyDev& T = B.tallies[t];
+            const uint64_t b = key - B.tally_key_base[t];
+            atomicAdd(T.sw + b, ltal[2 * i]);
+            atomicAdd(T.sw2 + b, ltal[2 * i + 1]);
+        }
+    }
+}
 
-    Counters cnt = {};
+// the block's waves run the histories of the current super-chunk
+template <bool SLDS, bool GRID>
+__device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDev& sd, BlockCtl& ctl, char* scene,
+                                               double* ltal, uint32_t* ckeys, Counters& cnt) {
+    SceneT<float> S;
+    if (SLDS) {
+        const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
+                                            sd.n_cell_start, sd.n_cell_items);
+        S = SceneT<float>{(const VolT<float>*)(scene + L.vols), (const MatT<float>*)(scene + L.mats),
+                          (const FamT<float>*)(scene + L.fams), (const int32_t*)(scene + L.children),
+                          (const GridT<float>*)(scene + L.grids), (const int32_t*)(scene + L.cell_start),
+                          (const int32_t*)(scene + L.cell_items)};
+    } else {
+        S = SceneT<float>{sd.vols, sd.mats, sd.fams, sd.children, sd.grids, sd.cell_start, sd.cell_items};
+    }
     PState<float> s;
     s.term = 1;
-    int sim = 0;            // simulation of this lane's history
     bool pending = false;
     bool exhausted = false;
-    // wave-uniform: the claimed chunk's simulation and its local history range
-    int csim = 0;
     unsigned long long cnext = 0, cend = 0;
+    const unsigned long long end =
+        ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ctl.end >> 32)) << 32) |
+        (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ctl.end);
     const int lane = lane_id();
     for (;;) {
         const bool idle = s.term != 0;
@@ -348,10 +423,9 @@ __global__ __launch_bounds__(256) void k_batch(BatchParams B) {
         if (n_idle >= B.refill_threshold || n_idle == kWave) {
             if (pending) {
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
-                    const SimDev& sd = B.sims[sim];
                     for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
                         int64_t b = tally_bin<float>(B.tallies[t], s);
-                        if (b >= 0) score_batch(B, t, b, s.w, cvals, ckeys);
+                        if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
                     }
                 }
                 count_end<float>(cnt, s);
@@ -360,21 +434,13 @@ __global__ __launch_bounds__(256) void k_batch(BatchParams B) {
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
                 unsigned long long got = 0;
-                if (lane == leader) got = atomicAdd(B.counter, 1ull);
+                if (lane == leader) got = atomicAdd(&ctl.next, B.chunk);
                 got = __shfl(got, leader, kWave);
-                if (got >= B.total_chunks) {
+                if (got >= end) {
                     exhausted = true;
                 } else {
-                    // simulation owning chunk `got`: last with chunk_begin <= got
-                    int lo = 0, hi = B.nsims - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (B.sims[mid].chunk_begin <= got) lo = mid; else hi = mid - 1;
-                    }
-                    csim = lo;
-                    const unsigned long long l0 = (got - B.sims[lo].chunk_begin) * B.chunk;
-                    cnext = l0;
-                    cend = l0 + B.chunk < B.sims[lo].n ? l0 + B.chunk : B.sims[lo].n;
+                    cnext = got;
+                    cend = got + B.chunk < end ? got + B.chunk : end;
                 }
             }
             if (!exhausted && cnext < cend) {
@@ -384,9 +450,7 @@ __global__ __launch_bounds__(256) void k_batch(BatchParams B) {
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        const SimDev& sd = B.sims[csim];
-                        sim = csim;
-                        source<float, false>(s, sd.src, S, B.seed, sd.first + cnext + (unsigned long long)rank, sd.root);
+                        source<float, false, GRID>(s, sd.src, S, B.seed, sd.first + cnext + (unsigned long long)rank, 0);
                         pending = s.term != 0;
                     }
                 }
@@ -398,21 +462,67 @@ __global__ __launch_bounds__(256) void k_batch(BatchParams B) {
             continue;
         }
         if (s.term == 0) {
-            step<float, false>(s, S, B.seed);
+            step<float, false, GRID>(s, S, B.seed);
             pending = s.term != 0;
         }
     }
-    flush_counters(cnt, B.stats);
-    __syncthreads();
-    for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
-        const uint32_t key = ckeys[i];
-        if (key == kEmptyKey) continue;
-        const int t = tally_of_key(B.tally_key_base, B.ntallies, key);
-        const TallyDev& T = B.tallies[t];
-        const uint64_t b = key - B.tally_key_base[t];
-        atomicAdd(T.sw + b, cvals[2 * i]);
-        atomicAdd(T.sw2 + b, cvals[2 * i + 1]);
+}
+
+template <bool SLDS, bool GRID>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 4, 8))) void k_batch(BatchParams B) {
+    extern __shared__ double lds[];
+    __shared__ BlockCtl ctl;
+    double* ltal = lds;
+    const int nslots = B.cache_bits > 0 ? (1 << B.cache_bits) : 0;
+    uint32_t* ckeys = (uint32_t*)(lds + B.lds_tally_doubles);
+    char* scene = (char*)ckeys + align16(nslots * 4);
+    Counters cnt = {};
+    int staged = -1;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const unsigned long long j = atomicAdd(B.counter, 1ull);
+            ctl.sc = j;
+            if (j < B.total_superchunks) {
+                const int sim = sim_of_superchunk(B, j);
+                const SimDev& sd = B.sims[sim];
+                const unsigned long long a = (j - sd.sc_begin) * B.superchunk;
+                ctl.sim = sim;
+                ctl.next = a;
+                ctl.end = a + B.superchunk < sd.n ? a + B.superchunk : sd.n;
+            }
+        }
+        __syncthreads();
+        if (ctl.sc >= B.total_superchunks) break;
+        // block-uniform: read once into scalar registers so the simulation's
+        // descriptor is fetched with scalar loads
+        const int sim = __builtin_amdgcn_readfirstlane(ctl.sim);
+        const SimDev& sd = B.sims[sim];
+        if (sim != staged) {
+            if (staged >= 0) {
+                flush_block(B, B.sims[staged], ltal, ckeys);
+                __syncthreads();
+            }
+            for (int i = threadIdx.x; i < B.lds_tally_doubles; i += blockDim.x) ltal[i] = 0.0;
+            for (int i = threadIdx.x; i < nslots; i += blockDim.x) ckeys[i] = kEmptyKey;
+            if (SLDS) {
+                const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
+                                                    sd.n_cell_start, sd.n_cell_items);
+                copy_words(scene + L.vols, sd.vols, sd.n_vols * (int)sizeof(VolT<float>));
+                copy_words(scene + L.mats, sd.mats, sd.n_mats * (int)sizeof(MatT<float>));
+                copy_words(scene + L.fams, sd.fams, sd.n_fams * (int)sizeof(FamT<float>));
+                copy_words(scene + L.children, sd.children, sd.n_children * 4);
+                copy_words(scene + L.grids, sd.grids, sd.n_grids * (int)sizeof(GridT<float>));
+                copy_words(scene + L.cell_start, sd.cell_start, sd.n_cell_start * 4);
+                copy_words(scene + L.cell_items, sd.cell_items, sd.n_cell_items * 4);
+            }
+            __syncthreads();
+            staged = sim;
+        }
+        run_superchunk<SLDS, GRID>(B, sd, ctl, scene, ltal, ckeys, cnt);
+        __syncthreads();
     }
+    if (staged >= 0) flush_block(B, B.sims[staged], ltal, ckeys);
+    flush_counters(cnt, B.stats);
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -435,54 +545,84 @@ int mixed_lds_bytes(const Params& P) { return lds_layout(P).bytes; }
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     if (P.n == 0) return hipSuccess;
     const int block = 256;
-    uint64_t grid = (P.n + block - 1) / block;
-    if (rec)
-        hipLaunchKernelGGL(k_plain<true>, dim3((unsigned)grid), dim3(block), 0, st, P);
-    else
-        hipLaunchKernelGGL(k_plain<false>, dim3((unsigned)grid), dim3(block), 0, st, P);
+    const dim3 grid((unsigned)((P.n + block - 1) / block));
+    if (P.has_grid) {
+        if (rec) hipLaunchKernelGGL((k_plain<true, true>), grid, dim3(block), 0, st, P);
+        else hipLaunchKernelGGL((k_plain<false, true>), grid, dim3(block), 0, st, P);
+    } else {
+        if (rec) hipLaunchKernelGGL((k_plain<true, false>), grid, dim3(block), 0, st, P);
+        else hipLaunchKernelGGL((k_plain<false, false>), grid, dim3(block), 0, st, P);
+    }
     return hipGetLastError();
+}
+
+template <bool REC>
+static void launch_mixed_t(const Params& P, int grid, int block, int lds, hipStream_t st) {
+    const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_mixed<REC, false, false>), dim3(grid), dim3(block), lds, st, P); break;
+    case 1: hipLaunchKernelGGL((k_mixed<REC, true, false>), dim3(grid), dim3(block), lds, st, P); break;
+    case 2: hipLaunchKernelGGL((k_mixed<REC, false, true>), dim3(grid), dim3(block), lds, st, P); break;
+    default: hipLaunchKernelGGL((k_mixed<REC, true, true>), dim3(grid), dim3(block), lds, st, P); break;
+    }
 }
 
 hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStream_t st) {
     if (P.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.counter, 1);
-    int lds = mixed_lds_bytes(P);
-    if (P.scene_in_lds) {
-        if (rec)
-            hipLaunchKernelGGL((k_mixed<true, true>), dim3(grid), dim3(block), lds, st, P);
-        else
-            hipLaunchKernelGGL((k_mixed<false, true>), dim3(grid), dim3(block), lds, st, P);
-    } else {
-        if (rec)
-            hipLaunchKernelGGL((k_mixed<true, false>), dim3(grid), dim3(block), lds, st, P);
-        else
-            hipLaunchKernelGGL((k_mixed<false, false>), dim3(grid), dim3(block), lds, st, P);
-    }
+    const int lds = mixed_lds_bytes(P);
+    if (rec) launch_mixed_t<true>(P, grid, block, lds, st);
+    else launch_mixed_t<false>(P, grid, block, lds, st);
     return hipGetLastError();
 }
 
 int mixed_occupancy(const Params& P, int block) {
     int nb = 0;
-    int lds = mixed_lds_bytes(P);
-    hipError_t e = P.scene_in_lds
-                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true>, block, lds)
-                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false>, block, lds);
+    const int lds = mixed_lds_bytes(P);
+    const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0);
+    hipError_t e;
+    switch (v) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false>, block, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false>, block, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, true>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, true>, block, lds); break;
+    }
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 
-int batch_lds_bytes(const BatchParams& B) { return B.cache_bits > 0 ? (1 << B.cache_bits) * 20 : 0; }
+int batch_lds_bytes(const BatchParams& B) {
+    const int nslots = B.cache_bits > 0 ? (1 << B.cache_bits) : 0;
+    return B.lds_tally_doubles * 8 + align16(nslots * 4) + B.lds_scene_bytes;
+}
 
-hipError_t launch_batch(const BatchParams& B, int grid, int block, hipStream_t st) {
-    if (B.total_chunks == 0) return hipSuccess;
+// one persistent launch per (scene placement, grid) class of simulations
+hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid, int block, hipStream_t st) {
+    if (B.total_superchunks == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, B.counter, 1);
-    hipLaunchKernelGGL(k_batch, dim3(grid), dim3(block), batch_lds_bytes(B), st, B);
+    const int lds = batch_lds_bytes(B);
+    const int v = (slds ? 1 : 0) + (grid_nav ? 2 : 0);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_batch<false, false>), dim3(grid), dim3(block), lds, st, B); break;
+    case 1: hipLaunchKernelGGL((k_batch<true, false>), dim3(grid), dim3(block), lds, st, B); break;
+    case 2: hipLaunchKernelGGL((k_batch<false, true>), dim3(grid), dim3(block), lds, st, B); break;
+    default: hipLaunchKernelGGL((k_batch<true, true>), dim3(grid), dim3(block), lds, st, B); break;
+    }
     return hipGetLastError();
 }
 
-int batch_occupancy(const BatchParams& B, int block) {
+int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch, block, batch_lds_bytes(B)) != hipSuccess) return 1;
+    const int lds = batch_lds_bytes(B);
+    const int v = (slds ? 1 : 0) + (grid_nav ? 2 : 0);
+    hipError_t e;
+    switch (v) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, false>, block, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, false>, block, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, true>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, true>, block, lds); break;
+    }
+    if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
 

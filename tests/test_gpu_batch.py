@@ -128,3 +128,30 @@ def test_batch_tuning_and_validation(ctx):
         ctx.run_batch([(0, 0, [0], 0, 10)], precision="fp64")
     with pytest.raises(B.PromptError):
         ctx.run_batch([(999, 0, [], 0, 10)])
+
+
+def test_autotune_leaves_tallies_untouched(ctx):
+    import torch
+    batch = W.config4(scale=0.003, imaging_histories=20_000, n_sims=8)
+    br = B.BatchRun(ctx, batch)
+    br.run()
+    torch.cuda.synchronize()
+    before = [s.results() for s in br.sims]
+    st_before = ctx.read_stats()
+    base = ctx.get_tuning()
+    try:
+        best = ctx.autotune(br.descriptors(), sample_fraction=0.5)
+        assert best == ctx.get_tuning()
+        assert best["refill_threshold"] >= 1 and best["chunk"] >= 1 and best["superchunk"] >= 1
+        single = br.sims[0]
+        best1 = ctx.autotune([(single.geom, single.src, single.tallies, 0, 20_000)], sample_fraction=1.0)
+        assert best1["chunk"] >= 1
+    finally:
+        ctx.set_tuning(**base)
+    torch.cuda.synchronize()
+    after = [s.results() for s in br.sims]
+    assert ctx.read_stats() == st_before
+    for a, b in zip(before, after):
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+            assert nh == rn
+            assert np.array_equal(sw, rw) and np.array_equal(sw2, rw2)
