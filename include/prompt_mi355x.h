@@ -203,7 +203,9 @@ int pr_create_material(pr_ctx* ctx, const pr_material_desc* desc, int32_t* id);
 /* n volumes, volume 0 the world; validates kinds, sizes, tree and overlaps. */
 int pr_create_geometry(pr_ctx* ctx, const pr_volume_desc* volumes, int32_t n, int32_t* id);
 int pr_create_source(pr_ctx* ctx, const pr_source_desc* desc, int32_t* id);
-/* allocates and zeroes the tally's device storage (2 x nbins doubles) */
+/* allocates and zeroes the tally's device storage: 2 x nbins doubles, (sum w,
+ * sum w^2) interleaved per bin so that the two atomics of a score update one
+ * 16-byte pair; pr_read_tally returns them as separate arrays */
 int pr_create_tally(pr_ctx* ctx, const pr_tally_desc* desc, int32_t* id);
 int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
 

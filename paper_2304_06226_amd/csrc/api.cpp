@@ -778,7 +778,7 @@ static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
     double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
     for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
     o.sw = T.dev;
-    o.sw2 = T.dev ? T.dev + T.nbins : nullptr;
+    o.sw2 = T.dev ? T.dev + 1 : nullptr;
     o.total = (int64_t)T.nbins;
     o.lds_offset = -1;
     o.cache_base = -1;
@@ -861,7 +861,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
         for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
         o.sw = T.dev;
-        o.sw2 = T.dev ? T.dev + T.nbins : nullptr;
+        o.sw2 = T.dev ? T.dev + 1 : nullptr;
         o.total = (int64_t)T.nbins;
         o.lds_offset = -1;
         o.cache_base = -1;
@@ -907,7 +907,7 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
     if (trial) {
         for (int i = 0; i < nt; ++i) {
             P.tallies[i].sw = c->scratch;
-            P.tallies[i].sw2 = c->scratch + c->scratch_bins;
+            P.tallies[i].sw2 = c->scratch + 1;
         }
         P.stats = c->scratch_stats;
     }
@@ -951,8 +951,22 @@ extern "C" int pr_read_tally_range(pr_ctx* c, int32_t tally, uint64_t offset, ui
     if (rc) return rc;
     HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
     if (count == 0) return PR_OK;
-    if (sw) HIPCHK(c, hipMemcpy(sw, T.dev + offset, count * sizeof(double), hipMemcpyDeviceToHost));
-    if (sw2) HIPCHK(c, hipMemcpy(sw2, T.dev + T.nbins + offset, count * sizeof(double), hipMemcpyDeviceToHost));
+    // device layout is (sum w, sum w^2) interleaved per bin: copy in slices and split
+    const uint64_t slice = 1ull << 22;
+    std::vector<double> tmp;
+    try {
+        tmp.resize(2 * std::min(slice, count));
+    } catch (...) {
+        return fail(c, PR_ENOMEM, "host buffer for tally readback");
+    }
+    for (uint64_t done = 0; done < count; done += slice) {
+        const uint64_t m = std::min(slice, count - done);
+        HIPCHK(c, hipMemcpy(tmp.data(), T.dev + 2 * (offset + done), 2 * m * sizeof(double), hipMemcpyDeviceToHost));
+        for (uint64_t i = 0; i < m; ++i) {
+            if (sw) sw[done + i] = tmp[2 * i];
+            if (sw2) sw2[done + i] = tmp[2 * i + 1];
+        }
+    }
     return PR_OK;
 }
 
@@ -1103,7 +1117,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
             make_tally_dev(c->tallies[sm.tallies[t]], 0, T);
             if (trial) {   // autotuner trials score into scratch, never into the caller's tallies
                 T.sw = c->scratch;
-                T.sw2 = c->scratch + c->scratch_bins;
+                T.sw2 = c->scratch + 1;
             }
             if (o.privatised) {
                 T.lds_offset = (int32_t)loff;

@@ -93,8 +93,8 @@ struct TallyDev {
     int32_t nbins[4];
     double lo[4], hi[4], scale[4];   // scale = nbins / (hi - lo)
     double beam[3];                  // unit vector
-    double* sw;
-    double* sw2;
+    double* sw;      // device storage: (sum w, sum w^2) interleaved per bin
+    double* sw2;     // = sw + 1
     int64_t total;
 };
 

@@ -56,6 +56,13 @@ __device__ __forceinline__ void flush_counters(const Counters& k, unsigned long 
     }
 }
 
+// Global tallies store (sum w, sum w^2) interleaved per bin, so the two atomics
+// of a score update the same 16-byte pair (one memory-side line, not two).
+__device__ __forceinline__ void add_global(const TallyDev& T, int64_t b, double w, double w2) {
+    atomicAdd(T.sw + 2 * b, w);
+    atomicAdd(T.sw + 2 * b + 1, w2);
+}
+
 // ------------------------------------------------------------------------
 // FP64 plain
 // ------------------------------------------------------------------------
@@ -74,8 +81,7 @@ __global__ __launch_bounds__(256) void k_plain(Params P) {
                 const TallyDev& T = P.tallies[t];
                 int64_t b = tally_bin<double>(T, s);
                 if (b >= 0) {
-                    atomicAdd(T.sw + b, s.w);
-                    atomicAdd(T.sw2 + b, s.w * s.w);
+                    add_global(T, b, s.w, s.w * s.w);
                 }
             }
         }
@@ -155,8 +161,7 @@ __device__ __forceinline__ void score_mixed(const TallyDev& T, int64_t b, double
             }
         }
     }
-    atomicAdd(T.sw + b, w);
-    atomicAdd(T.sw2 + b, w * w);
+    add_global(T, b, w, w * w);
 }
 
 __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes) {
@@ -263,8 +268,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
                 const int slot = T.cache_base + i;
                 const uint32_t key = ckeys[slot];
                 if (key != kEmptyKey) {
-                    atomicAdd(T.sw + key, cvals[2 * slot]);
-                    atomicAdd(T.sw2 + key, cvals[2 * slot + 1]);
+                    add_global(T, key, cvals[2 * slot], cvals[2 * slot + 1]);
                 }
             }
         }
@@ -273,8 +277,7 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
             double a = lds[T.lds_offset + i];
             double b = lds[T.lds_offset + T.total + i];
             if (a != 0.0 || b != 0.0) {
-                atomicAdd(T.sw + i, a);
-                atomicAdd(T.sw2 + i, b);
+                add_global(T, i, a, b);
             }
         }
     }
@@ -359,8 +362,7 @@ __device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& 
             }
         }
     }
-    atomicAdd(T.sw + b, w);
-    atomicAdd(T.sw2 + b, w * w);
+    add_global(T, b, w, w * w);
 }
 
 // merge the staged simulation's LDS tallies into global memory (whole block)
@@ -372,8 +374,7 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
             for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
                 const double a = ltal[T.lds_offset + i], b = ltal[T.lds_offset + T.total + i];
                 if (a != 0.0 || b != 0.0) {
-                    atomicAdd(T.sw + i, a);
-                    atomicAdd(T.sw2 + i, b);
+                    add_global(T, i, a, b);
                 }
             }
         }
@@ -386,8 +387,7 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
             while (t + 1 < sd.tally_begin + sd.tally_count && B.tally_key_base[t + 1] <= key) ++t;
             const TallyDev& T = B.tallies[t];
             const uint64_t b = key - B.tally_key_base[t];
-            atomicAdd(T.sw + b, ltal[2 * i]);
-            atomicAdd(T.sw2 + b, ltal[2 * i + 1]);
+            add_global(T, b, ltal[2 * i], ltal[2 * i + 1]);
         }
     }
 }

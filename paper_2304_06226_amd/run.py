@@ -1,0 +1,70 @@
+"""Run a named workload through the GPU library and print one JSON line of timings.
+
+    python -m paper_2304_06226_amd.run --workload guide --histories 1e8 --precision fp32 --repeat 3
+
+Workloads: sample (biased powder sample), vessel, guide, imaging, batch
+(the 256-simulation + imaging batch; always FP32-mixed).  One warm-up run,
+then `repeat` timed runs on disjoint history ranges (HIP events on the current
+stream).  Useful under rocprofv3 to profile one workload's kernels.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["sample", "vessel", "guide", "imaging", "batch"], default="sample")
+    ap.add_argument("--histories", type=float, default=None)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--repeat", type=int, default=3)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args(argv)
+
+    import torch
+    from . import binding as B
+    from . import workloads as W
+
+    torch.cuda.set_device(0)
+    ctx = B.Context(0, seed=W.RUN_SEED)
+    if args.workload == "batch":
+        batch = W.config4()
+        br = B.BatchRun(ctx, batch)
+        n = batch.total_histories
+        if args.autotune:
+            ctx.autotune(br.descriptors(), sample_fraction=0.05)
+
+        def go(k):
+            br.run(shift=k * br.span)
+    else:
+        prob = {"sample": W.config1, "vessel": W.config2, "guide": W.config3, "imaging": W.imaging_problem}[args.workload]()
+        n = int(args.histories) if args.histories else prob.n_histories
+        sim = B.Simulation(ctx, prob)
+        if args.autotune and args.precision == "fp32":
+            ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=0.2)
+
+        def go(k):
+            sim.run(first=k * n, n=n, precision=args.precision)
+    go(0)
+    torch.cuda.synchronize()
+    ctx.reset_stats()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(args.repeat):
+        go(k + 1)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / args.repeat
+    st = ctx.read_stats()
+    out = {"workload": args.workload, "precision": args.precision if args.workload != "batch" else "fp32",
+           "histories": n, "ms": ms, "histories_per_s": n / ms * 1e3,
+           "steps_per_history": st["steps"] / max(1, st["histories"]), "tuning": ctx.get_tuning()}
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    sys.exit(main())
