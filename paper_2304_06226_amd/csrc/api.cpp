@@ -40,6 +40,7 @@ struct Geometry {
     std::vector<GridT<double>> gd;
     std::vector<GridT<float>> gf;
     int nv = 0, nm = 0, nf = 0, nc = 0;
+    uint32_t kinds = 0;   // bit k: some volume has solid kind k
     void* vols_d = nullptr;
     void* mats_d = nullptr;
     void* fams_d = nullptr;
@@ -342,7 +343,7 @@ void build_grid(const pr_volume_desc* vols, const std::vector<int32_t>& kids, Ge
     g.vf[v].grid = g.vd[v].grid;
 }
 
-constexpr int kGridMinDaughters = 8;
+constexpr int kGridMinDaughters = 8;   // at most 7 daughters are scanned as step candidates
 
 int set_device(pr_ctx* c) {
     if (c->device < 0) return fail(c, PR_EDEVICE, "context has no device (created with hip_device = -1)");
@@ -630,6 +631,17 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
     g.children = std::move(children);
     for (int i = 0; i < n; ++i)
         if ((int)kids[i].size() >= kGridMinDaughters) build_grid(vols, kids[i], g, i);
+    // boundary candidates per solid kind: the volume itself (bit 0) and, unless a
+    // grid serves them, its daughters (bits 1..7; fewer than kGridMinDaughters)
+    for (int i = 0; i < n; ++i) {
+        uint64_t m = 1ull << (8 * g.vd[i].kind);
+        if (g.vd[i].grid < 0)
+            for (size_t j = 0; j < kids[i].size(); ++j) m |= 1ull << (8 * g.vd[kids[i][j]].kind + 1 + (int)j);
+        g.vd[i].kind_items = g.vf[i].kind_items = (uint32_t)m;
+        g.vd[i].kind_items4 = g.vf[i].kind_items4 = (uint32_t)(m >> 32);
+    }
+    g.kinds = 0;
+    for (int i = 0; i < n; ++i) g.kinds |= 1u << g.vd[i].kind;
     g.nv = n;
     g.nm = (int)g.md.size();
     g.nf = (int)g.fd.size();
@@ -815,6 +827,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n_cell_items = (int)g.cell_items.size();
     P.scene_in_lds = g.scene_f_bytes <= c->lds_scene_budget ? 1 : 0;
     P.has_grid = g.gd.empty() ? 0 : 1;
+    P.kinds = g.kinds;
     const pr_source_desc& s = c->srcs[src];
     SourceDev& d = P.src;
     d.kind = s.kind;
@@ -1100,6 +1113,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         o.n_cell_start = (int)g.cell_start.size();
         o.n_cell_items = (int)g.cell_items.size();
         o.scene_in_lds = slds ? 1 : 0;
+        o.kinds = g.kinds;
         if (slds)
             scene_bytes = std::max(scene_bytes, batch_scene_lds_bytes(o.n_vols, o.n_mats, o.n_fams, o.n_children,
                                                                       o.n_grids, o.n_cell_start, o.n_cell_items));

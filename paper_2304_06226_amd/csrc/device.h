@@ -33,6 +33,11 @@ struct VolT {
     int32_t kind, axis, parent, mat;
     int32_t detector, mirror_mask, child_begin, child_count;
     int32_t mirror_model, grid;   // grid: index of the daughter grid, -1 = scan the daughter list
+    // Boundary candidates of a step in this volume: item 0 is the volume itself,
+    // item i (1..7) its daughter i-1 (daughters behind a grid are not items).
+    // Byte k of kind_items (k = PR_BOX .. PR_SPHERE) and byte 0 of kind_items4
+    // (PR_SPH_SHELL) hold the bit set of the items of that solid kind.
+    uint32_t kind_items, kind_items4;
     R R0, Qc, alpha, mQc, W;
 };
 
@@ -73,6 +78,7 @@ struct SceneT {
     const GridT<R>* grids;
     const int32_t* cell_start;
     const int32_t* cell_items;
+    uint32_t kinds;   // bit k set: some volume of the scene has solid kind k
 };
 
 struct SourceDev {
@@ -117,6 +123,7 @@ struct Params {
     int32_t n_grids, n_cell_start, n_cell_items;
     int32_t scene_in_lds;          // mixed policy: stage the FP32 scene into LDS (else read it from global memory)
     int32_t has_grid;              // some volume navigates its daughters through a grid
+    uint32_t kinds;                // solid kinds present in the scene (bit per kind)
     int32_t pad2;
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
@@ -150,7 +157,7 @@ struct SimDev {
     int32_t scene_in_lds;          // stage the scene into LDS (else read it from global memory)
     int32_t tally_begin, tally_count;
     int32_t privatised;            // 1: tallies privatised in LDS at TallyDev::lds_offset; 0: LDS bin cache
-    int32_t pad;
+    uint32_t kinds;                // solid kinds present in the scene (bit per kind)
     uint64_t first;                // history id of the simulation's first history
     uint64_t n;                    // histories
     uint64_t sc_begin;             // first super-chunk of this simulation
@@ -471,12 +478,12 @@ __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int 
     P.n = (lo ? 1 : 0) + (hi ? 1 : 0);
 }
 
-template <class R>
-__device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
+// pieces of the ray p + t u inside a solid of compile-time kind K
+template <class R, int K>
+__device__ __forceinline__ void pieces_kind(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
     R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
     P.n = 0;
-    switch (V.kind) {
-    case PR_BOX: {
+    if (K == PR_BOX) {
         R ta = -rinf<R>(), tb = rinf<R>();
         int fa = -1, fb = -1;
 #pragma unroll
@@ -487,36 +494,37 @@ __device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u
             if (!clip<R>(ta, tb, fa, fb, xa, xb, xfa, xfb)) return;
         }
         P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
-        return;
-    }
-    case PR_CYLINDER: {
+    } else if (K == PR_CYLINDER) {
         R ta, tb;
         int fa, fb;
         if (!cyl_range<R>(q, u, V.axis, V.s[0], V.s[1], 0, ta, tb, fa, fb)) return;
         P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
-        return;
-    }
-    case PR_CYL_SHELL: {
+    } else if (K == PR_CYL_SHELL) {
         R oa, ob, ia, ib;
         int ofa, ofb, ifa, ifb;
         if (!cyl_range<R>(q, u, V.axis, V.s[1], V.s[2], 0, oa, ob, ofa, ofb)) return;
         bool hin = cyl_range<R>(q, u, V.axis, V.s[0], V.s[2], 3, ia, ib, ifa, ifb);
         subtract<R>(P, oa, ob, ofa, ofb, hin, ia, ib, ifa, ifb);
-        return;
-    }
-    case PR_SPHERE: {
+    } else if (K == PR_SPHERE) {
         R ta, tb;
         if (!ball_range<R>(q, u, V.s[0], ta, tb)) return;
         P.a0 = ta; P.b0 = tb; P.fa0 = 0; P.fb0 = 0; P.n = 1;
-        return;
-    }
-    default: {  // spherical shell
+    } else {  // spherical shell
         R oa, ob, ia, ib;
         if (!ball_range<R>(q, u, V.s[1], oa, ob)) return;
         bool hin = ball_range<R>(q, u, V.s[0], ia, ib);
         subtract<R>(P, oa, ob, 0, 0, hin, ia, ib, 3, 3);
-        return;
     }
+}
+
+template <class R>
+__device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
+    switch (V.kind) {
+    case PR_BOX: pieces_kind<R, PR_BOX>(V, p, u, P); return;
+    case PR_CYLINDER: pieces_kind<R, PR_CYLINDER>(V, p, u, P); return;
+    case PR_CYL_SHELL: pieces_kind<R, PR_CYL_SHELL>(V, p, u, P); return;
+    case PR_SPHERE: pieces_kind<R, PR_SPHERE>(V, p, u, P); return;
+    default: pieces_kind<R, PR_SPH_SHELL>(V, p, u, P); return;
     }
 }
 
@@ -789,6 +797,41 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 // One step of the history loop
 // -------------------------------------------------------------------------
 
+// Boundary candidates of kind K for this lane (bit set `items`, see VolT): the
+// exit of the lane's own volume (item 0) and the entry into its daughters.  The
+// loop runs while any lane of the wave has an item of kind K left, so the kind's
+// intersection code is executed once per round for all those lanes together.
+// A daughter is entered at the start of its first piece ahead (a > 0); among
+// equal entry distances the lower daughter index wins, as in a scan in order.
+template <class R, int K, class ST>
+__device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, const ST& s, uint32_t items, R& d_exit,
+                                          int& face, R& d_child, int& child, int& child_item) {
+    if (((S.kinds >> K) & 1u) == 0u) return;
+    while (__ballot(items != 0u) != 0ull) {
+        if (items != 0u) {
+            const int i = __builtin_ctz(items);
+            items &= items - 1u;
+            const int vid = i == 0 ? s.region : S.children[V.child_begin + i - 1];
+            Pieces<R> P;
+            pieces_kind<R, K>(S.vols[vid], s.p, s.u, P);
+            if (i == 0) {
+                if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
+                if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
+            } else {
+                R a = rinf<R>();
+                if (P.n > 0 && P.a0 > (R)0) a = P.a0;
+                else if (P.n > 1 && P.a1 > (R)0) a = P.a1;
+                if (a < d_child || (a == d_child && a != rinf<R>() && i < child_item)) {
+                    d_child = a;
+                    child = vid;
+                    child_item = i;
+                }
+            }
+        }
+    }
+}
+
+
 template <class R, bool REC, bool GRID>
 __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
     if (s.steps >= kMaxSteps) {
@@ -799,27 +842,20 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     s.steps++;
     const VolT<R>& V = S.vols[s.region];
 
-    // nearest boundary: leave this volume, or enter a daughter
-    Pieces<R> P;
-    pieces<R>(V, s.p, s.u, P);
+    // nearest boundary: leave this volume, or enter a daughter.  The candidate
+    // solids are taken one solid kind at a time over the whole wave, so lanes in
+    // different volumes that need the same kind of intersection run it together.
     R d_exit = rinf<R>();
     int face = -1;
-    if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
-    if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
-    if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
     R d_child = rinf<R>();
-    int child = -1;
-    if (GRID && V.grid >= 0) {
-        grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child);
-    } else {
-        for (int ci = 0; ci < V.child_count; ++ci) {
-            int c = S.children[V.child_begin + ci];
-            Pieces<R> Q;
-            pieces<R>(S.vols[c], s.p, s.u, Q);
-            if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
-            if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
-        }
-    }
+    int child = -1, child_item = 0;
+    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, d_child, child, child_item);
+    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, d_child, child, child_item);
+    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, d_child, child, child_item);
+    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, d_child, child, child_item);
+    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, d_child, child, child_item);
+    if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
+    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child);
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
 

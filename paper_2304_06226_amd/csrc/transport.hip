@@ -69,7 +69,7 @@ __device__ __forceinline__ void add_global(const TallyDev& T, int64_t b, double 
 
 template <bool REC, bool GRID>
 __global__ __launch_bounds__(256) void k_plain(Params P) {
-    const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items};
+    const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.kinds};
     Counters cnt = {};
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < P.n) {
@@ -193,8 +193,8 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
         SLDS ? SceneT<float>{(const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
                              (const FamT<float>*)(base + L.fams), (const int32_t*)(base + L.children),
                              (const GridT<float>*)(base + L.grids), (const int32_t*)(base + L.cell_start),
-                             (const int32_t*)(base + L.cell_items)}
-             : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items};
+                             (const int32_t*)(base + L.cell_items), P.kinds}
+             : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items, P.kinds};
 
     Counters cnt = {};
     PState<float> s;
@@ -403,9 +403,9 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
         S = SceneT<float>{(const VolT<float>*)(scene + L.vols), (const MatT<float>*)(scene + L.mats),
                           (const FamT<float>*)(scene + L.fams), (const int32_t*)(scene + L.children),
                           (const GridT<float>*)(scene + L.grids), (const int32_t*)(scene + L.cell_start),
-                          (const int32_t*)(scene + L.cell_items)};
+                          (const int32_t*)(scene + L.cell_items), sd.kinds};
     } else {
-        S = SceneT<float>{sd.vols, sd.mats, sd.fams, sd.children, sd.grids, sd.cell_start, sd.cell_items};
+        S = SceneT<float>{sd.vols, sd.mats, sd.fams, sd.children, sd.grids, sd.cell_start, sd.cell_items, sd.kinds};
     }
     PState<float> s;
     s.term = 1;
