@@ -39,6 +39,8 @@ struct Geometry {
     std::vector<int32_t> children, cell_start, cell_items;
     std::vector<GridT<double>> gd;
     std::vector<GridT<float>> gf;
+    std::vector<BoxT<double>> bd;   // box bounds by volume index (grid navigation)
+    std::vector<BoxT<float>> bf;
     int nv = 0, nm = 0, nf = 0, nc = 0;
     uint32_t kinds = 0;   // bit k: some volume has solid kind k
     void* vols_d = nullptr;
@@ -52,7 +54,10 @@ struct Geometry {
     void* grids_f = nullptr;
     void* cell_start_d = nullptr;
     void* cell_items_d = nullptr;
+    void* boxes_d = nullptr;
+    void* boxes_f = nullptr;
     int scene_f_bytes = 0;   // FP32 scene size (LDS staging decision)
+    int scene_lds_bytes = 0; // LDS the FP32 scene takes when staged (grid scenes: all but the volume table)
 };
 
 struct Tally {
@@ -94,6 +99,7 @@ struct pr_ctx {
     int bin_cache_slots = 1024;         // LDS bin-cache slots per non-privatised tally (power of two, 0 = off)
     int chunk = 256;                    // history indices a wave claims per atomic
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
+    int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     DescSlot slots[4];
     int superchunk = 2048;              // batched runs: histories a block claims per simulation visit
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
@@ -272,7 +278,7 @@ int upload(pr_ctx* c, void** dst, const std::vector<T>& v) {
 
 void free_geometry(Geometry& g) {
     void** ps[] = {&g.vols_d, &g.mats_d, &g.fams_d, &g.vols_f, &g.mats_f, &g.fams_f, &g.children_d,
-                   &g.grids_d, &g.grids_f, &g.cell_start_d, &g.cell_items_d};
+                   &g.grids_d, &g.grids_f, &g.cell_start_d, &g.cell_items_d, &g.boxes_d, &g.boxes_f};
     for (void** p : ps) {
         if (*p) (void)hipFree(*p);
         *p = nullptr;
@@ -320,7 +326,9 @@ void build_grid(const pr_volume_desc* vols, const std::vector<int32_t>& kids, Ge
         }
         for (int a = r0[0]; a <= r1[0]; ++a)
             for (int b = r0[1]; b <= r1[1]; ++b)
-                for (int c = r0[2]; c <= r1[2]; ++c) cells[(a * G.n[1] + b) * G.n[2] + c].push_back(kids[i]);
+                for (int c = r0[2]; c <= r1[2]; ++c)
+                    cells[(a * G.n[1] + b) * G.n[2] + c].push_back(
+                        (int32_t)((uint32_t)kids[i] | ((uint32_t)vols[kids[i]].kind << kItemKindShift)));
     }
     if (g.cell_start.empty()) g.cell_start.push_back(0);
     G.cells_off = (int32_t)g.cell_start.size() - 1;
@@ -642,6 +650,17 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
     }
     g.kinds = 0;
     for (int i = 0; i < n; ++i) g.kinds |= 1u << g.vd[i].kind;
+    g.bd.assign(n, BoxT<double>{});
+    g.bf.assign(n, BoxT<float>{});
+    for (int i = 0; i < n; ++i) {
+        if (g.vd[i].kind != PR_BOX) continue;
+        for (int k = 0; k < 3; ++k) {
+            g.bd[i].c[k] = g.vd[i].c[k];
+            g.bd[i].s[k] = g.vd[i].s[k];
+            g.bf[i].c[k] = g.vf[i].c[k];
+            g.bf[i].s[k] = g.vf[i].s[k];
+        }
+    }
     g.nv = n;
     g.nm = (int)g.md.size();
     g.nf = (int)g.fd.size();
@@ -650,6 +669,8 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
                             g.ff.size() * sizeof(FamT<float>) + g.children.size() * 4 +
                             g.gf.size() * sizeof(GridT<float>) + g.cell_start.size() * 4 + g.cell_items.size() * 4) +
                       7 * 16;
+    g.scene_lds_bytes = batch_scene_lds_bytes(g.nv, g.nm, g.nf, g.nc, (int)g.gf.size(), (int)g.cell_start.size(),
+                                              (int)g.cell_items.size(), g.gd.empty() ? 0 : 1);
     if (c->device >= 0) {
         int rc = set_device(c);
         if (rc) return rc;
@@ -657,7 +678,8 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
             (rc = upload(c, &g.mats_f, g.mf)) || (rc = upload(c, &g.fams_d, g.fd)) || (rc = upload(c, &g.fams_f, g.ff)) ||
             (rc = upload(c, &g.children_d, g.children)) || (rc = upload(c, &g.grids_d, g.gd)) ||
             (rc = upload(c, &g.grids_f, g.gf)) || (rc = upload(c, &g.cell_start_d, g.cell_start)) ||
-            (rc = upload(c, &g.cell_items_d, g.cell_items))) {
+            (rc = upload(c, &g.cell_items_d, g.cell_items)) || (rc = upload(c, &g.boxes_d, g.bd)) ||
+            (rc = upload(c, &g.boxes_f, g.bf))) {
             free_geometry(g);
             return rc;
         }
@@ -797,6 +819,23 @@ static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
     o.cache_bits = 0;
 }
 
+constexpr int kLdsPerCu = 160 * 1024;
+
+// Block size for kernels that stage a grid scene into LDS: the staged copy is
+// large, so fewer, larger blocks share it; take the size (up to 768 threads)
+// that keeps the most waves resident per CU, the smallest among equals.  A
+// block count per CU set by the tuning keeps the tuned block size.
+template <class Occ>
+static int grid_block(const pr_ctx* c, Occ occupancy) {
+    if (c->mixed_blocks_per_cu > 0) return c->mixed_block;
+    int best = c->mixed_block, best_waves = occupancy(best) * (best / 64);
+    for (int b = 256; b <= 768; b += 256) {
+        const int w = occupancy(b) * (b / 64);
+        if (w > best_waves) { best = b; best_waves = w; }
+    }
+    return best;
+}
+
 static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
                         uint64_t n, int32_t precision, void* records, Params& P) {
     if (geom < 0 || geom >= (int)c->geoms.size()) return fail(c, PR_ENOTFOUND, "geometry %d unknown", geom);
@@ -813,6 +852,8 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.vols_f = (const VolT<float>*)g.vols_f;
     P.mats_f = (const MatT<float>*)g.mats_f;
     P.fams_f = (const FamT<float>*)g.fams_f;
+    P.boxes_d = (const BoxT<double>*)g.boxes_d;
+    P.boxes_f = (const BoxT<float>*)g.boxes_f;
     P.children = (const int32_t*)g.children_d;
     P.grids_d = (const GridT<double>*)g.grids_d;
     P.grids_f = (const GridT<float>*)g.grids_f;
@@ -825,8 +866,8 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n_grids = (int)g.gd.size();
     P.n_cell_start = (int)g.cell_start.size();
     P.n_cell_items = (int)g.cell_items.size();
-    P.scene_in_lds = g.scene_f_bytes <= c->lds_scene_budget ? 1 : 0;
     P.has_grid = g.gd.empty() ? 0 : 1;
+    P.scene_in_lds = g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget) ? 1 : 0;
     P.kinds = g.kinds;
     const pr_source_desc& s = c->srcs[src];
     SourceDev& d = P.src;
@@ -928,9 +969,11 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
     if (precision == PR_FP64_PLAIN) {
         e = launch_plain(P, records != nullptr, st);
     } else {
-        const int block = c->mixed_block;
+        if (P.scene_in_lds && mixed_lds_bytes(P) > kLdsPerCu) P.scene_in_lds = 0;   // tallies leave no room
         int lds = mixed_lds_bytes(P);
-        if (lds > 160 * 1024) return fail(c, PR_EINVAL, "scene and tallies need %d bytes of LDS", lds);
+        if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "scene and tallies need %d bytes of LDS", lds);
+        int block = c->mixed_block;
+        if (P.has_grid && P.scene_in_lds) block = grid_block(c, [&](int b) { return mixed_occupancy(P, b); });
         int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : mixed_occupancy(P, block);
         uint64_t want = (n + block - 1) / block;
         uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, want);
@@ -1105,6 +1148,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         o.grids = (const GridT<float>*)g.grids_f;
         o.cell_start = (const int32_t*)g.cell_start_d;
         o.cell_items = (const int32_t*)g.cell_items_d;
+        o.boxes = (const BoxT<float>*)g.boxes_f;
         o.n_vols = g.nv;
         o.n_mats = g.nm;
         o.n_fams = g.nf;
@@ -1114,9 +1158,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         o.n_cell_items = (int)g.cell_items.size();
         o.scene_in_lds = slds ? 1 : 0;
         o.kinds = g.kinds;
-        if (slds)
-            scene_bytes = std::max(scene_bytes, batch_scene_lds_bytes(o.n_vols, o.n_mats, o.n_fams, o.n_children,
-                                                                      o.n_grids, o.n_cell_start, o.n_cell_items));
+        if (slds) scene_bytes = std::max(scene_bytes, g.scene_lds_bytes);
         o.tally_begin = (int32_t)td.size();
         o.tally_count = sm.n_tallies;
         int64_t need = 0;
@@ -1192,8 +1234,9 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
     B.stats = trial ? c->scratch_stats : c->stats;
     B.counter = c->counter;
     const int lds = batch_lds_bytes(B);
-    if (lds > 160 * 1024) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
-    const int block = c->mixed_block;
+    if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
+    int block = c->mixed_block;
+    if (grid_nav && slds) block = grid_block(c, [&](int b) { return batch_occupancy(B, slds, grid_nav, b); });
     const int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, block);
     uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, scs);
     if (grid < 1) grid = 1;
@@ -1246,9 +1289,8 @@ static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream
     std::vector<int> cls(nsims);
     for (int i = 0; i < nsims; ++i) {
         const Geometry& g = c->geoms[sims[i].geom];
-        const int sb = batch_scene_lds_bytes(g.nv, g.nm, g.nf, g.nc, (int)g.gf.size(), (int)g.cell_start.size(),
-                                             (int)g.cell_items.size());
-        cls[i] = (sb <= c->lds_scene_budget ? 1 : 0) + (g.gd.empty() ? 0 : 2);
+        const bool grid = !g.gd.empty();
+        cls[i] = (g.scene_lds_bytes <= (grid ? c->lds_grid_budget : c->lds_scene_budget) ? 1 : 0) + (grid ? 2 : 0);
     }
     for (int k = 0; k < 4; ++k) {
         std::vector<int> idx;

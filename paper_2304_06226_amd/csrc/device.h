@@ -69,6 +69,18 @@ struct FamT {
     R pad;
 };
 
+// Axis-aligned box bounds of a volume (centre, half sides), kept apart from the
+// volume table so that grid navigation over many boxes reads 24 bytes per box.
+template <class R>
+struct BoxT {
+    R c[3];
+    R s[3];
+};
+
+// A grid cell item is a daughter's volume index with its solid kind in the top bits.
+constexpr uint32_t kItemVol = 0x0FFFFFFFu;
+constexpr int kItemKindShift = 28;
+
 template <class R>
 struct SceneT {
     const VolT<R>* vols;
@@ -78,7 +90,8 @@ struct SceneT {
     const GridT<R>* grids;
     const int32_t* cell_start;
     const int32_t* cell_items;
-    uint32_t kinds;   // bit k set: some volume of the scene has solid kind k
+    const BoxT<R>* boxes;   // box bounds by volume index (grid scenes)
+    uint32_t kinds;         // bit k set: some volume of the scene has solid kind k
 };
 
 struct SourceDev {
@@ -114,6 +127,8 @@ struct Params {
     const VolT<float>* vols_f;
     const MatT<float>* mats_f;
     const FamT<float>* fams_f;
+    const BoxT<double>* boxes_d;
+    const BoxT<float>* boxes_f;
     const int32_t* children;
     const GridT<double>* grids_d;
     const GridT<float>* grids_f;
@@ -121,7 +136,8 @@ struct Params {
     const int32_t* cell_items;
     int32_t n_vols, n_mats, n_fams, n_children;
     int32_t n_grids, n_cell_start, n_cell_items;
-    int32_t scene_in_lds;          // mixed policy: stage the FP32 scene into LDS (else read it from global memory)
+    int32_t scene_in_lds;          // mixed policy: stage the FP32 scene into LDS (else read it from global memory);
+                                   // grid scenes stage all but the volume table, plus the box bounds
     int32_t has_grid;              // some volume navigates its daughters through a grid
     uint32_t kinds;                // solid kinds present in the scene (bit per kind)
     int32_t pad2;
@@ -153,6 +169,7 @@ struct SimDev {
     const GridT<float>* grids;
     const int32_t* cell_start;
     const int32_t* cell_items;
+    const BoxT<float>* boxes;
     int32_t n_vols, n_mats, n_fams, n_children, n_grids, n_cell_start, n_cell_items;
     int32_t scene_in_lds;          // stage the scene into LDS (else read it from global memory)
     int32_t tally_begin, tally_count;
@@ -478,22 +495,46 @@ __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int 
     P.n = (lo ? 1 : 0) + (hi ? 1 : 0);
 }
 
+// pieces of the ray q + t u (q relative to the centre) inside a box of half sides h
+template <class R>
+__device__ __forceinline__ void box_pieces(const R q[3], const R u[3], const R h[3], Pieces<R>& P) {
+    P.n = 0;
+    R ta = -rinf<R>(), tb = rinf<R>();
+    int fa = -1, fb = -1;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        R xa, xb;
+        int xfa, xfb;
+        if (!slab1<R>(q[k], u[k], -h[k], h[k], 2 * k, 2 * k + 1, xa, xb, xfa, xfb)) return;
+        if (!clip<R>(ta, tb, fa, fb, xa, xb, xfa, xfb)) return;
+    }
+    P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
+}
+
+template <class R>
+__device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P);
+
+// pieces of a grid daughter: boxes from the compact box table, other kinds
+// from the volume table
+template <class R>
+__device__ __forceinline__ void item_pieces(const SceneT<R>& S, uint32_t it, const R p[3], const R u[3], Pieces<R>& P) {
+    const int c = (int)(it & kItemVol);
+    if ((int)(it >> kItemKindShift) == PR_BOX) {
+        const BoxT<R>& B = S.boxes[c];
+        R q[3] = {p[0] - B.c[0], p[1] - B.c[1], p[2] - B.c[2]};
+        box_pieces<R>(q, u, B.s, P);
+    } else {
+        pieces<R>(S.vols[c], p, u, P);
+    }
+}
+
 // pieces of the ray p + t u inside a solid of compile-time kind K
 template <class R, int K>
 __device__ __forceinline__ void pieces_kind(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
     R q[3] = {p[0] - V.c[0], p[1] - V.c[1], p[2] - V.c[2]};
     P.n = 0;
     if (K == PR_BOX) {
-        R ta = -rinf<R>(), tb = rinf<R>();
-        int fa = -1, fb = -1;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            R xa, xb;
-            int xfa, xfb;
-            if (!slab1<R>(q[k], u[k], -V.s[k], V.s[k], 2 * k, 2 * k + 1, xa, xb, xfa, xfb)) return;
-            if (!clip<R>(ta, tb, fa, fb, xa, xb, xfa, xfb)) return;
-        }
-        P.a0 = ta; P.b0 = tb; P.fa0 = fa; P.fb0 = fb; P.n = 1;
+        box_pieces<R>(q, u, V.s, P);
     } else if (K == PR_CYLINDER) {
         R ta, tb;
         int fa, fb;
@@ -519,6 +560,7 @@ __device__ __forceinline__ void pieces_kind(const VolT<R>& V, const R p[3], cons
 
 template <class R>
 __device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u[3], Pieces<R>& P) {
+    P.n = 0;
     switch (V.kind) {
     case PR_BOX: pieces_kind<R, PR_BOX>(V, p, u, P); return;
     case PR_CYLINDER: pieces_kind<R, PR_CYLINDER>(V, p, u, P); return;
@@ -553,6 +595,18 @@ __device__ __forceinline__ bool contains(const VolT<R>& V, const R p[3]) {
         return r2 >= V.s[0] * V.s[0] && r2 <= V.s[1] * V.s[1];
     }
     }
+}
+
+template <class R>
+__device__ __forceinline__ bool item_contains(const SceneT<R>& S, uint32_t it, const R p[3]) {
+    const int c = (int)(it & kItemVol);
+    if ((int)(it >> kItemKindShift) == PR_BOX) {
+        const BoxT<R>& B = S.boxes[c];
+        const R q[3] = {p[0] - B.c[0], p[1] - B.c[1], p[2] - B.c[2]};
+        return __builtin_fabs((double)q[0]) <= (double)B.s[0] && __builtin_fabs((double)q[1]) <= (double)B.s[1] &&
+               __builtin_fabs((double)q[2]) <= (double)B.s[2];
+    }
+    return contains<R>(S.vols[c], p);
 }
 
 // outward normal of face f at point p
@@ -625,8 +679,8 @@ __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root
             if (in) {
                 const int je = S.cell_start[G.cells_off + cell + 1];
                 for (int j = S.cell_start[G.cells_off + cell]; j < je; ++j) {
-                    const int c = S.cell_items[j];
-                    if (contains<R>(S.vols[c], p)) { next = c; break; }
+                    const uint32_t it = (uint32_t)S.cell_items[j];
+                    if (item_contains<R>(S, it, p)) { next = (int)(it & kItemVol); break; }
                 }
             }
         } else {
@@ -775,9 +829,10 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
         const int cell = (ix[0] * G.n[1] + ix[1]) * G.n[2] + ix[2];
         const int jb = S.cell_start[G.cells_off + cell], je = S.cell_start[G.cells_off + cell + 1];
         for (int j = jb; j < je; ++j) {
-            const int c = S.cell_items[j];
+            const uint32_t it = (uint32_t)S.cell_items[j];
+            const int c = (int)(it & kItemVol);
             Pieces<R> Q;
-            pieces<R>(S.vols[c], p, u, Q);
+            item_pieces<R>(S, it, p, u, Q);
             if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
             if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
         }

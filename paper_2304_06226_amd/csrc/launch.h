@@ -14,7 +14,7 @@ int mixed_lds_bytes(const Params& P);
 hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid, int block, hipStream_t st);
 int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block);
 int batch_lds_bytes(const BatchParams& B);
-int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci);
+int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci, int grid);
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st);
 hipError_t zero_f64(double* p, uint64_t n, hipStream_t st);
 

@@ -69,7 +69,8 @@ __device__ __forceinline__ void add_global(const TallyDev& T, int64_t b, double 
 
 template <bool REC, bool GRID>
 __global__ __launch_bounds__(256) void k_plain(Params P) {
-    const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.kinds};
+    const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.boxes_d,
+                           P.kinds};
     Counters cnt = {};
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < P.n) {
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void k_plain(Params P) {
 // (2 doubles per slot)] [bin-cache keys (u32 per slot)] [scene, when staged:
 // volumes, materials, Bragg tables, daughter lists, grids, grid cells]
 struct LdsLayout {
-    int cache_vals, cache_keys, vols, mats, fams, children, grids, cell_start, cell_items, bytes;   // byte offsets
+    int cache_vals, cache_keys, vols, mats, fams, children, grids, cell_start, cell_items, boxes, bytes;   // byte offsets
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
@@ -107,13 +108,16 @@ __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
 __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
     LdsLayout L;
     const int st = P.scene_in_lds ? 1 : 0;
+    // grid scenes keep the volume table in global memory and stage the box bounds
+    const int sv = P.scene_in_lds && !P.has_grid ? 1 : 0;
+    const int sb = P.scene_in_lds && P.has_grid ? 1 : 0;
     int off = P.lds_tally_doubles * 8;
     L.cache_vals = off;
     off += P.cache_slots * 16;
     L.cache_keys = off;
     off = align16(off + P.cache_slots * 4);
     L.vols = off;
-    off = align16(off + st * P.n_vols * (int)sizeof(VolT<float>));
+    off = align16(off + sv * P.n_vols * (int)sizeof(VolT<float>));
     L.mats = off;
     off = align16(off + st * P.n_mats * (int)sizeof(MatT<float>));
     L.fams = off;
@@ -126,6 +130,8 @@ __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
     off = align16(off + st * P.n_cell_start * 4);
     L.cell_items = off;
     off = align16(off + st * P.n_cell_items * 4);
+    L.boxes = off;
+    off = align16(off + sb * P.n_vols * (int)sizeof(BoxT<float>));
     L.bytes = off;
     return L;
 }
@@ -171,14 +177,15 @@ __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes
 }
 
 template <bool REC, bool SLDS, bool GRID>
-__global__ __launch_bounds__(256) void k_mixed(Params P) {
+__global__ __launch_bounds__(GRID ? 768 : 256) void k_mixed(Params P) {
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
     char* base = (char*)lds;
     double* cvals = (double*)(base + L.cache_vals);
     uint32_t* ckeys = (uint32_t*)(base + L.cache_keys);
     if (SLDS) {
-        copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
+        if (!GRID) copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
+        if (GRID) copy_words(base + L.boxes, P.boxes_f, P.n_vols * (int)sizeof(BoxT<float>));
         copy_words(base + L.mats, P.mats_f, P.n_mats * (int)sizeof(MatT<float>));
         copy_words(base + L.fams, P.fams_f, P.n_fams * (int)sizeof(FamT<float>));
         copy_words(base + L.children, P.children, P.n_children * 4);
@@ -190,11 +197,13 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
     for (int i = threadIdx.x; i < P.cache_slots; i += blockDim.x) ckeys[i] = kEmptyKey;
     __syncthreads();
     const SceneT<float> S =
-        SLDS ? SceneT<float>{(const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
+        SLDS ? SceneT<float>{GRID ? P.vols_f : (const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
                              (const FamT<float>*)(base + L.fams), (const int32_t*)(base + L.children),
                              (const GridT<float>*)(base + L.grids), (const int32_t*)(base + L.cell_start),
-                             (const int32_t*)(base + L.cell_items), P.kinds}
-             : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items, P.kinds};
+                             (const int32_t*)(base + L.cell_items),
+                             GRID ? (const BoxT<float>*)(base + L.boxes) : P.boxes_f, P.kinds}
+             : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items,
+                             P.boxes_f, P.kinds};
 
     Counters cnt = {};
     PState<float> s;
@@ -290,14 +299,15 @@ __global__ __launch_bounds__(256) void k_mixed(Params P) {
 // LDS of a batch block: [tally region (doubles): privatised tallies of the
 // staged simulation, or bin-cache values] [bin-cache keys] [staged scene]
 struct SceneLds {
-    int vols, mats, fams, children, grids, cell_start, cell_items, bytes;
+    int vols, mats, fams, children, grids, cell_start, cell_items, boxes, bytes;
 };
 
-__host__ __device__ inline SceneLds scene_lds_layout(int nv, int nm, int nf, int nc, int ng, int ncs, int nci) {
+// grid scenes (grid != 0) keep the volume table in global memory and stage the box bounds
+__host__ __device__ inline SceneLds scene_lds_layout(int nv, int nm, int nf, int nc, int ng, int ncs, int nci, int grid) {
     SceneLds L;
     int off = 0;
     L.vols = off;
-    off = align16(off + nv * (int)sizeof(VolT<float>));
+    off = align16(off + (grid ? 0 : nv) * (int)sizeof(VolT<float>));
     L.mats = off;
     off = align16(off + nm * (int)sizeof(MatT<float>));
     L.fams = off;
@@ -310,12 +320,14 @@ __host__ __device__ inline SceneLds scene_lds_layout(int nv, int nm, int nf, int
     off = align16(off + ncs * 4);
     L.cell_items = off;
     off = align16(off + nci * 4);
+    L.boxes = off;
+    off = align16(off + (grid ? nv : 0) * (int)sizeof(BoxT<float>));
     L.bytes = off;
     return L;
 }
 
-int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci) {
-    return scene_lds_layout(nv, nm, nf, nc, ng, ncs, nci).bytes;
+int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci, int grid) {
+    return scene_lds_layout(nv, nm, nf, nc, ng, ncs, nci, grid).bytes;
 }
 
 struct BlockCtl {
@@ -399,13 +411,15 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
     SceneT<float> S;
     if (SLDS) {
         const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
-                                            sd.n_cell_start, sd.n_cell_items);
-        S = SceneT<float>{(const VolT<float>*)(scene + L.vols), (const MatT<float>*)(scene + L.mats),
+                                            sd.n_cell_start, sd.n_cell_items, GRID ? 1 : 0);
+        S = SceneT<float>{GRID ? sd.vols : (const VolT<float>*)(scene + L.vols), (const MatT<float>*)(scene + L.mats),
                           (const FamT<float>*)(scene + L.fams), (const int32_t*)(scene + L.children),
                           (const GridT<float>*)(scene + L.grids), (const int32_t*)(scene + L.cell_start),
-                          (const int32_t*)(scene + L.cell_items), sd.kinds};
+                          (const int32_t*)(scene + L.cell_items),
+                          GRID ? (const BoxT<float>*)(scene + L.boxes) : sd.boxes, sd.kinds};
     } else {
-        S = SceneT<float>{sd.vols, sd.mats, sd.fams, sd.children, sd.grids, sd.cell_start, sd.cell_items, sd.kinds};
+        S = SceneT<float>{sd.vols, sd.mats, sd.fams, sd.children, sd.grids, sd.cell_start, sd.cell_items, sd.boxes,
+                          sd.kinds};
     }
     PState<float> s;
     s.term = 1;
@@ -469,7 +483,8 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
 }
 
 template <bool SLDS, bool GRID>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 4, 8))) void k_batch(BatchParams B) {
+__global__ __launch_bounds__(GRID ? 768 : 256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 4, 8))) void k_batch(
+    BatchParams B) {
     extern __shared__ double lds[];
     __shared__ BlockCtl ctl;
     double* ltal = lds;
@@ -506,8 +521,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
             for (int i = threadIdx.x; i < nslots; i += blockDim.x) ckeys[i] = kEmptyKey;
             if (SLDS) {
                 const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
-                                                    sd.n_cell_start, sd.n_cell_items);
-                copy_words(scene + L.vols, sd.vols, sd.n_vols * (int)sizeof(VolT<float>));
+                                                    sd.n_cell_start, sd.n_cell_items, GRID ? 1 : 0);
+                if (!GRID) copy_words(scene + L.vols, sd.vols, sd.n_vols * (int)sizeof(VolT<float>));
+                if (GRID) copy_words(scene + L.boxes, sd.boxes, sd.n_vols * (int)sizeof(BoxT<float>));
                 copy_words(scene + L.mats, sd.mats, sd.n_mats * (int)sizeof(MatT<float>));
                 copy_words(scene + L.fams, sd.fams, sd.n_fams * (int)sizeof(FamT<float>));
                 copy_words(scene + L.children, sd.children, sd.n_children * 4);

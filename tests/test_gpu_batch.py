@@ -155,3 +155,55 @@ def test_autotune_leaves_tallies_untouched(ctx):
         for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
             assert nh == rn
             assert np.array_equal(sw, rw) and np.array_equal(sw2, rw2)
+
+
+def _mixed_grid_problem(n):
+    """A 4x4 lattice of daughters of every solid kind (16 daughters: the world
+    navigates them through a grid whose cells hold boxes, cylinders along each
+    axis, spheres and both shells), lit by a 1.8 A beam over 240x240 mm."""
+    mats = [W.sample_material(), W.vessel_material()]
+    vols = [W.Volume("box", (0.0, 0.0, 0.0), (400.0, 400.0, 400.0))]
+    kinds = ["box", "cylinder", "sphere", "cyl_shell", "sph_shell"]
+    i = 0
+    for x in (-90.0, -30.0, 30.0, 90.0):
+        for y in (-90.0, -30.0, 30.0, 90.0):
+            k = kinds[i % len(kinds)]
+            c = (x, y, 10.0 * (i % 3) - 10.0)
+            if k == "box":
+                v = W.Volume(k, c, (40.0, 30.0, 50.0), parent=0, material=i % 2)
+            elif k == "cylinder":
+                v = W.Volume(k, c, (15.0, 40.0), axis=i % 3, parent=0, material=i % 2)
+            elif k == "sphere":
+                v = W.Volume(k, c, (18.0,), parent=0, material=i % 2)
+            elif k == "cyl_shell":
+                v = W.Volume(k, c, (10.0, 16.0, 40.0), axis=(i + 1) % 3, parent=0, material=i % 2)
+            else:
+                v = W.Volume(k, c, (10.0, 18.0), parent=0, material=i % 2)
+            vols.append(v)
+            i += 1
+    src = W.Source("rect", origin=(0.0, 0.0, -150.0), direction=(0.0, 0.0, 1.0), size=(240.0, 240.0),
+                   spectrum="mono", lam0=1.8)
+    tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0.0, 180.0, 180)]),
+               W.Tally(trigger="escape", filter="unscattered"),
+               W.Tally(trigger="absorb")]
+    return W.Problem(mats, vols, src, tallies, n_histories=n, name="mixed-grid")
+
+
+def test_mixed_kind_grid_fp64_elementwise(ctx):
+    print("[case] mixed-kind grid fp64 n=20000", flush=True)
+    prob = _mixed_grid_problem(20_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+    ores = O.run(prob, first=0, n=20_000, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+    assert gst["scatters"] > 1000
+
+
+def test_mixed_kind_grid_fp32_tally_agreement(ctx):
+    print("[case] mixed-kind grid fp32 n=400000", flush=True)
+    prob = _mixed_grid_problem(400_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
+    ores = O.run(prob, first=0, n=400_000, threads=8)
+    for t, (sw, sw2, nh) in enumerate(gres):
+        p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
+        assert p > 1e-3, (t, p)
