@@ -253,6 +253,9 @@ int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precisi
  * chunk: history indices a wave claims from the shared counter per atomic;
  * superchunk: histories of one simulation a block claims per visit in
  * pr_run_batch (the block stages that simulation's scene and tallies in LDS).
+ * Scenes with a daughter grid whose grid, box bounds and tables are staged in
+ * LDS run blocks of 256, 512 or 768 threads, whichever keeps the most waves
+ * resident per CU, unless blocks_per_cu is set (then `block` is used).
  * Results do not depend on these settings beyond floating-point summation
  * order. */
 typedef struct {
