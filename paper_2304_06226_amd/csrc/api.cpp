@@ -619,6 +619,8 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         o.gs = d.scatter_bias;
         o.fam_begin = (int32_t)fd.size();
         o.nfam = d.n_families;
+        o.inv_ga = 1.0 / o.ga;
+        o.inv_gs = 1.0 / o.gs;
         double cum = 0.0;
         for (int j = 0; j < d.n_families; ++j) {
             cum += M.mult[j] * M.d[j] * M.f2[j];
@@ -627,8 +629,9 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
             ff.push_back(FamT<float>{(float)f.edge, (float)f.cum, (float)f.inv2d2, 0.0f});
         }
         md.push_back(o);
+        // the FP32 policy divides by its own (float) factors, in FP64
         mf.push_back(MatT<float>{(float)o.sa_per_lambda, (float)o.si, (float)o.sc_k, (float)o.ga, (float)o.gs,
-                                 o.fam_begin, o.nfam});
+                                 o.fam_begin, o.nfam, 1.0 / (double)(float)o.ga, 1.0 / (double)(float)o.gs});
     }
     g.vd = std::move(vd);
     g.vf = std::move(vf);

@@ -58,6 +58,7 @@ template <class R>
 struct MatT {
     R sa_per_lambda, si, sc_k, ga, gs;
     int32_t fam_begin, nfam;
+    double inv_ga, inv_gs;   // 1 / ga, 1 / gs in FP64 (weight factors of an interaction)
 };
 
 // Bragg family tables, all materials concatenated (canonical order per material)
@@ -233,7 +234,8 @@ struct M<float> {
     // [2^-24, 1] or positive energies, never denormal
     static __device__ __forceinline__ float log_(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
     static __device__ __forceinline__ float exp_(float x) { return __expf(x); }
-    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+    // hardware square root (about 1 ulp), without the correctly rounded fix-up sequence
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
     static __device__ __forceinline__ float div_(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float tan_(float x) { return ::tanf(x); }
     static __device__ __forceinline__ float cos_(float x) { return __cosf(x); }
@@ -938,12 +940,12 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         R r = draw_ready(s, seed) * sig_g;
         R wa = s.ga * s.sa, wi = s.gs * s.si, wc = s.gs * s.sc;
         if (r < wa || wi + wc == (R)0) {
-            s.w *= 1.0 / (double)s.ga;
+            s.w *= S.mats[s.xs_mat].inv_ga;
             s.term = PR_END_ABSORB;
             hash_ev<REC>(s.hash, EV_ABS, 0);
             return;
         }
-        s.w *= 1.0 / (double)s.gs;
+        s.w *= S.mats[s.xs_mat].inv_gs;
         bool inc = r < wa + wi || wc == (R)0 || s.nact == 0;
         R u1 = draw_ready(s, seed);
         R u2 = draw_ready(s, seed);
