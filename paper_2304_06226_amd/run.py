@@ -3,9 +3,10 @@
     python -m paper_2304_06226_amd.run --workload guide --histories 1e8 --precision fp32 --repeat 3
 
 Workloads: sample (biased powder sample), vessel, guide, imaging, batch
-(the 256-simulation + imaging batch; always FP32-mixed).  One warm-up run,
-then `repeat` timed runs on disjoint history ranges (HIP events on the current
-stream).  Useful under rocprofv3 to profile one workload's kernels.
+(the 256-simulation + imaging batch; always FP32-mixed).  The mixed policy uses
+the workload's stored launch tuning (--autotune re-measures it).  One warm-up
+run, then `repeat` timed runs on disjoint history ranges (HIP events on the
+current stream).  Useful under rocprofv3 to profile one workload's kernels.
 """
 from __future__ import annotations
 
@@ -26,9 +27,11 @@ def main(argv=None):
     import torch
     from . import binding as B
     from . import workloads as W
+    from .tuning import TUNED
 
     torch.cuda.set_device(0)
     ctx = B.Context(0, seed=W.RUN_SEED)
+    ctx.set_tuning(**TUNED[args.workload])
     if args.workload == "batch":
         batch = W.config4()
         br = B.BatchRun(ctx, batch)
