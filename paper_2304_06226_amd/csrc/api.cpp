@@ -328,7 +328,8 @@ void build_grid(const pr_volume_desc* vols, const std::vector<int32_t>& kids, Ge
             for (int b = r0[1]; b <= r1[1]; ++b)
                 for (int c = r0[2]; c <= r1[2]; ++c)
                     cells[(a * G.n[1] + b) * G.n[2] + c].push_back(
-                        (int32_t)((uint32_t)kids[i] | ((uint32_t)vols[kids[i]].kind << kItemKindShift)));
+                        (int32_t)((uint32_t)kids[i] | ((uint32_t)vols[kids[i]].kind << kItemKindShift) |
+                                  (vols[kids[i]].is_detector ? kItemDet : 0u)));
     }
     if (g.cell_start.empty()) g.cell_start.push_back(0);
     G.cells_off = (int32_t)g.cell_start.size() - 1;
@@ -646,10 +647,15 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
     // grid serves them, its daughters (bits 1..7; fewer than kGridMinDaughters)
     for (int i = 0; i < n; ++i) {
         uint64_t m = 1ull << (8 * g.vd[i].kind);
+        uint32_t det = 0;
         if (g.vd[i].grid < 0)
-            for (size_t j = 0; j < kids[i].size(); ++j) m |= 1ull << (8 * g.vd[kids[i][j]].kind + 1 + (int)j);
+            for (size_t j = 0; j < kids[i].size(); ++j) {
+                m |= 1ull << (8 * g.vd[kids[i][j]].kind + 1 + (int)j);
+                if (g.vd[kids[i][j]].detector) det |= 1u << (1 + (int)j);
+            }
         g.vd[i].kind_items = g.vf[i].kind_items = (uint32_t)m;
         g.vd[i].kind_items4 = g.vf[i].kind_items4 = (uint32_t)(m >> 32);
+        g.vd[i].det_items = g.vf[i].det_items = det;
     }
     g.kinds = 0;
     for (int i = 0; i < n; ++i) g.kinds |= 1u << g.vd[i].kind;

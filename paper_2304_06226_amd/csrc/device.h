@@ -36,8 +36,9 @@ struct VolT {
     // Boundary candidates of a step in this volume: item 0 is the volume itself,
     // item i (1..7) its daughter i-1 (daughters behind a grid are not items).
     // Byte k of kind_items (k = PR_BOX .. PR_SPHERE) and byte 0 of kind_items4
-    // (PR_SPH_SHELL) hold the bit set of the items of that solid kind.
-    uint32_t kind_items, kind_items4;
+    // (PR_SPH_SHELL) hold the bit set of the items of that solid kind;
+    // det_items the items that are detector volumes.
+    uint32_t kind_items, kind_items4, det_items;
     R R0, Qc, alpha, mQc, W;
 };
 
@@ -78,9 +79,12 @@ struct BoxT {
     R s[3];
 };
 
-// A grid cell item is a daughter's volume index with its solid kind in the top bits.
+// A grid cell item is a daughter's volume index (bits 0-27), its solid kind
+// (bits 28-30) and whether it is a detector volume (bit 31).
 constexpr uint32_t kItemVol = 0x0FFFFFFFu;
 constexpr int kItemKindShift = 28;
+constexpr uint32_t kItemDet = 0x80000000u;
+__host__ __device__ inline int item_kind(uint32_t it) { return (int)((it >> kItemKindShift) & 7u); }
 
 template <class R>
 struct SceneT {
@@ -521,7 +525,7 @@ __device__ __forceinline__ void pieces(const VolT<R>& V, const R p[3], const R u
 template <class R>
 __device__ __forceinline__ void item_pieces(const SceneT<R>& S, uint32_t it, const R p[3], const R u[3], Pieces<R>& P) {
     const int c = (int)(it & kItemVol);
-    if ((int)(it >> kItemKindShift) == PR_BOX) {
+    if (item_kind(it) == PR_BOX) {
         const BoxT<R>& B = S.boxes[c];
         R q[3] = {p[0] - B.c[0], p[1] - B.c[1], p[2] - B.c[2]};
         box_pieces<R>(q, u, B.s, P);
@@ -602,7 +606,7 @@ __device__ __forceinline__ bool contains(const VolT<R>& V, const R p[3]) {
 template <class R>
 __device__ __forceinline__ bool item_contains(const SceneT<R>& S, uint32_t it, const R p[3]) {
     const int c = (int)(it & kItemVol);
-    if ((int)(it >> kItemKindShift) == PR_BOX) {
+    if (item_kind(it) == PR_BOX) {
         const BoxT<R>& B = S.boxes[c];
         const R q[3] = {p[0] - B.c[0], p[1] - B.c[1], p[2] - B.c[2]};
         return __builtin_fabs((double)q[0]) <= (double)B.s[0] && __builtin_fabs((double)q[1]) <= (double)B.s[1] &&
@@ -790,7 +794,7 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
 
 template <class R>
 __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>& G, const R p[3], const R u[3], R tmax,
-                                             R& d_child, int& child) {
+                                             R& d_child, int& child, int& child_det) {
     R t0 = (R)0, t1 = tmax;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -831,12 +835,17 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
         const int cell = (ix[0] * G.n[1] + ix[1]) * G.n[2] + ix[2];
         const int jb = S.cell_start[G.cells_off + cell], je = S.cell_start[G.cells_off + cell + 1];
         for (int j = jb; j < je; ++j) {
-            const uint32_t it = (uint32_t)S.cell_items[j];
-            const int c = (int)(it & kItemVol);
+            const uint32_t item = (uint32_t)S.cell_items[j];
             Pieces<R> Q;
-            item_pieces<R>(S, it, p, u, Q);
-            if (Q.n > 0 && Q.a0 > (R)0 && Q.a0 < d_child) { d_child = Q.a0; child = c; }
-            if (Q.n > 1 && Q.a1 > (R)0 && Q.a1 < d_child) { d_child = Q.a1; child = c; }
+            item_pieces<R>(S, item, p, u, Q);
+            R a = rinf<R>();
+            if (Q.n > 0 && Q.a0 > (R)0) a = Q.a0;
+            else if (Q.n > 1 && Q.a1 > (R)0) a = Q.a1;
+            if (a < d_child) {
+                d_child = a;
+                child = (int)(item & kItemVol);
+                child_det = (item & kItemDet) ? 1 : 0;
+            }
         }
         // leave through the nearest cell wall (selects, no indexed private arrays)
         const bool ax0 = tn[0] <= tn[1] && tn[0] <= tn[2];
@@ -862,7 +871,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 // equal entry distances the lower daughter index wins, as in a scan in order.
 template <class R, int K, class ST>
 __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, const ST& s, uint32_t items, R& d_exit,
-                                          int& face, R& d_child, int& child, int& child_item) {
+                                          int& face, R& d_child, int& child, int& child_item, int& child_det) {
     if (((S.kinds >> K) & 1u) == 0u) return;
     while (__ballot(items != 0u) != 0ull) {
         if (items != 0u) {
@@ -882,6 +891,7 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
                     d_child = a;
                     child = vid;
                     child_item = i;
+                    child_det = (int)((V.det_items >> i) & 1u);
                 }
             }
         }
@@ -905,14 +915,14 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     R d_exit = rinf<R>();
     int face = -1;
     R d_child = rinf<R>();
-    int child = -1, child_item = 0;
-    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, d_child, child, child_item);
-    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, d_child, child, child_item);
-    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, d_child, child, child_item);
-    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, d_child, child, child_item);
-    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, d_child, child, child_item);
+    int child = -1, child_item = 0, child_det = 0;
+    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
-    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child);
+    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child, child_det);
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
 
@@ -998,7 +1008,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     if (to_child) {
         s.region = child;
         hash_ev<REC>(s.hash, EV_ENTER, child);
-        if (S.vols[child].detector) {
+        if (child_det) {
             s.term = PR_END_DETECT;
             hash_ev<REC>(s.hash, EV_DETECT, child);
         }
