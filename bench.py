@@ -166,7 +166,8 @@ def main():
                                  "draws": head_st["draws"] / head_st["histories"],
                                  "scatters": head_st["scatters"] / head_st["histories"]}
     if not args.no_batch:
-        # the batched workload: 256 uneven powder simulations + the 1000-box imaging setup
+        # the batched workload: 256 uneven powder simulations + the 1000-box imaging setup,
+        # prepared once and stepped by replaying a HIP graph of one prepared run
         batch = W.config4()
         br = B.BatchRun(ctx, batch, base=1 << 40)
         if args.autotune:
@@ -174,21 +175,37 @@ def main():
         else:
             ctx.set_tuning(**TUNED["batch"])
             tuned = ctx.get_tuning()
+        # host cost of one unprepared call, for comparison
         br.run()
+        torch.cuda.synchronize()
+        h0 = time.perf_counter()
+        br.run(shift=br.span)
+        h_run_batch = (time.perf_counter() - h0) * 1e3
+        torch.cuda.synchronize()
+        pid = ctx.prepare_batch(br.descriptors(shift=2 * br.span), stride=br.span)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            ctx.run_prepared(pid)
+        graph.replay()   # warm-up step
         torch.cuda.synchronize()
         ctx.reset_stats()
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
+        h0 = time.perf_counter()
         t0.record()
-        for k in range(args.batch_steps):
-            br.run(shift=(k + 1) * br.span)
+        for _ in range(args.batch_steps):
+            graph.replay()
         t1.record()
+        h_graph = (time.perf_counter() - h0) * 1e3 / args.batch_steps
         torch.cuda.synchronize()
         bms = t0.elapsed_time(t1) / args.batch_steps
         bst = ctx.read_stats()
+        ctx.release_batch(pid)
         out["batched"] = {"value": batch.total_histories / bms * 1e3, "unit": "histories/s", "ms_per_step": bms,
                           "histories_per_step": batch.total_histories, "simulations": len(batch.problems),
                           "steps_per_history": bst["steps"] / max(1, bst["histories"]), "tuning": tuned,
+                          "step": "HIP graph replay of a prepared batch run",
+                          "host_ms_per_step": {"graph_replay": h_graph, "pr_run_batch": h_run_batch},
                           "workload": "256 powder simulations (r 1-20 mm, a 3.5-6 A, lambda 1-5 A, bias 1/2/4/8, "
                                       "1e4-1e6 histories each, odd ones in a vessel) + 1000-box imaging, 1e7 histories"}
         print(f"[bench] batched {bms:.3f} ms/step, {batch.total_histories / bms * 1e3:.4g} histories/s",

@@ -243,6 +243,26 @@ typedef struct {
  * be reused as soon as the call returns. */
 int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream);
 
+/* ---- prepared batches (repeated steps, HIP graph capture) ----
+ * pr_prepare_batch validates sims as pr_run_batch does, uploads their
+ * descriptors once into device memory owned by the context and freezes the
+ * launch tuning; *batch receives its id.  Each pr_run_prepared then runs every
+ * simulation over histories [first_history + offset, first_history + offset +
+ * n) with the batch's device-resident offset (0 at preparation) and afterwards
+ * adds `stride` to that offset (ids wrap modulo 2^64), so successive runs or
+ * graph replays continue with fresh histories when stride covers the batch's id
+ * span.  A run consists of kernel launches on `stream` only (no host copies,
+ * allocations, memsets or synchronisation), so it may be captured into a HIP
+ * graph and replayed; the histories of its tallies are counted on the device
+ * and included in pr_read_tally's n_hist.  Runs of one context must not
+ * overlap in time (they share its work counter).  Errors as pr_run_batch;
+ * PR_ENOTFOUND for an unknown or released batch.  pr_release_batch synchronises
+ * the device and frees the batch's device memory. */
+int pr_prepare_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, uint64_t stride,
+                     int32_t* batch);
+int pr_run_prepared(pr_ctx* ctx, int32_t batch, void* stream);
+int pr_release_batch(pr_ctx* ctx, int32_t batch);
+
 /* ---- launch tuning of PR_FP32_MIXED ---- */
 /* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
  * blocks per compute unit of the persistent grid (0 = occupancy limit);

@@ -42,7 +42,8 @@ RECORD_BYTES = 96
 EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_material", "pr_create_geometry",
            "pr_create_source", "pr_create_tally", "pr_tally_nbins", "pr_run_histories", "pr_read_tally",
            "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats", "pr_set_tuning",
-           "pr_get_tuning", "pr_run_batch", "pr_autotune"]
+           "pr_get_tuning", "pr_run_batch", "pr_autotune", "pr_prepare_batch", "pr_run_prepared",
+           "pr_release_batch"]
 
 
 class pr_material_desc(C.Structure):
@@ -129,6 +130,9 @@ def load():
     L.pr_run_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, vp]
     L.pr_autotune.argtypes = [vp, C.POINTER(pr_sim), i32, C.c_double, C.POINTER(pr_tuning), vp]
     L.pr_get_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
+    L.pr_prepare_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, u64, C.POINTER(i32)]
+    L.pr_run_prepared.argtypes = [vp, i32, vp]
+    L.pr_release_batch.argtypes = [vp, i32]
     for name in EXPORTS:
         f = getattr(L, name)
         if name not in ("pr_destroy", "pr_last_error"):
@@ -319,15 +323,25 @@ class Context:
 
     def run_batch(self, sims, precision="fp32", stream=None):
         """sims: list of (geom, src, tallies, first, n)."""
-        arr = (pr_sim * len(sims))()
-        for i, (g, sr, ts, first, n) in enumerate(sims):
-            arr[i].geom, arr[i].src, arr[i].n_tallies = g, sr, len(ts)
-            for j, t in enumerate(ts):
-                arr[i].tallies[j] = t
-            arr[i].first_history, arr[i].n = first, n
+        arr = self._sims(sims)
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         st = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(self.lib.pr_run_batch(self.h, arr, len(sims), prec, st))
+
+    def prepare_batch(self, sims, stride, precision="fp32") -> int:
+        """Upload a batch once (sims as for run_batch); each run_prepared advances its ids by stride."""
+        arr = self._sims(sims)
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        out = C.c_int32()
+        self._check(self.lib.pr_prepare_batch(self.h, arr, len(sims), prec, stride, C.byref(out)))
+        return out.value
+
+    def run_prepared(self, batch: int, stream=None):
+        st = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(self.lib.pr_run_prepared(self.h, batch, st))
+
+    def release_batch(self, batch: int):
+        self._check(self.lib.pr_release_batch(self.h, batch))
 
     def get_tuning(self) -> dict:
         t = pr_tuning()

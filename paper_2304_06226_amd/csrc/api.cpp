@@ -63,8 +63,9 @@ struct Geometry {
 struct Tally {
     pr_tally_desc desc;
     uint64_t nbins = 0;
-    double* dev = nullptr;   // [sum_w | sum_w2]
-    uint64_t n_hist = 0;
+    double* dev = nullptr;   // (sum_w, sum_w2) interleaved per bin
+    uint64_t n_hist = 0;     // histories of host-issued runs
+    unsigned long long* dev_nhist = nullptr;   // histories counted on the device (prepared batches)
 };
 
 // Per-call batch descriptors (simulations, tallies, key bases): a small ring of
@@ -79,6 +80,29 @@ struct DescSlot {
 };
 
 }  // namespace
+
+// One class of a batched run, planned on the host: descriptors and launch shape.
+struct ClassPlan {
+    std::vector<SimDev> sd;
+    std::vector<TallyDev> td;
+    std::vector<uint64_t> kb;
+    BatchParams B{};        // device pointers set by bind_plan
+    bool slds = false, grid_nav = false;
+    int grid = 1, block = 256;
+    size_t b_sims = 0, b_tal = 0, total = 0;   // descriptor byte layout [sims | tallies | key bases]
+};
+
+// A batch uploaded once for repeated, capturable runs.
+struct PreparedBatch {
+    bool live = false;
+    std::vector<ClassPlan> plans;
+    std::vector<void*> desc;                  // device descriptors per class
+    unsigned long long* shift = nullptr;      // device: history-id offset of the next run
+    uint64_t stride = 0;
+    unsigned long long** hist_ptrs = nullptr; // device: history counters of the tallies involved
+    unsigned long long* hist_add = nullptr;   // device: histories added to each per run
+    int nh = 0;
+};
 
 struct pr_ctx {
     int device = -1;
@@ -106,6 +130,7 @@ struct pr_ctx {
     uint64_t scratch_bins = 0;
     unsigned long long* scratch_stats = nullptr;
     int next_slot = 0;
+    std::vector<PreparedBatch> prepared;
 };
 
 namespace {
@@ -276,6 +301,21 @@ int upload(pr_ctx* c, void** dst, const std::vector<T>& v) {
     return PR_OK;
 }
 
+void free_prepared(PreparedBatch& pb) {
+    for (void* d : pb.desc)
+        if (d) (void)hipFree(d);
+    pb.desc.clear();
+    pb.plans.clear();
+    if (pb.shift) (void)hipFree(pb.shift);
+    if (pb.hist_ptrs) (void)hipFree(pb.hist_ptrs);
+    if (pb.hist_add) (void)hipFree(pb.hist_add);
+    pb.shift = nullptr;
+    pb.hist_ptrs = nullptr;
+    pb.hist_add = nullptr;
+    pb.nh = 0;
+    pb.live = false;
+}
+
 void free_geometry(Geometry& g) {
     void** ps[] = {&g.vols_d, &g.mats_d, &g.fams_d, &g.vols_f, &g.mats_f, &g.fams_f, &g.children_d,
                    &g.grids_d, &g.grids_f, &g.cell_start_d, &g.cell_items_d, &g.boxes_d, &g.boxes_f};
@@ -356,7 +396,9 @@ constexpr int kGridMinDaughters = 8;   // at most 7 daughters are scanned as ste
 
 int set_device(pr_ctx* c) {
     if (c->device < 0) return fail(c, PR_EDEVICE, "context has no device (created with hip_device = -1)");
-    HIPCHK(c, hipSetDevice(c->device));
+    int cur = -1;
+    HIPCHK(c, hipGetDevice(&cur));
+    if (cur != c->device) HIPCHK(c, hipSetDevice(c->device));
     return PR_OK;
 }
 
@@ -407,8 +449,11 @@ extern "C" void pr_destroy(pr_ctx* c) {
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();
         for (auto& g : c->geoms) free_geometry(g);
-        for (auto& t : c->tallies)
+        for (auto& t : c->tallies) {
             if (t.dev) (void)hipFree(t.dev);
+            if (t.dev_nhist) (void)hipFree(t.dev_nhist);
+        }
+        for (auto& pb : c->prepared) free_prepared(pb);
         if (c->stats) (void)hipFree(c->stats);
         if (c->counter) (void)hipFree(c->counter);
         if (c->scratch) (void)hipFree(c->scratch);
@@ -1042,7 +1087,14 @@ extern "C" int pr_read_tally(pr_ctx* c, int32_t tally, double* sw, double* sw2, 
     const Tally& T = c->tallies[tally];
     if ((sw || sw2) && nbins < T.nbins)
         return fail(c, PR_EWORKSPACE, "tally %d has %llu bins, buffer holds %zu", tally, (unsigned long long)T.nbins, nbins);
-    if (n_hist) *n_hist = T.n_hist;
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    if (n_hist) {
+        unsigned long long d = 0;
+        if (T.dev_nhist) HIPCHK(c, hipMemcpy(&d, T.dev_nhist, sizeof(d), hipMemcpyDeviceToHost));
+        *n_hist = T.n_hist + d;
+    }
     return pr_read_tally_range(c, tally, 0, (sw || sw2) ? T.nbins : 0, sw, sw2, stream);
 }
 
@@ -1053,6 +1105,7 @@ extern "C" int pr_reset_tally(pr_ctx* c, int32_t tally, void* stream) {
     int rc = set_device(c);
     if (rc) return rc;
     hipError_t e = zero_f64(T.dev, 2 * T.nbins, (hipStream_t)stream);
+    if (e == hipSuccess && T.dev_nhist) e = zero_u64(T.dev_nhist, 1, (hipStream_t)stream);
     if (e != hipSuccess) return hipfail(c, e, "zeroing tally");
     T.n_hist = 0;
     return PR_OK;
@@ -1127,9 +1180,10 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
 // batched runs
 // =========================================================================
 
-// One persistent launch over the simulations idx of one class.
-static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>& idx, bool slds, bool grid_nav,
-                           hipStream_t st, bool trial = false) {
+// Plan one class of simulations idx: per-simulation descriptors, tally
+// entries, bin-cache key bases, LDS budget and launch shape.
+static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>& idx, bool slds, bool grid_nav,
+                            bool trial, ClassPlan& P) {
     // LDS budgets: a simulation's tallies are privatised when they fit the tally
     // region, else they go through the bin cache whose values share that region
     const int priv_cap = c->lds_tally_budget / 8;
@@ -1138,9 +1192,11 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         while ((1 << (cache_bits + 1)) <= c->bin_cache_slots) ++cache_bits;
     const int nslots = c->bin_cache_slots > 0 ? (1 << cache_bits) : 0;
     const int ns = (int)idx.size();
-    std::vector<SimDev> sd(ns);
-    std::vector<TallyDev> td;
-    std::vector<uint64_t> kb;
+    P.sd.assign(ns, SimDev{});
+    P.td.clear();
+    P.kb.clear();
+    P.slds = slds;
+    P.grid_nav = grid_nav;
     const uint64_t sc_size = (uint64_t)c->superchunk;
     uint64_t scs = 0;
     int tally_doubles = 0, scene_bytes = 0;
@@ -1148,7 +1204,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
     for (int q = 0; q < ns; ++q) {
         const pr_sim& sm = sims[idx[q]];
         const Geometry& g = c->geoms[sm.geom];
-        SimDev& o = sd[q];
+        SimDev& o = P.sd[q];
         memset(&o, 0, sizeof(o));
         o.vols = (const VolT<float>*)g.vols_f;
         o.mats = (const MatT<float>*)g.mats_f;
@@ -1168,7 +1224,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         o.scene_in_lds = slds ? 1 : 0;
         o.kinds = g.kinds;
         if (slds) scene_bytes = std::max(scene_bytes, g.scene_lds_bytes);
-        o.tally_begin = (int32_t)td.size();
+        o.tally_begin = (int32_t)P.td.size();
         o.tally_count = sm.n_tallies;
         int64_t need = 0;
         for (int t = 0; t < sm.n_tallies; ++t) need += 2 * (int64_t)c->tallies[sm.tallies[t]].nbins;
@@ -1188,8 +1244,8 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
                 T.lds_offset = (int32_t)loff;
                 loff += 2 * T.total;
             }
-            td.push_back(T);
-            kb.push_back(key);
+            P.td.push_back(T);
+            P.kb.push_back(key);
             key += (uint64_t)T.total;
         }
         o.first = sm.first_history;
@@ -1198,40 +1254,17 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
         scs += (sm.n + sc_size - 1) / sc_size;
         make_source_dev(c->srcs[sm.src], o.src);
     }
-    if (scs == 0) return PR_OK;
     if (any_cache) tally_doubles = std::max(tally_doubles, 2 * nslots);
-    if (td.empty()) kb.push_back(0);
-
-    // descriptor slot: [sims | tallies | key bases], 256-byte aligned parts
+    if (P.td.empty()) P.kb.push_back(0);
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t b_sims = al(sd.size() * sizeof(SimDev)), b_tal = al(std::max<size_t>(1, td.size()) * sizeof(TallyDev));
-    const size_t b_kb = al(kb.size() * sizeof(uint64_t)), total = b_sims + b_tal + b_kb;
-    DescSlot& sl = c->slots[c->next_slot];
-    c->next_slot = (c->next_slot + 1) % 4;
-    if (sl.used) HIPCHK(c, hipEventSynchronize(sl.done));
-    if (sl.bytes < total) {
-        if (sl.dev) (void)hipFree(sl.dev);
-        if (sl.host) (void)hipHostFree(sl.host);
-        sl.dev = sl.host = nullptr;
-        sl.bytes = 0;
-        HIPCHK(c, hipMalloc(&sl.dev, total));
-        HIPCHK(c, hipHostMalloc(&sl.host, total, hipHostMallocDefault));
-        sl.bytes = total;
-    }
-    if (!sl.done) HIPCHK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    char* h = (char*)sl.host;
-    memcpy(h, sd.data(), sd.size() * sizeof(SimDev));
-    if (!td.empty()) memcpy(h + b_sims, td.data(), td.size() * sizeof(TallyDev));
-    memcpy(h + b_sims + b_tal, kb.data(), kb.size() * sizeof(uint64_t));
-    HIPCHK(c, hipMemcpyAsync(sl.dev, sl.host, total, hipMemcpyHostToDevice, st));
+    P.b_sims = al(P.sd.size() * sizeof(SimDev));
+    P.b_tal = al(std::max<size_t>(1, P.td.size()) * sizeof(TallyDev));
+    P.total = P.b_sims + P.b_tal + al(P.kb.size() * sizeof(uint64_t));
 
-    BatchParams B;
+    BatchParams& B = P.B;
     memset(&B, 0, sizeof(B));
-    B.sims = (const SimDev*)sl.dev;
-    B.tallies = (const TallyDev*)((char*)sl.dev + b_sims);
-    B.tally_key_base = (const uint64_t*)((char*)sl.dev + b_sims + b_tal);
     B.nsims = ns;
-    B.ntallies = (int32_t)td.size();
+    B.ntallies = (int32_t)P.td.size();
     B.lds_tally_doubles = tally_doubles;
     B.cache_bits = any_cache ? cache_bits : 0;
     B.lds_scene_bytes = scene_bytes;
@@ -1242,14 +1275,56 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
     B.seed = c->seed;
     B.stats = trial ? c->scratch_stats : c->stats;
     B.counter = c->counter;
+    B.shift = nullptr;
     const int lds = batch_lds_bytes(B);
     if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
-    int block = c->mixed_block;
-    if (grid_nav && slds) block = grid_block(c, [&](int b) { return batch_occupancy(B, slds, grid_nav, b); });
-    const int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, block);
+    P.block = c->mixed_block;
+    if (grid_nav && slds) P.block = grid_block(c, [&](int b) { return batch_occupancy(B, slds, grid_nav, b); });
+    const int per_cu =
+        c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, P.block);
     uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, scs);
-    if (grid < 1) grid = 1;
-    hipError_t e = launch_batch(B, slds, grid_nav, (int)grid, block, st);
+    P.grid = (int)std::max<uint64_t>(grid, 1);
+    return PR_OK;
+}
+
+// host image of a plan's descriptors, laid out as on the device
+static void pack_plan(const ClassPlan& P, char* h) {
+    memcpy(h, P.sd.data(), P.sd.size() * sizeof(SimDev));
+    if (!P.td.empty()) memcpy(h + P.b_sims, P.td.data(), P.td.size() * sizeof(TallyDev));
+    memcpy(h + P.b_sims + P.b_tal, P.kb.data(), P.kb.size() * sizeof(uint64_t));
+}
+
+static void bind_plan(ClassPlan& P, void* dev) {
+    P.B.sims = (const SimDev*)dev;
+    P.B.tallies = (const TallyDev*)((char*)dev + P.b_sims);
+    P.B.tally_key_base = (const uint64_t*)((char*)dev + P.b_sims + P.b_tal);
+}
+
+// One persistent launch over the simulations idx of one class.
+static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>& idx, bool slds, bool grid_nav,
+                           hipStream_t st, bool trial = false) {
+    ClassPlan P;
+    int rc = plan_batch_class(c, sims, idx, slds, grid_nav, trial, P);
+    if (rc) return rc;
+    if (P.B.total_superchunks == 0) return PR_OK;
+    // descriptors go through a ring slot: pinned staging, then one async copy
+    DescSlot& sl = c->slots[c->next_slot];
+    c->next_slot = (c->next_slot + 1) % 4;
+    if (sl.used) HIPCHK(c, hipEventSynchronize(sl.done));
+    if (sl.bytes < P.total) {
+        if (sl.dev) (void)hipFree(sl.dev);
+        if (sl.host) (void)hipHostFree(sl.host);
+        sl.dev = sl.host = nullptr;
+        sl.bytes = 0;
+        HIPCHK(c, hipMalloc(&sl.dev, P.total));
+        HIPCHK(c, hipHostMalloc(&sl.host, P.total, hipHostMallocDefault));
+        sl.bytes = P.total;
+    }
+    if (!sl.done) HIPCHK(c, hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    pack_plan(P, (char*)sl.host);
+    HIPCHK(c, hipMemcpyAsync(sl.dev, sl.host, P.total, hipMemcpyHostToDevice, st));
+    bind_plan(P, sl.dev);
+    hipError_t e = launch_batch(P.B, slds, grid_nav, P.grid, P.block, st);
     if (e != hipSuccess) return hipfail(c, e, "batch kernel launch");
     HIPCHK(c, hipEventRecord(sl.done, st));
     sl.used = true;
@@ -1292,15 +1367,21 @@ extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_
 }
 
 // simulations fall into classes by scene placement (LDS or global) and grid
-// navigation; each non-empty class runs as one persistent launch
-static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream_t stream, bool trial) {
-    int rc;
+// navigation (class = staged + 2 * grid); each non-empty class runs as one
+// persistent launch
+static std::vector<int> batch_classes(const pr_ctx* c, const pr_sim* sims, int32_t nsims) {
     std::vector<int> cls(nsims);
     for (int i = 0; i < nsims; ++i) {
         const Geometry& g = c->geoms[sims[i].geom];
         const bool grid = !g.gd.empty();
         cls[i] = (g.scene_lds_bytes <= (grid ? c->lds_grid_budget : c->lds_scene_budget) ? 1 : 0) + (grid ? 2 : 0);
     }
+    return cls;
+}
+
+static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream_t stream, bool trial) {
+    int rc;
+    const std::vector<int> cls = batch_classes(c, sims, nsims);
     for (int k = 0; k < 4; ++k) {
         std::vector<int> idx;
         for (int i = 0; i < nsims; ++i)
@@ -1308,6 +1389,117 @@ static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream
         if (idx.empty()) continue;
         if ((rc = run_batch_class(c, sims, idx, (k & 1) != 0, (k & 2) != 0, stream, trial))) return rc;
     }
+    return PR_OK;
+}
+
+// =========================================================================
+// prepared batches
+// =========================================================================
+
+extern "C" int pr_prepare_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_t precision, uint64_t stride,
+                                int32_t* batch) {
+    if (!c || !sims || !batch) return fail(c, PR_EINVAL, "null argument");
+    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
+    if (precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "batched runs use the PR_FP32_MIXED policy");
+    if (c->device < 0) return fail(c, PR_EDEVICE, "context has no device");
+    int rc = set_device(c);
+    if (rc) return rc;
+    if ((rc = validate_sims(c, sims, nsims))) return rc;
+    PreparedBatch pb;
+    pb.stride = stride;
+    auto bail = [&](int code) {
+        free_prepared(pb);
+        return code;
+    };
+    const std::vector<int> cls = batch_classes(c, sims, nsims);
+    for (int k = 0; k < 4; ++k) {
+        std::vector<int> idx;
+        for (int i = 0; i < nsims; ++i)
+            if (cls[i] == k) idx.push_back(i);
+        if (idx.empty()) continue;
+        ClassPlan P;
+        if ((rc = plan_batch_class(c, sims, idx, (k & 1) != 0, (k & 2) != 0, false, P))) return bail(rc);
+        if (P.B.total_superchunks == 0) continue;
+        std::vector<char> host(P.total, 0);
+        pack_plan(P, host.data());
+        void* dev = nullptr;
+        hipError_t e = hipMalloc(&dev, P.total);
+        if (e != hipSuccess) return bail(hipfail(c, e, "prepared batch descriptors"));
+        pb.desc.push_back(dev);
+        if ((e = hipMemcpy(dev, host.data(), P.total, hipMemcpyHostToDevice)) != hipSuccess)
+            return bail(hipfail(c, e, "prepared batch descriptors"));
+        bind_plan(P, dev);
+        pb.plans.push_back(std::move(P));
+    }
+    // history-id offset and per-tally history counts live on the device
+    hipError_t e = hipMalloc(&pb.shift, sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemset(pb.shift, 0, sizeof(unsigned long long));
+    if (e != hipSuccess) return bail(hipfail(c, e, "prepared batch offset"));
+    std::map<int32_t, unsigned long long> per_tally;
+    for (int i = 0; i < nsims; ++i)
+        for (int t = 0; t < sims[i].n_tallies; ++t) per_tally[sims[i].tallies[t]] += sims[i].n;
+    std::vector<unsigned long long*> ptrs;
+    std::vector<unsigned long long> adds;
+    for (auto& kv : per_tally) {
+        Tally& T = c->tallies[kv.first];
+        if (!T.dev_nhist) {
+            if ((e = hipMalloc(&T.dev_nhist, sizeof(unsigned long long))) != hipSuccess ||
+                (e = hipMemset(T.dev_nhist, 0, sizeof(unsigned long long))) != hipSuccess) {
+                T.dev_nhist = nullptr;
+                return bail(hipfail(c, e, "tally history counter"));
+            }
+        }
+        ptrs.push_back(T.dev_nhist);
+        adds.push_back(kv.second);
+    }
+    pb.nh = (int)ptrs.size();
+    if (pb.nh > 0) {
+        if ((e = hipMalloc(&pb.hist_ptrs, ptrs.size() * sizeof(void*))) != hipSuccess ||
+            (e = hipMalloc(&pb.hist_add, adds.size() * sizeof(unsigned long long))) != hipSuccess ||
+            (e = hipMemcpy(pb.hist_ptrs, ptrs.data(), ptrs.size() * sizeof(void*), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(pb.hist_add, adds.data(), adds.size() * sizeof(unsigned long long), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+            return bail(hipfail(c, e, "prepared batch history counters"));
+    }
+    for (auto& P : pb.plans) P.B.shift = pb.shift;
+    pb.live = true;
+    int id = -1;
+    for (size_t i = 0; i < c->prepared.size(); ++i)
+        if (!c->prepared[i].live) { id = (int)i; break; }
+    if (id < 0) {
+        id = (int)c->prepared.size();
+        c->prepared.emplace_back();
+    }
+    c->prepared[id] = std::move(pb);
+    *batch = id;
+    return PR_OK;
+}
+
+extern "C" int pr_run_prepared(pr_ctx* c, int32_t batch, void* stream) {
+    if (!c) return PR_EINVAL;
+    if (batch < 0 || batch >= (int)c->prepared.size() || !c->prepared[batch].live)
+        return fail(c, PR_ENOTFOUND, "prepared batch %d unknown", batch);
+    int rc = set_device(c);
+    if (rc) return rc;
+    PreparedBatch& pb = c->prepared[batch];
+    const hipStream_t st = (hipStream_t)stream;
+    for (const ClassPlan& P : pb.plans) {
+        hipError_t e = launch_batch(P.B, P.slds, P.grid_nav, P.grid, P.block, st);
+        if (e != hipSuccess) return hipfail(c, e, "batch kernel launch");
+    }
+    hipError_t e = prepared_tail(pb.hist_ptrs, pb.hist_add, pb.nh, pb.shift, pb.stride, st);
+    if (e != hipSuccess) return hipfail(c, e, "prepared batch tail");
+    return PR_OK;
+}
+
+extern "C" int pr_release_batch(pr_ctx* c, int32_t batch) {
+    if (!c) return PR_EINVAL;
+    if (batch < 0 || batch >= (int)c->prepared.size() || !c->prepared[batch].live)
+        return fail(c, PR_ENOTFOUND, "prepared batch %d unknown", batch);
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIPCHK(c, hipDeviceSynchronize());
+    free_prepared(c->prepared[batch]);
     return PR_OK;
 }
 

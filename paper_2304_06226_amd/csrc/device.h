@@ -198,6 +198,7 @@ struct BatchParams {
     uint64_t total_superchunks, superchunk, chunk, seed;
     unsigned long long* stats;
     unsigned long long* counter;
+    const unsigned long long* shift;  // prepared batches: history-id offset added to every simulation (or null)
 };
 
 // -------------------------------------------------------------------------

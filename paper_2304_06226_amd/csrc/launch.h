@@ -16,6 +16,8 @@ int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block);
 int batch_lds_bytes(const BatchParams& B);
 int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int nci, int grid);
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st);
+hipError_t prepared_tail(unsigned long long* const* hist, const unsigned long long* add, int n,
+                         unsigned long long* shift, unsigned long long stride, hipStream_t st);
 hipError_t zero_f64(double* p, uint64_t n, hipStream_t st);
 
 }  // namespace prk

@@ -407,7 +407,7 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
 // the block's waves run the histories of the current super-chunk
 template <bool SLDS, bool GRID>
 __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDev& sd, BlockCtl& ctl, char* scene,
-                                               double* ltal, uint32_t* ckeys, Counters& cnt) {
+                                               double* ltal, uint32_t* ckeys, Counters& cnt, unsigned long long shift) {
     SceneT<float> S;
     if (SLDS) {
         const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
@@ -464,7 +464,8 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<float, false, GRID>(s, sd.src, S, B.seed, sd.first + cnext + (unsigned long long)rank, 0);
+                        source<float, false, GRID>(s, sd.src, S, B.seed, sd.first + shift + cnext + (unsigned long long)rank,
+                                                   0);
                         pending = s.term != 0;
                     }
                 }
@@ -493,6 +494,7 @@ __global__ __launch_bounds__(GRID ? 768 : 256) __attribute__((amdgpu_waves_per_e
     char* scene = (char*)ckeys + align16(nslots * 4);
     Counters cnt = {};
     int staged = -1;
+    const unsigned long long shift = B.shift ? *B.shift : 0ull;
     for (;;) {
         if (threadIdx.x == 0) {
             const unsigned long long j = atomicAdd(B.counter, 1ull);
@@ -534,11 +536,20 @@ __global__ __launch_bounds__(GRID ? 768 : 256) __attribute__((amdgpu_waves_per_e
             __syncthreads();
             staged = sim;
         }
-        run_superchunk<SLDS, GRID>(B, sd, ctl, scene, ltal, ckeys, cnt);
+        run_superchunk<SLDS, GRID>(B, sd, ctl, scene, ltal, ckeys, cnt, shift);
         __syncthreads();
     }
     if (staged >= 0) flush_block(B, B.sims[staged], ltal, ckeys);
     flush_counters(cnt, B.stats);
+}
+
+// End of a prepared batch run: add each tally's histories to its device
+// history count, then advance the history-id offset by the stride.
+__global__ void k_prepared_tail(unsigned long long* const* hist, const unsigned long long* add, int n,
+                                unsigned long long* shift, unsigned long long stride) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) *hist[i] += add[i];
+    if (i == 0) *shift += stride;
 }
 
 __global__ void k_zero_u64(unsigned long long* p, int n) {
@@ -640,6 +651,13 @@ int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block) {
     }
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
+}
+
+hipError_t prepared_tail(unsigned long long* const* hist, const unsigned long long* add, int n,
+                         unsigned long long* shift, unsigned long long stride, hipStream_t st) {
+    hipLaunchKernelGGL(k_prepared_tail, dim3((n + 255) / 256 > 0 ? (n + 255) / 256 : 1), dim3(256), 0, st, hist, add, n,
+                       shift, stride);
+    return hipGetLastError();
 }
 
 hipError_t zero_u64(unsigned long long* p, int n, hipStream_t st) {

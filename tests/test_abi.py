@@ -125,3 +125,15 @@ def test_tuning_validation(ctx):
     assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
     ctx.set_tuning(refill_threshold=8)
     assert ctx.get_tuning()["refill_threshold"] == 8
+
+
+def test_prepared_batch_validation(ctx):
+    p = W.config0()
+    sim = B.Simulation(ctx, p)
+    desc = [(sim.geom, sim.src, sim.tallies, 0, 1000)]
+    # a validation-only context has no device to hold a prepared batch
+    assert code_of(lambda: ctx.prepare_batch(desc, stride=1000)) == -5
+    assert code_of(lambda: ctx.prepare_batch(desc, stride=1000, precision="fp64")) == -1
+    assert code_of(lambda: ctx.prepare_batch([], stride=1000)) == -1
+    assert code_of(lambda: ctx.run_prepared(0, stream=0)) == -2
+    assert code_of(lambda: ctx.release_batch(3)) == -2
