@@ -57,7 +57,7 @@ enum { PR_MONO = 0, PR_UNIFORM = 1, PR_MAXWELL = 2 };
 enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2 };
 enum { PR_FILT_ALL = 0, PR_FILT_UNSCATTERED = 1, PR_FILT_SCATTERED = 2, PR_FILT_NSCAT_EQ = 3 };
 enum { PR_Q_THETA2 = 0, PR_Q_LAMBDA = 1, PR_Q_X = 2, PR_Q_Y = 3, PR_Q_Z = 4, PR_Q_DIVX = 5, PR_Q_DIVY = 6,
-       PR_Q_NSCAT = 7 };
+       PR_Q_NSCAT = 7, PR_Q_Q = 8 };
 enum { PR_MIRROR_LINEAR = 0, PR_MIRROR_TANH = 1 };
 enum { PR_ACC_FP64 = 0, PR_ACC_KAHAN_FP32 = 1 };
 /* precision policies of pr_run_histories */
@@ -153,7 +153,10 @@ typedef struct {
 
 typedef struct {
     int32_t quantity;         /* PR_Q_*: 2theta = acos(u.beam) deg; lambda A; x,y,z mm;
-                                 div_x = atan2(u_x, u_z) deg; div_y = atan2(u_y, u_z) deg; n_scat */
+                                 div_x = atan2(u_x, u_z) deg; div_y = atan2(u_y, u_z) deg; n_scat;
+                                 Q = |k_out - k_beam| = (4 pi / lambda) sqrt((1 - u.beam) / 2) 1/A,
+                                 the momentum transfer of elastic scattering out of the beam direction
+                                 (the DeltaMomentum scorer, Table tableScorer) */
     int32_t nbins;            /* >= 1 */
     double lo, hi;            /* hi > lo; bin = floor((x - lo) / (hi - lo) nbins); x = hi goes to the
                                  last bin; values outside [lo, hi] are not scored */

@@ -462,6 +462,17 @@ static void score(const orc_problem* P, acc_t* acc, int term, int det_vol, const
             case ORC_Q_DIVX: x = atan2(u[0], u[2]) * 180.0 / PI; break;
             case ORC_Q_DIVY: x = atan2(u[1], u[2]) * 180.0 / PI; break;
             case ORC_Q_NSCAT: x = (double)nscat; break;
+            case ORC_Q_Q: {
+                /* momentum transfer of elastic scattering from the beam direction to u:
+                   |k_out - k_in| = 2 k sin(alpha / 2), k = 2 pi / lambda, with
+                   sin(alpha / 2) = sqrt((1 - cos alpha) / 2) (DeltaMomentum scorer) */
+                double bn = sqrt(t->beam[0] * t->beam[0] + t->beam[1] * t->beam[1] + t->beam[2] * t->beam[2]);
+                double c = (u[0] * t->beam[0] + u[1] * t->beam[1] + u[2] * t->beam[2]) / bn;
+                if (c > 1.0) c = 1.0;
+                if (c < -1.0) c = -1.0;
+                x = 4.0 * PI / lam * sqrt((1.0 - c) / 2.0);
+                break;
+            }
             }
             int b = tally_bin(t, x, a);
             if (b < 0) { ok = 0; break; }

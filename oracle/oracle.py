@@ -24,7 +24,7 @@ SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
 TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
-QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7}
+QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8}
 MIRROR = {"linear": 0, "tanh": 1}
 
 END_ESCAPE, END_ABSORB, END_KILL, END_DETECT, END_CAPPED, END_OUTSIDE = 1, 2, 3, 4, 5, 6

@@ -787,7 +787,7 @@ extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
     uint64_t nb = 1;
     for (int a = 0; a < d->naxes; ++a) {
         const pr_tally_axis& x = d->axes[a];
-        if (x.quantity < PR_Q_THETA2 || x.quantity > PR_Q_NSCAT) return fail(c, PR_EINVAL, "tally.axes[%d].quantity invalid", a);
+        if (x.quantity < PR_Q_THETA2 || x.quantity > PR_Q_Q) return fail(c, PR_EINVAL, "tally.axes[%d].quantity invalid", a);
         if (x.nbins < 1) return fail(c, PR_EINVAL, "tally.axes[%d].nbins must be >= 1", a);
         if (!(std::isfinite(x.lo) && std::isfinite(x.hi) && x.hi > x.lo))
             return fail(c, PR_EINVAL, "tally.axes[%d] needs lo < hi", a);
@@ -796,7 +796,8 @@ extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
     }
     double bn = std::sqrt(d->beam[0] * d->beam[0] + d->beam[1] * d->beam[1] + d->beam[2] * d->beam[2]);
     for (int a = 0; a < d->naxes; ++a)
-        if (d->axes[a].quantity == PR_Q_THETA2 && !(bn > 0)) return fail(c, PR_EINVAL, "tally.beam must be non-zero");
+        if ((d->axes[a].quantity == PR_Q_THETA2 || d->axes[a].quantity == PR_Q_Q) && !(bn > 0))
+            return fail(c, PR_EINVAL, "tally.beam must be non-zero");
     Tally t;
     t.desc = *d;
     t.nbins = nb;

@@ -1071,6 +1071,13 @@ __device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>&
         case PR_Q_Z: x = s.p[2]; break;
         case PR_Q_DIVX: x = M<R>::atan2_deg(s.u[0], s.u[2]); break;
         case PR_Q_DIVY: x = M<R>::atan2_deg(s.u[1], s.u[2]); break;
+        case PR_Q_Q: {
+            // momentum transfer from the beam direction: (4 pi / lambda) sin(alpha / 2)
+            R c = s.u[0] * (R)T.beam[0] + s.u[1] * (R)T.beam[1] + s.u[2] * (R)T.beam[2];
+            c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
+            x = M<R>::div_((R)(4.0 * 3.14159265358979323846), s.lam) * M<R>::sqrt_(((R)1 - c) / (R)2);
+            break;
+        }
         default: x = (R)s.nscat; break;
         }
         R lo = (R)T.lo[a], hi = (R)T.hi[a];

@@ -34,7 +34,7 @@ SOURCES = ("pencil", "rect", "rect_divergent")
 SPECTRA = ("mono", "uniform", "maxwell")
 TRIGGERS = ("escape", "absorb", "detect")
 FILTERS = ("all", "unscattered", "scattered", "nscat_eq")
-QUANTITIES = ("theta2", "lambda", "x", "y", "z", "div_x", "div_y", "nscat")
+QUANTITIES = ("theta2", "lambda", "x", "y", "z", "div_x", "div_y", "nscat", "q")
 MIRROR_MODELS = ("linear", "tanh")
 
 

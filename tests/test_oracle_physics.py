@@ -453,3 +453,87 @@ def test_imaging_unscattered_transmission_closed_form():
             assert abs((got[g].sum() - expect[g].sum()) / np.sqrt(v)) < 4.5
     # the tally's unscattered image holds exactly those weights
     assert r.sumw[1].sum() == pytest.approx(got.sum())
+
+
+# ---------------------------------------------------------------------------
+# Momentum-transfer tally (DeltaMomentum scorer) and process removal
+# ---------------------------------------------------------------------------
+
+def _q_problem(mat, lam, qmax, nbins, filt="nscat_eq", arg=1):
+    p = pencil_problem(mat, lam=lam)
+    p.tallies = [W.Tally(trigger="escape", filter=filt, filter_arg=arg, axes=[W.Axis("q", 0.0, qmax, nbins)])]
+    return p
+
+
+@pytest.mark.parametrize("lam", [1.8, 1.2])
+def test_q_tally_single_bragg_peaks_at_2pi_over_d(lam):
+    """A single coherent scattering transfers Q = 2 k sin(theta) = 2 pi / d_j for
+    any wavelength (Bragg's law): the single-scattering Q tally has weight only in
+    bins holding some 2 pi / d_j of an active family (2 d_j > lambda), with
+    weights proportional to m_j d_j F2_j."""
+    a = 4.0
+    base = W.sample_material()
+    mat = dilute(dataclasses.replace(base, sigma_inc=0.0, sigma_abs_ref=0.0), 0.1)
+    qmax, nb = 20.0, 20000
+    r = O.run(_q_problem(mat, lam, qmax, nb), n=400_000, threads=8)
+    sw = r.sumw[0]
+    assert sw.sum() > 3000
+    d_f, m_f, _ = W.fcc_families(a, 0.5)
+    act = 2 * d_f > lam
+    q_peaks = 2 * np.pi / d_f[act]
+    width = qmax / nb
+    centers = (np.arange(nb) + 0.5) * width
+    hit = np.nonzero(sw)[0]
+    dist = np.min(np.abs(centers[hit][:, None] - q_peaks[None, :]), axis=1)
+    assert dist.max() <= width, dist.max()
+    # weight per distinct d against m d F2
+    wts = (m_f * d_f * mat.f2)[act]
+    dd = d_f[act]
+    ud = np.unique(np.round(dd, 12))
+    probs = np.array([wts[np.isclose(dd, x)].sum() for x in ud])
+    probs /= probs.sum()
+    qd = 2 * np.pi / ud
+    which = np.argmin(np.abs(centers[hit][:, None] - qd[None, :]), axis=1)
+    counts = np.bincount(which, weights=sw[hit], minlength=len(ud))   # unit weights: counts
+    assert stats.chisquare(counts, probs * counts.sum()).pvalue > 1e-3
+
+
+def test_q_tally_isotropic_closed_form():
+    """Isotropic single scattering: cos(alpha) is uniform, so with s = Q lambda / (4 pi)
+    P(s <= x) = x^2 and a Q bin [a, b] holds (b^2 - a^2) / Q_max^2 of the entries."""
+    lam = 1.8
+    mat = dilute(W.Material(number_density=0.06, sigma_inc=5.0, sigma_abs_ref=0.0), 0.1)
+    qmax = 4 * np.pi / lam
+    nb = 24
+    r = O.run(_q_problem(mat, lam, qmax, nb), n=600_000, threads=8)
+    counts = r.sumw[0]
+    assert counts.sum() > 3000
+    e = np.linspace(0.0, qmax, nb + 1)
+    pb = (e[1:] ** 2 - e[:-1] ** 2) / qmax ** 2
+    assert stats.chisquare(counts, pb * counts.sum()).pvalue > 1e-3
+
+
+def test_bias_factor_zero_removes_the_process():
+    """A bias factor of 0 removes that process from the physics (not a variance
+    reduction): with abs_bias = 0 nothing is absorbed and the transmission is
+    exp(-Sigma_s L); with scatter_bias = 0 nothing scatters, the transmission is
+    exp(-Sigma_a L) and the rest is absorbed.  The remaining process is unbiased,
+    so every weight stays exactly 1."""
+    lam, L = 1.8, 10.0
+    base = W.sample_material()
+    sa = 0.06 * 0.1 * 2.0 * lam / 1.798
+    ss = 0.06 * 0.1 * 5.0 + sigma_coh_bruteforce(base, 4.0, lam)
+    n = 300_000
+    r = O.run(pencil_problem(base.biased(abs_bias=0.0), lam=lam), n=n, threads=8, records=True)
+    assert r.stats["absorbed"] == 0
+    assert np.all(r.records["w"] == 1.0)
+    t = r.mean(1)[0]
+    exp_t = np.exp(-ss * L)
+    assert abs(t - exp_t) < 4 * np.sqrt(exp_t * (1 - exp_t) / n)
+    r = O.run(pencil_problem(base.biased(scatter_bias=0.0), lam=lam), n=n, threads=8, records=True)
+    assert np.all(r.records["n_scat"] == 0)
+    assert np.all(r.records["w"] == 1.0)
+    t = r.mean(1)[0]
+    exp_t = np.exp(-sa * L)
+    assert abs(t - exp_t) < 4 * np.sqrt(exp_t * (1 - exp_t) / n)
+    assert abs(r.stats["absorbed"] / n - (1 - exp_t)) < 4 * np.sqrt(exp_t * (1 - exp_t) / n)
