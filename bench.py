@@ -108,6 +108,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-paper-guide", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="re-measure the launch tuning before timing")
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
@@ -210,6 +211,16 @@ def main():
                                       "1e4-1e6 histories each, odd ones in a vessel) + 1000-box imaging, 1e7 histories"}
         print(f"[bench] batched {bms:.3f} ms/step, {batch.total_histories / bms * 1e3:.4g} histories/s",
               file=sys.stderr, flush=True)
+    if not args.no_paper_guide:
+        # the paper's m = 1 guide benchmark at its own size (1e8 neutrons), for context
+        # with the paper's only timing (about 140 s on a laptop)
+        pg = W.paper_guide()
+        ctx.set_tuning(**TUNED["paper_guide"])
+        gsim = B.Simulation(ctx, pg)
+        gms, _ = time_policy(torch, gsim, pg.n_histories, "fp32", 2, 1)
+        out["paper_guide"] = {"histories": pg.n_histories, "ms": gms, "histories_per_s": pg.n_histories / gms * 1e3,
+                              "paper_laptop_s": 140.0, "note": "the paper's timing is on other hardware: context only"}
+        print(f"[bench] paper guide 1e8: {gms:.3f} ms", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

@@ -52,7 +52,7 @@ extern "C" {
 
 /* ---- enumerations ---- */
 enum { PR_BOX = 0, PR_CYLINDER = 1, PR_CYL_SHELL = 2, PR_SPHERE = 3, PR_SPH_SHELL = 4 };
-enum { PR_PENCIL = 0, PR_RECT = 1, PR_RECT_DIVERGENT = 2 };
+enum { PR_PENCIL = 0, PR_RECT = 1, PR_RECT_DIVERGENT = 2, PR_MODERATOR = 3 };
 enum { PR_MONO = 0, PR_UNIFORM = 1, PR_MAXWELL = 2 };
 enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2 };
 enum { PR_FILT_ALL = 0, PR_FILT_UNSCATTERED = 1, PR_FILT_SCATTERED = 2, PR_FILT_NSCAT_EQ = 3 };
@@ -137,6 +137,11 @@ typedef struct {
  * PR_RECT: origin + ((u0 - 1/2) size_x, (u1 - 1/2) size_y, 0), direction dir.
  * PR_RECT_DIVERGENT: as PR_RECT, then alpha_x, alpha_y uniform in
  * [-div, div] degrees and direction ~ (tan alpha_x, tan alpha_y, 1).
+ * PR_MODERATOR (the moderator-surface guns): the position as PR_RECT on the
+ * source rectangle, then a point slit_center + ((u2 - 1/2) slit_x,
+ * (u3 - 1/2) slit_y, 0) on the slit rectangle; the direction joins the two
+ * (dir is not used; slit_center z must differ from origin z).  A uniform
+ * spectrum mean +- range is lam_lo = mean - range, lam_hi = mean + range.
  * Spectrum: PR_MONO lam0; PR_UNIFORM lambda uniform in [lam_lo, lam_hi];
  * PR_MAXWELL energy density ~ sqrt(E) exp(-E/kT), rejected to [lam_lo, lam_hi]
  * (at most 64 tries of three draws).  Draw order: position, divergence, lambda. */
@@ -149,6 +154,8 @@ typedef struct {
     double div_deg[2];        /* degrees */
     double lam0, lam_lo, lam_hi;   /* A */
     double kT;                /* eV */
+    double slit_center[3];    /* mm, PR_MODERATOR */
+    double slit_size[2];      /* mm, PR_MODERATOR */
 } pr_source_desc;
 
 typedef struct {

@@ -369,13 +369,20 @@ static void sample_source(const orc_source* s, rng_t* r, double p[3], double u[3
 {
     p[0] = s->origin[0]; p[1] = s->origin[1]; p[2] = s->origin[2];
     u[0] = s->dir[0]; u[1] = s->dir[1]; u[2] = s->dir[2];
-    if (s->kind == ORC_RECT || s->kind == ORC_RECT_DIVERGENT) {
+    if (s->kind == ORC_RECT || s->kind == ORC_RECT_DIVERGENT || s->kind == ORC_MODERATOR) {
         double a = next_u(r);
         double b = next_u(r);
         p[0] += (a - 0.5) * s->size[0];
         p[1] += (b - 0.5) * s->size[1];
     }
-    if (s->kind == ORC_RECT_DIVERGENT) {
+    if (s->kind == ORC_MODERATOR) {
+        /* moderator-surface gun: aim from the source point at a uniform point of the slit */
+        double sx = s->slit_center[0] + (next_u(r) - 0.5) * s->slit_size[0];
+        double sy = s->slit_center[1] + (next_u(r) - 0.5) * s->slit_size[1];
+        double v[3] = {sx - p[0], sy - p[1], s->slit_center[2] - p[2]};
+        double nrm = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        u[0] = v[0] / nrm; u[1] = v[1] / nrm; u[2] = v[2] / nrm;
+    } else if (s->kind == ORC_RECT_DIVERGENT) {
         double ax = (2.0 * next_u(r) - 1.0) * s->div_deg[0] * PI / 180.0;
         double ay = (2.0 * next_u(r) - 1.0) * s->div_deg[1] * PI / 180.0;
         double v[3] = {tan(ax), tan(ay), 1.0};

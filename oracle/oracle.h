@@ -34,7 +34,7 @@ extern "C" {
 #endif
 
 enum { ORC_BOX = 0, ORC_CYLINDER = 1, ORC_CYL_SHELL = 2, ORC_SPHERE = 3, ORC_SPH_SHELL = 4 };
-enum { ORC_PENCIL = 0, ORC_RECT = 1, ORC_RECT_DIVERGENT = 2 };
+enum { ORC_PENCIL = 0, ORC_RECT = 1, ORC_RECT_DIVERGENT = 2, ORC_MODERATOR = 3 };
 enum { ORC_MONO = 0, ORC_UNIFORM = 1, ORC_MAXWELL = 2 };
 enum { ORC_TRIG_ESCAPE = 0, ORC_TRIG_ABSORB = 1, ORC_TRIG_DETECT = 2 };
 enum { ORC_FILT_ALL = 0, ORC_FILT_UNSCATTERED = 1, ORC_FILT_SCATTERED = 2, ORC_FILT_NSCAT_EQ = 3 };
@@ -78,6 +78,7 @@ typedef struct {
     int32_t kind, spectrum;
     double origin[3], dir[3], size[2], div_deg[2];
     double lam0, lam_lo, lam_hi, kT;
+    double slit_center[3], slit_size[2];
 } orc_source;
 
 typedef struct {

@@ -23,7 +23,7 @@ PR_FP64_PLAIN, PR_FP32_MIXED = 0, 1
 PRECISION = {"fp64": PR_FP64_PLAIN, "fp64_plain": PR_FP64_PLAIN, "fp32": PR_FP32_MIXED, "fp32_mixed": PR_FP32_MIXED}
 
 SOLID = {"box": 0, "cylinder": 1, "cyl_shell": 2, "sphere": 3, "sph_shell": 4}
-SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2}
+SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
 TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
@@ -67,7 +67,8 @@ class pr_volume_desc(C.Structure):
 class pr_source_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("spectrum", C.c_int32), ("origin", C.c_double * 3), ("dir", C.c_double * 3),
                 ("size", C.c_double * 2), ("div_deg", C.c_double * 2), ("lam0", C.c_double), ("lam_lo", C.c_double),
-                ("lam_hi", C.c_double), ("kT", C.c_double)]
+                ("lam_hi", C.c_double), ("kT", C.c_double), ("slit_center", C.c_double * 3),
+                ("slit_size", C.c_double * 2)]
 
 
 class pr_tally_axis(C.Structure):
@@ -192,6 +193,9 @@ def source_desc(src: W.Source) -> pr_source_desc:
     s.size[0], s.size[1] = src.size
     s.div_deg[0], s.div_deg[1] = src.divergence
     s.lam0, s.lam_lo, s.lam_hi, s.kT = src.lam0, src.lam_lo, src.lam_hi, src.kT
+    for k in range(3):
+        s.slit_center[k] = src.slit_center[k]
+    s.slit_size[0], s.slit_size[1] = src.slit_size
     return s
 
 

@@ -749,7 +749,7 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
 
 extern "C" int pr_create_source(pr_ctx* c, const pr_source_desc* d, int32_t* id) {
     if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
-    if (d->kind < PR_PENCIL || d->kind > PR_RECT_DIVERGENT) return fail(c, PR_EINVAL, "source.kind invalid");
+    if (d->kind < PR_PENCIL || d->kind > PR_MODERATOR) return fail(c, PR_EINVAL, "source.kind invalid");
     if (d->spectrum < PR_MONO || d->spectrum > PR_MAXWELL) return fail(c, PR_EINVAL, "source.spectrum invalid");
     for (int k = 0; k < 3; ++k)
         if (!std::isfinite(d->origin[k]) || !std::isfinite(d->dir[k])) return fail(c, PR_EINVAL, "source origin/dir not finite");
@@ -763,6 +763,13 @@ extern "C" int pr_create_source(pr_ctx* c, const pr_source_desc* d, int32_t* id)
         for (int k = 0; k < 2; ++k)
             if (!(finite_nonneg(d->div_deg[k]) && d->div_deg[k] < 89.0))
                 return fail(c, PR_EINVAL, "source.div_deg must be in [0, 89)");
+    }
+    if (d->kind == PR_MODERATOR) {
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(d->slit_center[k])) return fail(c, PR_EINVAL, "source.slit_center not finite");
+        if (!(finite_nonneg(d->slit_size[0]) && finite_nonneg(d->slit_size[1])))
+            return fail(c, PR_EINVAL, "source.slit_size must be >= 0");
+        if (!(d->slit_center[2] != d->origin[2])) return fail(c, PR_EINVAL, "source slit must lie off the source plane");
     }
     if (d->spectrum == PR_MONO && !(std::isfinite(d->lam0) && d->lam0 > 0)) return fail(c, PR_EINVAL, "source.lam0 must be > 0");
     if (d->spectrum != PR_MONO && !(std::isfinite(d->lam_lo) && d->lam_lo > 0 && d->lam_hi > d->lam_lo && std::isfinite(d->lam_hi)))
@@ -847,6 +854,9 @@ static void make_source_dev(const pr_source_desc& s, SourceDev& d) {
     d.lam_hi = s.lam_hi;
     d.kT = s.kT;
     d.e_const = ev_angstrom2();
+    for (int k = 0; k < 3; ++k) d.slit[k] = s.slit_center[k];
+    d.slit_size[0] = s.slit_size[0];
+    d.slit_size[1] = s.slit_size[1];
 }
 
 static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
@@ -924,24 +934,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.has_grid = g.gd.empty() ? 0 : 1;
     P.scene_in_lds = g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget) ? 1 : 0;
     P.kinds = g.kinds;
-    const pr_source_desc& s = c->srcs[src];
-    SourceDev& d = P.src;
-    d.kind = s.kind;
-    d.spectrum = s.spectrum;
-    double nd = std::sqrt(s.dir[0] * s.dir[0] + s.dir[1] * s.dir[1] + s.dir[2] * s.dir[2]);
-    for (int k = 0; k < 3; ++k) {
-        d.o[k] = s.origin[k];
-        d.u[k] = s.dir[k] / nd;
-    }
-    d.size[0] = s.size[0];
-    d.size[1] = s.size[1];
-    d.div_rad[0] = s.div_deg[0] * 3.14159265358979323846 / 180.0;
-    d.div_rad[1] = s.div_deg[1] * 3.14159265358979323846 / 180.0;
-    d.lam0 = s.lam0;
-    d.lam_lo = s.lam_lo;
-    d.lam_hi = s.lam_hi;
-    d.kT = s.kT;
-    d.e_const = ev_angstrom2();
+    make_source_dev(c->srcs[src], P.src);
     P.n_tallies = nt;
     int lds_doubles = 0;
     const int budget = precision == PR_FP32_MIXED ? c->lds_tally_budget / 8 : 0;

@@ -106,6 +106,7 @@ struct SourceDev {
     double div_rad[2];
     double lam0, lam_lo, lam_hi, kT;
     double e_const;   // h^2 / (2 m_n) in eV A^2
+    double slit[3], slit_size[2];   // moderator source: slit centre and sides
 };
 
 struct TallyDev {
@@ -725,6 +726,17 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
         R b = draw(s, seed);
         p[0] += (a - (R)0.5) * (R)src.size[0];
         p[1] += (b - (R)0.5) * (R)src.size[1];
+    }
+    if (src.kind == PR_MODERATOR) {
+        // the direction joins the source point to a uniform point of the slit
+        R a = draw(s, seed);
+        R b = draw(s, seed);
+        R v[3] = {(R)src.slit[0] + (a - (R)0.5) * (R)src.slit_size[0] - p[0],
+                  (R)src.slit[1] + (b - (R)0.5) * (R)src.slit_size[1] - p[1], (R)src.slit[2] - p[2]};
+        R nrm = M<R>::sqrt_(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        u[0] = M<R>::div_(v[0], nrm);
+        u[1] = M<R>::div_(v[1], nrm);
+        u[2] = M<R>::div_(v[2], nrm);
     }
     if (src.kind == PR_RECT_DIVERGENT) {
         R ax = ((R)2 * draw(s, seed) - (R)1) * (R)src.div_rad[0];

@@ -2,7 +2,8 @@
 
     python -m paper_2304_06226_amd.run --workload guide --histories 1e8 --precision fp32 --repeat 3
 
-Workloads: sample (biased powder sample), vessel, guide, imaging, batch
+Workloads: sample (biased powder sample), vessel, guide, imaging, paper_guide
+(the paper's m = 1 guide benchmark, 1e8 neutrons), batch
 (the 256-simulation + imaging batch; always FP32-mixed).  The mixed policy uses
 the workload's stored launch tuning (--autotune re-measures it).  One warm-up
 run, then `repeat` timed runs on disjoint history ranges (HIP events on the
@@ -17,7 +18,8 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["sample", "vessel", "guide", "imaging", "batch"], default="sample")
+    ap.add_argument("--workload", choices=["sample", "vessel", "guide", "imaging", "paper_guide", "batch"],
+                    default="sample")
     ap.add_argument("--histories", type=float, default=None)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--repeat", type=int, default=3)
@@ -31,7 +33,8 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     ctx = B.Context(0, seed=W.RUN_SEED)
-    ctx.set_tuning(**TUNED[args.workload])
+    if args.workload in TUNED:
+        ctx.set_tuning(**TUNED[args.workload])
     if args.workload == "batch":
         batch = W.config4()
         br = B.BatchRun(ctx, batch)
@@ -42,7 +45,8 @@ def main(argv=None):
         def go(k):
             br.run(shift=k * br.span)
     else:
-        prob = {"sample": W.config1, "vessel": W.config2, "guide": W.config3, "imaging": W.imaging_problem}[args.workload]()
+        prob = {"sample": W.config1, "vessel": W.config2, "guide": W.config3, "imaging": W.imaging_problem,
+                "paper_guide": W.paper_guide}[args.workload]()
         n = int(args.histories) if args.histories else prob.n_histories
         sim = B.Simulation(ctx, prob)
         if args.autotune and args.precision == "fp32":

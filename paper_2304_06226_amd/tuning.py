@@ -13,6 +13,8 @@ TUNED = {
                "bin_cache_slots": 1024, "chunk": 256, "superchunk": 2048},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
                 "bin_cache_slots": 1024, "chunk": 64, "superchunk": 2048},
+    "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
+                    "bin_cache_slots": 1024, "chunk": 1024, "superchunk": 2048},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
               "bin_cache_slots": 2048, "chunk": 64, "superchunk": 2048},
 }

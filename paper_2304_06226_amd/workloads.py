@@ -30,7 +30,7 @@ RUN_SEED = 4096  # the launcher's default seed (program section, launcher option
 
 # Kinds are plain strings so that each binding maps them to its own integers.
 SOLIDS = ("box", "cylinder", "cyl_shell", "sphere", "sph_shell")
-SOURCES = ("pencil", "rect", "rect_divergent")
+SOURCES = ("pencil", "rect", "rect_divergent", "moderator")
 SPECTRA = ("mono", "uniform", "maxwell")
 TRIGGERS = ("escape", "absorb", "detect")
 FILTERS = ("all", "unscattered", "scattered", "nscat_eq")
@@ -96,6 +96,8 @@ class Source:
     lam_lo: float = 0.5
     lam_hi: float = 5.0
     kT: float = 0.025852
+    slit_center: Tuple[float, float, float] = (0.0, 0.0, 0.0)   # moderator: slit centre, mm
+    slit_size: Tuple[float, float] = (0.0, 0.0)                 # moderator: slit width (x), height (y)
 
 
 @dataclass
@@ -260,6 +262,37 @@ def config3(n: int = 100_000_000, nbins_xy: int = 200, nbins_div: int = 100) -> 
                      axes=[Axis("x", -25.0, 25.0, nbins_xy), Axis("y", -25.0, 25.0, nbins_xy),
                            Axis("div_x", -1.0, 1.0, nbins_div), Axis("div_y", -1.0, 1.0, nbins_div)])]
     return Problem([], vols, src, tallies, n_histories=n, name="config3")
+
+
+def paper_guide(n: int = 100_000_000, det_side: float = 100.0, det_bins: int = 100) -> Problem:
+    """The straight-guide benchmark of the paper's neutron guide section (a
+    reproduction of McStas' Test_Guides): a 50x50 mm moderator surface at z = 0
+    emitting 3.39 A neutrons aimed at a 50x50 mm window 1 m downstream (the front
+    detector plane); an m = 1 straight guide formed by four wall boxes around a
+    50x50x1000 mm opening whose entrance is at z = 1100 mm, with the paper's mirror
+    model and default parameters (R0 0.99, Qc 0.0219 1/A, alpha 6.07 A, W 0.003
+    1/A) on the opening's side faces and strongly absorbing walls (neutrons that
+    miss the entrance stop in them); and a rear position-sensitive detector whose
+    front face is 3.2 m from the source (det_side x det_side mm, det_bins^2
+    pixels).  The walls stand 0.01 mm off the opening (volumes must not touch)."""
+    mirror = Mirror(model="tanh", R0=0.99, Qc=0.0219, alpha=6.07, m=1.0, W=0.003)
+    wall = Material(number_density=0.05, sigma_inc=0.0, sigma_abs_ref=5000.0)
+    z0, length, t, gap = 1600.0, 1000.0, 10.0, 0.01
+    half = 25.0 + gap
+    vols = [Volume("box", (0.0, 0.0, 1650.0), (1000.0, 1000.0, 3500.0)),
+            Volume("box", (0.0, 0.0, z0), (50.0, 50.0, length), parent=0, mirror_mask=0b001111, mirror=mirror),
+            Volume("box", (+(half + t / 2), 0.0, z0), (t, 2 * (half + t), length), parent=0, material=0),
+            Volume("box", (-(half + t / 2), 0.0, z0), (t, 2 * (half + t), length), parent=0, material=0),
+            Volume("box", (0.0, +(half + t / 2), z0), (2 * half - 2 * gap, t, length), parent=0, material=0),
+            Volume("box", (0.0, -(half + t / 2), z0), (2 * half - 2 * gap, t, length), parent=0, material=0),
+            Volume("box", (0.0, 0.0, 3201.0), (det_side, det_side, 2.0), parent=0, detector=True)]
+    det = len(vols) - 1
+    src = Source("moderator", origin=(0.0, 0.0, 0.0), size=(50.0, 50.0), spectrum="mono", lam0=3.39,
+                 slit_center=(0.0, 0.0, 1000.0), slit_size=(50.0, 50.0))
+    h = det_side / 2
+    tallies = [Tally(trigger="detect", trigger_volume=det, axes=[Axis("x", -h, h, det_bins), Axis("y", -h, h, det_bins)]),
+               Tally(trigger="detect", trigger_volume=det)]
+    return Problem([wall], vols, src, tallies, n_histories=n, name="paper_guide")
 
 
 def with_histories(p: Problem, n: int) -> Problem:

@@ -246,3 +246,35 @@ def unscattered_block_fraction(prob, sig, nblk, half=250.0):
     out = np.zeros((nblk, nblk))
     np.add.at(out, (bi[:, None].repeat(len(yc), 1), bj[None, :].repeat(len(xc), 0)), np.exp(-tau) * area)
     return out / (2 * half) ** 2
+
+
+def test_paper_guide_full_1e8_fp32(ctx):
+    """The paper's guide benchmark at its own size, 1e8 neutrons: the detected
+    fraction and the rear-detector image (20x20 blocks) against a 1e7-history
+    oracle sample."""
+    import torch
+    prob = W.paper_guide()
+    n = prob.n_histories
+    print(f"[case] paper guide fp32 n={n}", flush=True)
+    sim = B.Simulation(ctx, prob)
+    base = _tuned(ctx, sim, n // 10)
+    try:
+        ctx.reset_stats()
+        sim.run(first=0, n=n, precision="fp32")
+        torch.cuda.synchronize()
+        res = sim.results()
+        st = ctx.read_stats()
+    finally:
+        ctx.set_tuning(**base)
+    assert st["histories"] == n
+    assert st["detected"] + st["escaped"] + st["absorbed"] + st["killed"] == n
+    o = O.run(prob, first=0, n=10_000_000, threads=16)
+
+    def coarse(a):
+        return a.reshape(20, 5, 20, 5).sum(axis=(1, 3)).ravel()
+    gw, gw2, gn = res[0]
+    p, z = tally_stat_test(coarse(gw), coarse(gw2), gn, coarse(o.sumw[0]), coarse(o.sumw2[0]), o.n)
+    assert p > 1e-3, p
+    gw, gw2, gn = res[1]
+    p, z = tally_stat_test(gw, gw2, gn, o.sumw[1], o.sumw2[1], o.n)
+    assert p > 1e-3, p

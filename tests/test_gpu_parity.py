@@ -239,3 +239,30 @@ def test_biasing_validations_on_gpu(ctx):
         m = sw / nh
         return float(np.sum((sw2 / nh - m * m) / (nh - 1)))
     assert var_sum(res["biased"][0]) < 0.5 * var_sum(res["analog"][0])
+
+
+# ---------------------------------------------------------------------------
+# Moderator-surface gun and the paper's m = 1 guide benchmark
+# ---------------------------------------------------------------------------
+
+def _gun_problem(n):
+    vols = [W.Volume("box", (0.0, 0.0, 1000.0), (400.0, 400.0, 3000.0)),
+            W.Volume("box", (0.0, 0.0, 1501.0), (300.0, 300.0, 2.0), parent=0, detector=True)]
+    src = W.Source("moderator", origin=(10.0, -5.0, 0.0), size=(60.0, 40.0), spectrum="uniform", lam_lo=1.0,
+                   lam_hi=4.0, slit_center=(3.0, 4.0, 500.0), slit_size=(20.0, 30.0))
+    tallies = [W.Tally(trigger="detect", trigger_volume=1,
+                       axes=[W.Axis("x", -150, 150, 60), W.Axis("y", -150, 150, 60), W.Axis("lambda", 1, 4, 6)])]
+    return W.Problem([], vols, src, tallies, n_histories=n, name="moderator-gun")
+
+
+def test_moderator_gun_fp64_elementwise(ctx):
+    _fp64_case(ctx, _gun_problem(50_000), 99, 50_000)
+
+
+def test_paper_guide_fp64_elementwise(ctx):
+    _, grec, _, _ = _fp64_case(ctx, W.paper_guide(100_000), 0, 100_000)
+    assert (grec["term"] == B.END_DETECT).mean() > 0.2
+
+
+def test_paper_guide_fp32_tally_agreement(ctx):
+    _fp32_case(ctx, W.paper_guide(1_000_000), 1_000_000)

@@ -537,3 +537,119 @@ def test_bias_factor_zero_removes_the_process():
     exp_t = np.exp(-sa * L)
     assert abs(t - exp_t) < 4 * np.sqrt(exp_t * (1 - exp_t) / n)
     assert abs(r.stats["absorbed"] / n - (1 - exp_t)) < 4 * np.sqrt(exp_t * (1 - exp_t) / n)
+
+
+# ---------------------------------------------------------------------------
+# Moderator-surface gun and the paper's m = 1 guide benchmark
+# ---------------------------------------------------------------------------
+
+def _gun_problem(det_z, side=300.0, nb=60):
+    vols = [W.Volume("box", (0.0, 0.0, 1000.0), (400.0, 400.0, 3000.0)),
+            W.Volume("box", (0.0, 0.0, det_z + 1.0), (side, side, 2.0), parent=0, detector=True)]
+    src = W.Source("moderator", origin=(10.0, -5.0, 0.0), size=(60.0, 40.0), spectrum="mono", lam0=2.0,
+                   slit_center=(3.0, 4.0, 500.0), slit_size=(20.0, 30.0))
+    h = side / 2
+    tallies = [W.Tally(trigger="detect", trigger_volume=1, axes=[W.Axis("x", -h, h, nb)]),
+               W.Tally(trigger="detect", trigger_volume=1, axes=[W.Axis("y", -h, h, nb)])]
+    return W.Problem([], vols, src, tallies, n_histories=0, name="gun")
+
+
+def _sum_of_uniforms_cdf(x, a1, a2, b1, b2):
+    """Exact CDF of A + B with A ~ U[a1, a2] and B ~ U[b1, b2] independent."""
+    w = a2 - a1
+
+    def G(t):   # integral of the CDF of A up to t
+        return np.where(t <= a1, 0.0, np.where(t <= a2, (t - a1) ** 2 / (2 * w), t - a1 - w / 2))
+    return (G(x - b1) - G(x - b2)) / (b2 - b1)
+
+
+def test_moderator_gun_hits_the_slit_uniformly():
+    """Every ray crosses the slit plane inside the slit, uniformly (the detector's
+    front face is the slit plane)."""
+    p = _gun_problem(500.0, side=300.0, nb=300)
+    r = O.run(p, n=200_000, threads=8)
+    assert r.stats["detected"] == 200_000
+    for t, (c, half) in enumerate(((3.0, 10.0), (4.0, 15.0))):
+        sw = r.sumw[t]
+        edges = np.linspace(-150, 150, 301)
+        inside = (edges[:-1] >= c - half) & (edges[1:] <= c + half)
+        assert sw[~inside].sum() == 0
+        assert stats.chisquare(sw[inside]).pvalue > 1e-3
+
+
+def test_moderator_gun_far_plane_is_a_trapezoid():
+    """Beyond the slit the crossing point is a fixed mix of two independent
+    uniforms, x = f x_slit - (f - 1) x_source with f = z / z_slit: its distribution
+    is the trapezoid of a sum of uniforms."""
+    zd = 1500.0
+    f = zd / 500.0
+    p = _gun_problem(zd, side=300.0, nb=60)
+    n = 400_000
+    r = O.run(p, n=n, threads=8)
+    assert r.stats["detected"] == n
+    edges = np.linspace(-150, 150, 61)
+    for t, (cs, hs, ct, ht) in enumerate(((10.0, 30.0, 3.0, 10.0), (-5.0, 20.0, 4.0, 15.0))):
+        a1, a2 = f * (ct - ht), f * (ct + ht)
+        b1, b2 = -(f - 1) * (cs + hs), -(f - 1) * (cs - hs)
+        pb = np.diff(_sum_of_uniforms_cdf(edges, a1, a2, b1, b2))
+        assert abs(pb.sum() - 1) < 1e-12
+        keep = pb * n > 5
+        obs = r.sumw[t]
+        assert obs[~keep].sum() <= 5 * (~keep).sum()
+        exp = pb[keep] * n
+        assert stats.chisquare(obs[keep], exp * obs[keep].sum() / exp.sum()).pvalue > 1e-3
+
+
+def R_tanh(Q, R0=0.99, Qc=0.0219, alpha=6.07, m=1.0, W_=0.003):
+    Q = np.asarray(Q, dtype=float)
+    R = 0.5 * R0 * (1 - alpha * (Q - Qc)) * (1 - np.tanh((Q - m * Qc) / W_))
+    return np.maximum(np.where(Q <= Qc, R0, R), 0.0)
+
+
+def test_paper_guide_method_of_images():
+    """The paper's m = 1 guide per history: rays entering the opening are unfolded
+    through the mirror walls (weight R(Q)^n per axis with the paper's mirror model,
+    a history ends where R = 0), fly on to the rear detector plane, and rays
+    hitting the wall fronts are absorbed."""
+    p = W.paper_guide(n=20_000, det_bins=10)
+    n = 20_000
+    r = O.run(p, n=n, threads=8, records=True)
+    rec = r.records
+    u = np.array([[O.uniform(4096, h, k) for k in range(4)] for h in range(n)])
+    xs, ys = (u[:, 0] - 0.5) * 50.0, (u[:, 1] - 0.5) * 50.0
+    xt, yt = (u[:, 2] - 0.5) * 50.0, (u[:, 3] - 0.5) * 50.0
+    v = np.stack([xt - xs, yt - ys, np.full(n, 1000.0)], axis=1)
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    x_in = xs + 1100.0 * v[:, 0] / v[:, 2]
+    y_in = ys + 1100.0 * v[:, 1] / v[:, 2]
+    clear = (np.abs(np.abs(x_in) - 25.0) > 0.02) & (np.abs(np.abs(y_in) - 25.0) > 0.02)
+    enter = clear & (np.abs(x_in) < 25.0) & (np.abs(y_in) < 25.0)
+    wall = clear & ~enter
+    assert np.all(rec["term"][wall] == O.END_ABSORB)
+    lam = 3.39
+    xe, nx = _fold(x_in + 1000.0 * v[:, 0] / v[:, 2], 25.0)
+    ye, ny = _fold(y_in + 1000.0 * v[:, 1] / v[:, 2], 25.0)
+    Rx = R_tanh(4 * np.pi * np.abs(v[:, 0]) / lam)
+    Ry = R_tanh(4 * np.pi * np.abs(v[:, 1]) / lam)
+    dead = ((nx > 0) & (Rx == 0)) | ((ny > 0) & (Ry == 0))
+    w = Rx ** nx * Ry ** ny
+    # where 1 - tanh(.) is within an ulp of 0 two libraries may give R = 0 or ~1e-17:
+    # such rays must be killed or carry a weight below 1e-12
+    faint = ((nx > 0) & (Rx < 1e-12)) | ((ny > 0) & (Ry < 1e-12))
+    assert np.all(rec["term"][enter & dead & ~faint] == O.END_KILL)
+    assert np.all((rec["term"][enter & faint] == O.END_KILL) | (rec["w"][enter & faint] < 1e-12))
+    live = enter & ~dead & ~faint
+    vx = v[:, 0] * (-1.0) ** nx
+    vy = v[:, 1] * (-1.0) ** ny
+    xd = xe + 1100.0 * vx / v[:, 2]
+    yd = ye + 1100.0 * vy / v[:, 2]
+    hit = live & (np.abs(xd) < 49.9) & (np.abs(yd) < 49.9)
+    miss = live & ((np.abs(xd) > 50.2) | (np.abs(yd) > 50.2))
+    assert np.all(rec["term"][hit] == O.END_DETECT)
+    assert np.all(rec["term"][miss] == O.END_ESCAPE)
+    assert np.allclose(rec["w"][hit], w[hit], rtol=1e-12)
+    assert np.allclose(rec["pos"][hit, 0], xd[hit], atol=1e-6)
+    assert np.allclose(rec["pos"][hit, 1], yd[hit], atol=1e-6)
+    assert np.allclose(rec["pos"][hit, 2], 3200.0, atol=1e-6)
+    assert hit.sum() > 0.3 * n and wall.sum() > 0.1 * n and (enter & dead).sum() > 0.2 * n
+    assert (nx + ny)[hit].max() >= 2
