@@ -57,7 +57,7 @@ enum { PR_MONO = 0, PR_UNIFORM = 1, PR_MAXWELL = 2 };
 enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2 };
 enum { PR_FILT_ALL = 0, PR_FILT_UNSCATTERED = 1, PR_FILT_SCATTERED = 2, PR_FILT_NSCAT_EQ = 3 };
 enum { PR_Q_THETA2 = 0, PR_Q_LAMBDA = 1, PR_Q_X = 2, PR_Q_Y = 3, PR_Q_Z = 4, PR_Q_DIVX = 5, PR_Q_DIVY = 6,
-       PR_Q_NSCAT = 7, PR_Q_Q = 8 };
+       PR_Q_NSCAT = 7, PR_Q_Q = 8, PR_Q_TOF = 9 };
 enum { PR_MIRROR_LINEAR = 0, PR_MIRROR_TANH = 1 };
 enum { PR_ACC_FP64 = 0, PR_ACC_KAHAN_FP32 = 1 };
 /* precision policies of pr_run_histories */
@@ -109,6 +109,24 @@ typedef struct {
     double R0, Qc, alpha, m, W;
 } pr_mirror_desc;
 
+/* Disk chopper (mirror and disk chopper section; Table tableDiskChopper),
+ * carried by a PR_CYLINDER volume (the disk, normally very thin) whose axis
+ * is the rotation axis and whose radius is the outer radius R.  When a neutron
+ * enters the disk at position p and time t its weight is multiplied by the
+ * ray-tracing mask epsilon (0 or 1): with rho, phi the polar coordinates of p
+ * about the axis (phi from the next axis towards the one after, right-handed:
+ * x -> y about z, y -> z about x, z -> x about y), epsilon = 1 iff rho >= r and
+ * (phi - phase - 2 pi rot_freq t) mod (2 pi / n) < theta0; epsilon = 0 ends the
+ * history (killed).  n = 0: no chopper. */
+typedef struct {
+    int32_t n;                /* number of windows, evenly spread over 2 pi (0 = none) */
+    int32_t pad;
+    double r;                 /* mm, inner (black) radius */
+    double rot_freq;          /* Hz, positive = right-handed about the axis */
+    double theta0;            /* degrees, opening angle of a window */
+    double phase;             /* degrees, window start at t = 0 */
+} pr_chopper_desc;
+
 /* Volume (geometry section).  size by kind:
  *   PR_BOX        {side_x, side_y, side_z} (full sides, axis aligned)
  *   PR_CYLINDER   {r, h}               axis = 0,1,2
@@ -131,6 +149,7 @@ typedef struct {
     double center[3];         /* mm */
     double size[3];           /* mm, see above */
     pr_mirror_desc mirror;
+    pr_chopper_desc chopper;
 } pr_volume_desc;
 
 /* Source (particle gun section).  PR_PENCIL: origin and direction.
@@ -163,7 +182,9 @@ typedef struct {
                                  div_x = atan2(u_x, u_z) deg; div_y = atan2(u_y, u_z) deg; n_scat;
                                  Q = |k_out - k_beam| = (4 pi / lambda) sqrt((1 - u.beam) / 2) 1/A,
                                  the momentum transfer of elastic scattering out of the beam direction
-                                 (the DeltaMomentum scorer, Table tableScorer) */
+                                 (the DeltaMomentum scorer, Table tableScorer); tof = time since
+                                 emission in s (TOF scorer; sources emit at t = 0, a neutron moves at
+                                 v = h / (m_n lambda)) */
     int32_t nbins;            /* >= 1 */
     double lo, hi;            /* hi > lo; bin = floor((x - lo) / (hi - lo) nbins); x = hi goes to the
                                  last bin; values outside [lo, hi] are not scored */

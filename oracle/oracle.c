@@ -436,7 +436,7 @@ static int tally_bin(const orc_tally* t, double value, int axis)
 }
 
 static void score(const orc_problem* P, acc_t* acc, int term, int det_vol, const double p[3], const double u[3],
-                  double lam, double w, int nscat)
+                  double lam, double w, int nscat, double tof)
 {
     for (int ti = 0; ti < P->n_tallies; ++ti) {
         const orc_tally* t = &P->tallies[ti];
@@ -469,6 +469,7 @@ static void score(const orc_problem* P, acc_t* acc, int term, int det_vol, const
             case ORC_Q_DIVX: x = atan2(u[0], u[2]) * 180.0 / PI; break;
             case ORC_Q_DIVY: x = atan2(u[1], u[2]) * 180.0 / PI; break;
             case ORC_Q_NSCAT: x = (double)nscat; break;
+            case ORC_Q_TOF: x = tof; break;
             case ORC_Q_Q: {
                 /* momentum transfer of elastic scattering from the beam direction to u:
                    |k_out - k_in| = 2 k sin(alpha / 2), k = 2 pi / lambda, with
@@ -495,6 +496,29 @@ static void score(const orc_problem* P, acc_t* acc, int term, int det_vol, const
 /* One history (simulation flow section)                                     */
 /* ------------------------------------------------------------------------ */
 
+/* h / m_n in mm A / s (CODATA 2018): a neutron of wavelength lambda [A] moves
+ * at h / (m_n lambda) */
+#define H_OVER_MN (6.62607015e-34 / 1.67492749804e-27 * 1e13)
+
+/* Disk chopper (mirror and disk chopper section, Table tableDiskChopper): the
+ * polar angle phi of the crossing point about the disk axis (from the next axis
+ * towards the one after), the disk turned by phase + 2 pi f t; the point is open
+ * when it lies outside the black inner radius and within theta0 after the start
+ * of one of the n evenly spread windows. */
+static int chopper_open(const orc_volume* V, const double p[3], double t)
+{
+    int a = V->axis, b = (a + 1) % 3, c = (a + 2) % 3;
+    double qb = p[b] - V->center[b], qc = p[c] - V->center[c];
+    double rho = sqrt(qb * qb + qc * qc);
+    if (rho < V->chop_r) return 0;
+    double phi = atan2(qc, qb);
+    double ang = phi - V->chop_phase * PI / 180.0 - 2.0 * PI * V->chop_freq * t;
+    double per = 2.0 * PI / V->chop_n;
+    double m = fmod(ang, per);
+    if (m < 0.0) m += per;
+    return m < V->chop_theta0 * PI / 180.0;
+}
+
 static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t* acc, orc_record* rec,
                         orc_stats* st)
 {
@@ -502,6 +526,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
     double p[3], u[3], lam;
     sample_source(P->source, &rng, p, u, &lam);
     double w = 1.0;
+    double t = 0.0;   /* time since emission, s */
     int nscat = 0, steps = 0, term = 0, det_vol = -1;
     uint64_t hash = 14695981039346656037ull;
     int region = locate(P, p);
@@ -568,6 +593,8 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
             if (l < d_b) { collide = 1; x = l; }
         }
         for (int k = 0; k < 3; ++k) p[k] += x * u[k];
+        /* time of flight: speed h / (m_n lambda) */
+        t += x * lam / H_OVER_MN;
         /* weight correction for the move: exp(sum_i (g_i - 1) rho sigma_i x) */
         if (sig_g > 0.0) w *= exp((sig_g - sig) * x);
 
@@ -630,6 +657,11 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
                 term = ORC_END_DETECT;
                 det_vol = region;
                 hash_event(&hash, ORC_EV_DETECT, region);
+            } else if (P->volumes[region].chop_n > 0 && !chopper_open(&P->volumes[region], p, t)) {
+                /* ray-tracing mask of the disk chopper: 0 outside an open window */
+                w = 0.0;
+                term = ORC_END_KILL;
+                hash_event(&hash, ORC_EV_KILL, 0);
             }
             continue;
         }
@@ -659,7 +691,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
     }
 
     if (term == ORC_END_ESCAPE || term == ORC_END_ABSORB || term == ORC_END_DETECT)
-        score(P, acc, term, det_vol, p, u, lam, w, nscat);
+        score(P, acc, term, det_vol, p, u, lam, w, nscat, t);
 
     st->histories++;
     st->steps += (uint64_t)steps;

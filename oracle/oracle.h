@@ -39,7 +39,7 @@ enum { ORC_MONO = 0, ORC_UNIFORM = 1, ORC_MAXWELL = 2 };
 enum { ORC_TRIG_ESCAPE = 0, ORC_TRIG_ABSORB = 1, ORC_TRIG_DETECT = 2 };
 enum { ORC_FILT_ALL = 0, ORC_FILT_UNSCATTERED = 1, ORC_FILT_SCATTERED = 2, ORC_FILT_NSCAT_EQ = 3 };
 enum { ORC_Q_THETA2 = 0, ORC_Q_LAMBDA = 1, ORC_Q_X = 2, ORC_Q_Y = 3, ORC_Q_Z = 4,
-       ORC_Q_DIVX = 5, ORC_Q_DIVY = 6, ORC_Q_NSCAT = 7, ORC_Q_Q = 8 };
+       ORC_Q_DIVX = 5, ORC_Q_DIVY = 6, ORC_Q_NSCAT = 7, ORC_Q_Q = 8, ORC_Q_TOF = 9 };
 enum { ORC_MIRROR_LINEAR = 0, ORC_MIRROR_TANH = 1 };
 /* termination codes */
 enum { ORC_END_ESCAPE = 1, ORC_END_ABSORB = 2, ORC_END_KILL = 3, ORC_END_DETECT = 4,
@@ -72,6 +72,9 @@ typedef struct {
     int32_t mirror_model;
     int32_t pad;
     double R0, Qc, alpha, m, W;
+    int32_t chop_n;          /* disk chopper windows (0 = none), cylinder volumes */
+    int32_t chop_pad;
+    double chop_r, chop_freq, chop_theta0, chop_phase;   /* mm, Hz, degrees, degrees */
 } orc_volume;
 
 typedef struct {

@@ -24,7 +24,7 @@ SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
 TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
-QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8}
+QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8, "tof": 9}
 MIRROR = {"linear": 0, "tanh": 1}
 
 END_ESCAPE, END_ABSORB, END_KILL, END_DETECT, END_CAPPED, END_OUTSIDE = 1, 2, 3, 4, 5, 6
@@ -48,7 +48,9 @@ class orc_volume(C.Structure):
                 ("is_detector", C.c_int32), ("mirror_mask", C.c_int32),
                 ("center", C.c_double * 3), ("size", C.c_double * 3),
                 ("mirror_model", C.c_int32), ("pad", C.c_int32),
-                ("R0", C.c_double), ("Qc", C.c_double), ("alpha", C.c_double), ("m", C.c_double), ("W", C.c_double)]
+                ("R0", C.c_double), ("Qc", C.c_double), ("alpha", C.c_double), ("m", C.c_double), ("W", C.c_double),
+                ("chop_n", C.c_int32), ("chop_pad", C.c_int32), ("chop_r", C.c_double), ("chop_freq", C.c_double),
+                ("chop_theta0", C.c_double), ("chop_phase", C.c_double)]
 
 
 class orc_source(C.Structure):
@@ -169,6 +171,9 @@ def make_volume(v) -> orc_volume:
     if mir is not None:
         s.mirror_model = MIRROR[mir.model]
         s.R0, s.Qc, s.alpha, s.m, s.W = mir.R0, mir.Qc, mir.alpha, mir.m, mir.W
+    ch = getattr(v, "chopper", None)
+    if ch is not None:
+        s.chop_n, s.chop_r, s.chop_freq, s.chop_theta0, s.chop_phase = ch.n, ch.r, ch.rot_freq, ch.theta0, ch.phase
     return s
 
 

@@ -27,7 +27,7 @@ SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
 TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
-QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8}
+QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8, "tof": 9}
 MIRROR = {"linear": 0, "tanh": 1}
 ACCUMULATOR = {"fp64": 0, "kahan_fp32": 1}
 
@@ -58,10 +58,15 @@ class pr_mirror_desc(C.Structure):
                 ("alpha", C.c_double), ("m", C.c_double), ("W", C.c_double)]
 
 
+class pr_chopper_desc(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad", C.c_int32), ("r", C.c_double), ("rot_freq", C.c_double),
+                ("theta0", C.c_double), ("phase", C.c_double)]
+
+
 class pr_volume_desc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("axis", C.c_int32), ("parent", C.c_int32), ("material", C.c_int32),
                 ("is_detector", C.c_int32), ("mirror_mask", C.c_int32), ("center", C.c_double * 3),
-                ("size", C.c_double * 3), ("mirror", pr_mirror_desc)]
+                ("size", C.c_double * 3), ("mirror", pr_mirror_desc), ("chopper", pr_chopper_desc)]
 
 
 class pr_source_desc(C.Structure):
@@ -181,6 +186,10 @@ def volume_desc(v: W.Volume, mat_ids: Sequence[int]) -> pr_volume_desc:
         mi = v.mirror
         s.mirror.model = MIRROR[mi.model]
         s.mirror.R0, s.mirror.Qc, s.mirror.alpha, s.mirror.m, s.mirror.W = mi.R0, mi.Qc, mi.alpha, mi.m, mi.W
+    if v.chopper is not None:
+        ch = v.chopper
+        s.chopper.n, s.chopper.r, s.chopper.rot_freq = ch.n, ch.r, ch.rot_freq
+        s.chopper.theta0, s.chopper.phase = ch.theta0, ch.phase
     return s
 
 

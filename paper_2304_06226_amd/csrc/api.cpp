@@ -544,6 +544,16 @@ static int validate_volume(pr_ctx* c, const pr_volume_desc& v, int i, int nmat) 
         if (m.model == PR_MIRROR_TANH && !(std::isfinite(m.W) && m.W > 0))
             return fail(c, PR_EINVAL, "volume[%d].mirror.W must be > 0", i);
     }
+    const pr_chopper_desc& ch = v.chopper;
+    if (ch.n != 0) {
+        if (v.kind != PR_CYLINDER) return fail(c, PR_EINVAL, "volume[%d]: a chopper needs a cylinder", i);
+        if (i == 0 || v.is_detector) return fail(c, PR_EINVAL, "volume[%d]: a chopper cannot be the world or a detector", i);
+        if (ch.n < 1 || ch.n > 1024) return fail(c, PR_EINVAL, "volume[%d].chopper.n must be in [1, 1024]", i);
+        if (!finite_nonneg(ch.r) || !std::isfinite(ch.rot_freq) || !std::isfinite(ch.phase))
+            return fail(c, PR_EINVAL, "volume[%d].chopper r, rot_freq, phase must be finite (r >= 0)", i);
+        if (!(ch.theta0 > 0 && ch.theta0 <= 360.0 / ch.n))
+            return fail(c, PR_EINVAL, "volume[%d].chopper.theta0 must be in (0, 360/n]", i);
+    }
     return PR_OK;
 }
 
@@ -640,6 +650,15 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         o.alpha = v.mirror.alpha;
         o.mQc = v.mirror.m * v.mirror.Qc;
         o.W = v.mirror.W > 0 ? v.mirror.W : 1.0;
+        o.chop_n = v.chopper.n;
+        if (v.chopper.n > 0) {
+            // the same expressions as the definition: phase pi / 180, 2 pi f, 2 pi / n
+            o.chop_r = v.chopper.r;
+            o.chop_omega = 2.0 * 3.14159265358979323846 * v.chopper.rot_freq;
+            o.chop_theta0 = v.chopper.theta0 * 3.14159265358979323846 / 180.0;
+            o.chop_phase = v.chopper.phase * 3.14159265358979323846 / 180.0;
+            o.chop_period = 2.0 * 3.14159265358979323846 / v.chopper.n;
+        }
         vd[i] = o;
         VolT<float> f{};
         for (int k = 0; k < 3; ++k) { f.c[k] = (float)o.c[k]; f.s[k] = (float)o.s[k]; }
@@ -648,6 +667,9 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         f.mirror_model = o.mirror_model;
         f.grid = -1;
         f.R0 = (float)o.R0; f.Qc = (float)o.Qc; f.alpha = (float)o.alpha; f.mQc = (float)o.mQc; f.W = (float)o.W;
+        f.chop_n = o.chop_n;
+        f.chop_r = (float)o.chop_r; f.chop_omega = (float)o.chop_omega; f.chop_theta0 = (float)o.chop_theta0;
+        f.chop_phase = (float)o.chop_phase; f.chop_period = (float)o.chop_period;
         vf[i] = f;
     }
     std::vector<MatT<double>> md;
@@ -703,7 +725,10 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         g.vd[i].det_items = g.vf[i].det_items = det;
     }
     g.kinds = 0;
-    for (int i = 0; i < n; ++i) g.kinds |= 1u << g.vd[i].kind;
+    for (int i = 0; i < n; ++i) {
+        g.kinds |= 1u << g.vd[i].kind;
+        if (g.vd[i].chop_n > 0) g.kinds |= 1u << kChopperBit;
+    }
     g.bd.assign(n, BoxT<double>{});
     g.bf.assign(n, BoxT<float>{});
     for (int i = 0; i < n; ++i) {
@@ -794,7 +819,7 @@ extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
     uint64_t nb = 1;
     for (int a = 0; a < d->naxes; ++a) {
         const pr_tally_axis& x = d->axes[a];
-        if (x.quantity < PR_Q_THETA2 || x.quantity > PR_Q_Q) return fail(c, PR_EINVAL, "tally.axes[%d].quantity invalid", a);
+        if (x.quantity < PR_Q_THETA2 || x.quantity > PR_Q_TOF) return fail(c, PR_EINVAL, "tally.axes[%d].quantity invalid", a);
         if (x.nbins < 1) return fail(c, PR_EINVAL, "tally.axes[%d].nbins must be >= 1", a);
         if (!(std::isfinite(x.lo) && std::isfinite(x.hi) && x.hi > x.lo))
             return fail(c, PR_EINVAL, "tally.axes[%d] needs lo < hi", a);

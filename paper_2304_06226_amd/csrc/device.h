@@ -16,6 +16,10 @@
 namespace prk {
 
 constexpr int kMaxSteps = PR_MAX_STEPS;
+// h / m_n in mm A / s (CODATA 2018): a neutron of wavelength lambda [A] moves at h / (m_n lambda)
+constexpr double kHOverMn = 6.62607015e-34 / 1.67492749804e-27 * 1e13;
+// bit of SceneT::kinds set when some volume carries a disk chopper
+constexpr int kChopperBit = 8;
 constexpr int kMaxTallies = PR_MAX_TALLIES;
 constexpr int kWave = 64;
 
@@ -40,6 +44,10 @@ struct VolT {
     // det_items the items that are detector volumes.
     uint32_t kind_items, kind_items4, det_items;
     R R0, Qc, alpha, mQc, W;
+    // disk chopper carried by a cylinder (chop_n = 0: none); angles in radians,
+    // chop_omega = 2 pi rot_freq, chop_period = 2 pi / chop_n
+    int32_t chop_n;
+    R chop_r, chop_omega, chop_theta0, chop_phase, chop_period;
 };
 
 // Uniform grid over the daughters of a volume with many daughters: cell c holds
@@ -228,6 +236,8 @@ struct M<double> {
         return ::atan2(y, x) * (180.0 / 3.14159265358979323846);
     }
     static __device__ __forceinline__ double tanh_(double x) { return ::tanh(x); }
+    static __device__ __forceinline__ double atan2_(double y, double x) { return ::atan2(y, x); }
+    static __device__ __forceinline__ double fmod_(double x, double y) { return ::fmod(x, y); }
     // 53-bit uniform in [0,1) from two Philox words
     static __device__ __forceinline__ double uni(uint32_t a, uint32_t b) {
         return (double)(a >> 5) * (1.0 / 134217728.0) + (double)(b >> 6) * (1.0 / 9007199254740992.0);
@@ -253,6 +263,8 @@ struct M<float> {
     static __device__ __forceinline__ float acos_deg(float c) { return ::acosf(c) * (180.0f / 3.14159265f); }
     static __device__ __forceinline__ float atan2_deg(float y, float x) { return ::atan2f(y, x) * (180.0f / 3.14159265f); }
     static __device__ __forceinline__ float tanh_(float x) { return ::tanhf(x); }
+    static __device__ __forceinline__ float atan2_(float y, float x) { return ::atan2f(y, x); }
+    static __device__ __forceinline__ float fmod_(float x, float y) { return ::fmodf(x, y); }
     // 24-bit uniform in [0,1) from the first word of the pair
     static __device__ __forceinline__ float uni(uint32_t a, uint32_t) { return (float)(a >> 8) * (1.0f / 16777216.0f); }
 };
@@ -302,6 +314,7 @@ struct PState {
     // cross sections cached for material xs_mat (lambda is constant per history)
     int32_t xs_mat, nact;
     R sa, si, sc, sig, sig_g, ga, gs, cl;
+    R t;   // time since emission, s
 };
 
 // FP64 draws: the block of draw k is computed when k is even, its second word
@@ -651,6 +664,21 @@ __device__ __forceinline__ void normal(const VolT<R>& V, int f, const R p[3], R 
     for (int k = 0; k < 3; ++k) n[k] = sg * M<R>::div_(q[k], r);
 }
 
+// Disk chopper mask at crossing point p and time t: polar angle about the disk
+// axis (from the next axis towards the one after), disk turned by phase + omega t;
+// open outside the black inner radius and within theta0 after a window start.
+template <class R>
+__device__ __forceinline__ bool chopper_open(const VolT<R>& V, const R p[3], R t) {
+    const int a = V.axis, b = a == 0 ? 1 : (a == 1 ? 2 : 0), c = a == 0 ? 2 : (a == 1 ? 0 : 1);
+    const R qb = pick(p, b) - pick(V.c, b), qc = pick(p, c) - pick(V.c, c);
+    const R rho = M<R>::sqrt_(qb * qb + qc * qc);
+    if (rho < V.chop_r) return false;
+    const R ang = M<R>::atan2_(qc, qb) - V.chop_phase - V.chop_omega * t;
+    R m = M<R>::fmod_(ang, V.chop_period);
+    if (m < (R)0) m += V.chop_period;
+    return m < V.chop_theta0;
+}
+
 template <class R>
 __device__ __forceinline__ R reflectivity(const VolT<R>& V, R Q) {
     if (Q <= V.Qc) return V.R0;
@@ -714,6 +742,7 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     s.k = 0;
     s.nbuf = 0;
     s.w = 1.0;
+    s.t = (R)0;
     s.nscat = 0;
     s.steps = 0;
     s.term = 0;
@@ -957,6 +986,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     s.p[0] += x * s.u[0];
     s.p[1] += x * s.u[1];
     s.p[2] += x * s.u[2];
+    s.t += M<R>::div_(x * s.lam, (R)kHOverMn);
     if (sig_g > (R)0) s.w *= (double)M<R>::exp_((sig_g - sig) * x);
 
     if (collide) {
@@ -1024,6 +1054,14 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         if (child_det) {
             s.term = PR_END_DETECT;
             hash_ev<REC>(s.hash, EV_DETECT, child);
+        } else if ((S.kinds >> kChopperBit) & 1u) {
+            const VolT<R>& C = S.vols[child];
+            if (C.chop_n > 0 && !chopper_open<R>(C, s.p, s.t)) {
+                // ray-tracing mask of the disk chopper: 0 outside an open window
+                s.w = 0.0;
+                s.term = PR_END_KILL;
+                hash_ev<REC>(s.hash, EV_KILL, 0);
+            }
         }
         return;
     }
@@ -1083,6 +1121,7 @@ __device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>&
         case PR_Q_Z: x = s.p[2]; break;
         case PR_Q_DIVX: x = M<R>::atan2_deg(s.u[0], s.u[2]); break;
         case PR_Q_DIVY: x = M<R>::atan2_deg(s.u[1], s.u[2]); break;
+        case PR_Q_TOF: x = s.t; break;
         case PR_Q_Q: {
             // momentum transfer from the beam direction: (4 pi / lambda) sin(alpha / 2)
             R c = s.u[0] * (R)T.beam[0] + s.u[1] * (R)T.beam[1] + s.u[2] * (R)T.beam[2];

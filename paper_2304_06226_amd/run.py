@@ -18,7 +18,8 @@ import sys
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["sample", "vessel", "guide", "imaging", "paper_guide", "batch"],
+    ap.add_argument("--workload", choices=["sample", "vessel", "guide", "imaging", "paper_guide", "paper_chopper",
+                                           "batch"],
                     default="sample")
     ap.add_argument("--histories", type=float, default=None)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -46,7 +47,7 @@ def main(argv=None):
             br.run(shift=k * br.span)
     else:
         prob = {"sample": W.config1, "vessel": W.config2, "guide": W.config3, "imaging": W.imaging_problem,
-                "paper_guide": W.paper_guide}[args.workload]()
+                "paper_guide": W.paper_guide, "paper_chopper": W.paper_chopper}[args.workload]()
         n = int(args.histories) if args.histories else prob.n_histories
         sim = B.Simulation(ctx, prob)
         if args.autotune and args.precision == "fp32":

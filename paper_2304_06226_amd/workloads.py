@@ -34,7 +34,7 @@ SOURCES = ("pencil", "rect", "rect_divergent", "moderator")
 SPECTRA = ("mono", "uniform", "maxwell")
 TRIGGERS = ("escape", "absorb", "detect")
 FILTERS = ("all", "unscattered", "scattered", "nscat_eq")
-QUANTITIES = ("theta2", "lambda", "x", "y", "z", "div_x", "div_y", "nscat", "q")
+QUANTITIES = ("theta2", "lambda", "x", "y", "z", "div_x", "div_y", "nscat", "q", "tof")
 MIRROR_MODELS = ("linear", "tanh")
 
 
@@ -71,6 +71,15 @@ class Mirror:
 
 
 @dataclass
+class Chopper:
+    n: int = 4                  # windows
+    r: float = 130.0            # mm, inner black radius
+    rot_freq: float = 100.0     # Hz
+    theta0: float = 20.0        # degrees, window opening
+    phase: float = 0.0          # degrees
+
+
+@dataclass
 class Volume:
     kind: str
     center: Tuple[float, float, float]
@@ -82,6 +91,7 @@ class Volume:
     detector: bool = False           # entering it scores 'detect' tallies and ends the history
     mirror_mask: int = 0             # faces carrying a mirror (bit per face id)
     mirror: Optional[Mirror] = None
+    chopper: Optional["Chopper"] = None   # disk chopper carried by a cylinder
 
 
 @dataclass
@@ -293,6 +303,32 @@ def paper_guide(n: int = 100_000_000, det_side: float = 100.0, det_bins: int = 1
     tallies = [Tally(trigger="detect", trigger_volume=det, axes=[Axis("x", -h, h, det_bins), Axis("y", -h, h, det_bins)]),
                Tally(trigger="detect", trigger_volume=det)]
     return Problem([wall], vols, src, tallies, n_histories=n, name="paper_guide")
+
+
+def paper_chopper(n: int = 10_000_000, chopper: bool = True, lam_mono: Optional[float] = None,
+                  slit: float = 45.0, phase: float = 0.0, tof_bins: int = 600) -> Problem:
+    """The disk-chopper benchmark of the paper's chopper section: a 293 K
+    Maxwellian moderator gun (1x1 mm opening at z = 0 aimed at a 45x45 mm opening
+    10 m away), a disk chopper in that plane (4 windows of 20 degrees, radii 130 and
+    250 mm, 100 Hz; its axis is offset so that the beam crosses the middle of the
+    window annulus, 190 mm from the axis), and a time-of-flight detector just behind
+    it (TOF 0-30 ms).  chopper=False leaves the disk out; lam_mono replaces the
+    Maxwellian by one wavelength."""
+    vols = [Volume("box", (0.0, 0.0, 10000.0), (1200.0, 1200.0, 20400.0))]
+    if chopper:
+        vols.append(Volume("cylinder", (0.0, -190.0, 10000.0), (250.0, 0.002), axis=2, parent=0,
+                           chopper=Chopper(n=4, r=130.0, rot_freq=100.0, theta0=20.0, phase=phase)))
+    vols.append(Volume("box", (0.0, 0.0, 10002.0), (300.0, 300.0, 2.0), parent=0, detector=True))
+    det = len(vols) - 1
+    if lam_mono is None:
+        src = Source("moderator", origin=(0.0, 0.0, 0.0), size=(1.0, 1.0), spectrum="maxwell", kT=0.025249,
+                     lam_lo=0.1, lam_hi=20.0, slit_center=(0.0, 0.0, 10000.0), slit_size=(slit, slit))
+    else:
+        src = Source("moderator", origin=(0.0, 0.0, 0.0), size=(1.0, 1.0), spectrum="mono", lam0=lam_mono,
+                     slit_center=(0.0, 0.0, 10000.0), slit_size=(slit, slit))
+    tallies = [Tally(trigger="detect", trigger_volume=det, axes=[Axis("tof", 0.0, 0.03, tof_bins)]),
+               Tally(trigger="detect", trigger_volume=det)]
+    return Problem([], vols, src, tallies, n_histories=n, name="paper_chopper")
 
 
 def with_histories(p: Problem, n: int) -> Problem:

@@ -2,6 +2,7 @@
 declared in include/*.h, and validates descriptors (device-less context:
 hip_device = -1) with the documented error codes."""
 import ctypes as C
+import subprocess
 import dataclasses
 import glob
 import os
@@ -14,6 +15,7 @@ from paper_2304_06226_amd import binding as B
 from paper_2304_06226_amd import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "prompt_mi355x.h")
 
 
 def declared_functions():
@@ -35,12 +37,33 @@ def test_every_declared_symbol_is_exported():
     assert set(names) == set(B.EXPORTS)
 
 
-def test_struct_sizes_match_header():
-    # pr_history_record is 96 bytes; descriptor layouts as laid out by the binding
-    assert C.sizeof(B.pr_volume_desc) == 6 * 4 + 6 * 8 + C.sizeof(B.pr_mirror_desc)
-    assert C.sizeof(B.pr_mirror_desc) == 8 + 5 * 8
-    assert B.RECORD_DTYPE.itemsize == 96
-    assert C.sizeof(B.pr_tally_desc) == 6 * 4 + 4 * 24 + 24
+def test_struct_sizes_match_header(tmp_path):
+    """The binding's ctypes structs have the sizes and field offsets that a C
+    compiler gives the header's structs."""
+    structs = {"pr_material_desc": B.pr_material_desc, "pr_mirror_desc": B.pr_mirror_desc,
+               "pr_chopper_desc": B.pr_chopper_desc, "pr_volume_desc": B.pr_volume_desc,
+               "pr_source_desc": B.pr_source_desc, "pr_tally_axis": B.pr_tally_axis,
+               "pr_tally_desc": B.pr_tally_desc, "pr_history_record": None, "pr_run_stats": B.pr_run_stats,
+               "pr_sim": B.pr_sim, "pr_tuning": B.pr_tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        if cls is not None:
+            for f in cls._fields_:
+                lines.append(f'  printf("{name}.{f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append('  return 0; }')
+    src = tmp_path / "sizes.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "sizes"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(src)], check=True)
+    out = dict(l.split() for l in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines())
+    for name, cls in structs.items():
+        if cls is None:
+            assert int(out[name]) == B.RECORD_DTYPE.itemsize == 96
+            continue
+        assert int(out[name]) == C.sizeof(cls), name
+        for f in cls._fields_:
+            assert int(out[f"{name}.{f[0]}"]) == getattr(cls, f[0]).offset, (name, f[0])
 
 
 @pytest.fixture

@@ -266,3 +266,21 @@ def test_paper_guide_fp64_elementwise(ctx):
 
 def test_paper_guide_fp32_tally_agreement(ctx):
     _fp32_case(ctx, W.paper_guide(1_000_000), 1_000_000)
+
+
+# ---------------------------------------------------------------------------
+# Time of flight and the disk chopper
+# ---------------------------------------------------------------------------
+
+def test_paper_chopper_fp64_elementwise(ctx):
+    _, grec, _, _ = _fp64_case(ctx, W.paper_chopper(100_000), 0, 100_000)
+    assert 0.15 < (grec["term"] == B.END_DETECT).mean() < 0.3
+
+
+def test_paper_chopper_mono_fp64_elementwise(ctx):
+    _fp64_case(ctx, W.paper_chopper(50_000, lam_mono=2.0, phase=37.0, tof_bins=3000), 5, 50_000)
+
+
+def test_paper_chopper_fp32_tally_agreement(ctx):
+    _fp32_case(ctx, W.paper_chopper(1_000_000), 1_000_000)
+    _fp32_case(ctx, W.paper_chopper(400_000, chopper=False), 400_000)

@@ -653,3 +653,102 @@ def test_paper_guide_method_of_images():
     assert np.allclose(rec["pos"][hit, 2], 3200.0, atol=1e-6)
     assert hit.sum() > 0.3 * n and wall.sum() > 0.1 * n and (enter & dead).sum() > 0.2 * n
     assert (nx + ny)[hit].max() >= 2
+
+
+# ---------------------------------------------------------------------------
+# Time of flight and the disk chopper (ray-tracing mask)
+# ---------------------------------------------------------------------------
+
+H_OVER_MN = 6.62607015e-34 / 1.67492749804e-27 * 1e13      # mm A / s, from CODATA h and m_n
+E_CONST = 0.0818042                                          # eV A^2, E = E_CONST / lambda^2
+
+
+def test_tof_of_the_maxwellian_beam():
+    """Without the chopper every neutron reaches the detector face 10001 mm away
+    at t = L lambda m_n / h (the path is straight, L(1/cos - 1) < 3e-6 L), so the
+    TOF histogram is the truncated Maxwellian energy law mapped to time."""
+    p = W.paper_chopper(chopper=False, tof_bins=120)
+    n = 400_000
+    r = O.run(p, n=n, threads=8)
+    assert r.stats["detected"] == n
+    L = 10001.0
+    kT = p.source.kT
+    g = stats.gamma(1.5, scale=kT)
+    lam_lo, lam_hi = p.source.lam_lo, p.source.lam_hi
+
+    def cdf_lambda(x):   # P(lambda <= x) = P(E >= E_CONST / x^2)
+        return g.sf(E_CONST / np.asarray(x) ** 2)
+    mass = cdf_lambda(lam_hi) - cdf_lambda(lam_lo)
+    edges = np.linspace(0.0, 0.03, 121)
+    lam_edges = np.clip(edges * H_OVER_MN / L, lam_lo, lam_hi)
+    pb = np.diff(cdf_lambda(np.maximum(lam_edges, 1e-9))) / mass
+    obs = r.sumw[0]
+    keep = pb * n > 20
+    assert obs[~keep].sum() < 0.002 * n
+    assert stats.chisquare(obs[keep], pb[keep] / pb[keep].sum() * obs[keep].sum()).pvalue > 1e-3
+
+
+def _open_fraction(phase_deg, lam, slit=45.0, ngrid=1500):
+    """Fraction of the 45x45 mm slit square that is open when a beam of one
+    wavelength crosses the disk face (independent numpy evaluation of the
+    chopper geometry: 4 windows of 20 degrees from phase, radii 130-250 mm, axis
+    at (0, -190), 100 Hz; crossing time from the straight path from the origin)."""
+    c = (np.arange(ngrid) + 0.5) / ngrid * slit - slit / 2
+    x, y = np.meshgrid(c, c, indexing="ij")
+    zf = 10000.0 - 0.001
+    t = np.sqrt(x * x + y * y + zf * zf) * lam / H_OVER_MN
+    qb, qc = x, y + 190.0
+    rho = np.hypot(qb, qc)
+    ang = np.arctan2(qc, qb) - np.radians(phase_deg) - 2 * np.pi * 100.0 * t
+    m = np.mod(ang, np.pi / 2)
+    return float(((rho >= 130.0) & (m < np.radians(20.0))).mean())
+
+
+def test_chopper_transmission_of_a_mono_beam():
+    """At one wavelength every neutron crosses the disk at the same time (to 1e-5),
+    so the transmitted fraction is the open part of the beam footprint at that
+    instant; with a phase that puts the whole footprint in a window, every neutron
+    passes with weight 1."""
+    lam = 2.0
+    n = 300_000
+    phases = np.arange(0.0, 90.0, 1.0)
+    fr = np.array([_open_fraction(ph, lam, ngrid=300) for ph in phases])
+    ph_half = phases[np.argmin(np.abs(fr - 0.5))]
+    expect = _open_fraction(ph_half, lam)
+    assert 0.3 < expect < 0.7
+    r = O.run(W.paper_chopper(lam_mono=lam, phase=ph_half), n=n, threads=8, records=True)
+    got = r.stats["detected"] / n
+    assert abs(got - expect) < 4 * np.sqrt(expect * (1 - expect) / n), (got, expect)
+    assert r.stats["killed"] + r.stats["detected"] == n
+    assert np.all(r.records["w"][r.records["term"] == O.END_KILL] == 0.0)
+    ph_open = phases[np.argmax(fr)]
+    assert _open_fraction(ph_open, lam) == 1.0
+    r = O.run(W.paper_chopper(lam_mono=lam, phase=ph_open), n=50_000, threads=8, records=True)
+    assert r.stats["detected"] == 50_000 and np.all(r.records["w"] == 1.0)
+
+
+def test_chopper_tof_windows_repeat_at_400_hz():
+    """A point-like beam (1x1 mm slit) crossing the disk at 90 degrees in its frame
+    passes only while (90 deg - 360 deg f t) mod 90 deg < 20 deg: TOF weight lies
+    only in these windows, 0.556 ms wide every 2.5 ms (4 windows x 100 Hz), and
+    every window inside the beam's TOF range is populated."""
+    p = W.paper_chopper(slit=1.0, tof_bins=3000)
+    n = 600_000
+    r = O.run(p, n=n, threads=8)
+    w = 2 * np.pi * 100.0
+    per, th = np.pi / 2, np.radians(20.0)
+    edges = np.linspace(0.0, 0.03, 3001)
+    ks = np.arange(-20, 2)
+    lo = (np.pi / 2 - th - ks * per) / w
+    hi = (np.pi / 2 - ks * per) / w
+    blur = 1e-5 * 0.6     # angular half-width of the 1 mm slit at 190 mm, in time
+    nz = np.nonzero(r.sumw[0])[0]
+    for b in nz:
+        a0, a1 = edges[b], edges[b + 1]
+        assert np.any((a1 >= lo - blur) & (a0 <= hi + blur)), (a0, a1)
+    centers = np.sort((lo + hi)[(lo > 0.002) & (hi < 0.02)] / 2)
+    assert np.allclose(np.diff(centers), 0.0025, atol=1e-12)
+    for c_ in centers:
+        inwin = (edges[:-1] >= c_ - th / w / 2) & (edges[1:] <= c_ + th / w / 2)
+        assert r.sumw[0][inwin].sum() > 0
+    assert 6 <= len(centers) <= 8
