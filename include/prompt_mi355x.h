@@ -96,6 +96,17 @@ typedef struct {
     const double* d;          /* [n_families] A, > 0, non-increasing */
     const int32_t* mult;      /* [n_families] > 0 */
     const double* f2;         /* [n_families] b per cell, >= 0 */
+    /* Optional tabulated cross sections (stand-ins for externally computed
+     * materials): with n_table >= 2 rows, sigma_abs(lambda) and sigma_inc(lambda)
+     * are interpolated linearly in lambda between rows (constant beyond the first
+     * and last rows) and replace the 1/v law and the constant sigma_inc; the
+     * interpolation error on [l_i, l_i+1] is at most (l_i+1 - l_i)^2 / 8 times the
+     * largest |sigma''| there.  Coherent scattering stays the Bragg sum. */
+    int32_t n_table;          /* 0, or 2..4096 */
+    int32_t table_pad;
+    const double* table_lambda;     /* [n_table] A, > 0, strictly increasing */
+    const double* table_sigma_abs;  /* [n_table] b, >= 0 */
+    const double* table_sigma_inc;  /* [n_table] b, >= 0 */
 } pr_material_desc;
 
 /* Mirror on faces of a volume (mirror section).  "tanh": the empirical form

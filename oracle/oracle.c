@@ -105,11 +105,27 @@ static double angstrom_from_ev(double e)
  *           delta on Q = tau contributes when tau < 2k, i.e. 2d > lambda)
  *   out[3] number of active Bragg families.
  * n in 1/A^3 times sigma in barn (1e-8 A^2) gives 1/A; times 1e7 gives 1/mm. */
+/* linear interpolation in a table of rows (x_i, y_i), x increasing, constant
+ * beyond the first and last rows */
+static double table_interp(int n, const double* x, const double* y, double v)
+{
+    if (v <= x[0]) return y[0];
+    if (v >= x[n - 1]) return y[n - 1];
+    int i = 0;
+    while (x[i + 1] < v) ++i;
+    return y[i] + (y[i + 1] - y[i]) * (v - x[i]) / (x[i + 1] - x[i]);
+}
+
 void orc_macro_xs(const orc_material* m, double lambda, double out[4])
 {
     const double barn_per_A3_to_per_mm = 1e-8 * 1e7;
     double sa = m->sigma_abs_ref * lambda / 1.798;
     double si = m->sigma_inc;
+    if (m->n_table >= 2) {
+        /* tabulated cross sections replace the 1/v law and the constant sigma_inc */
+        sa = table_interp(m->n_table, m->table_lambda, m->table_sigma_abs, lambda);
+        si = table_interp(m->n_table, m->table_lambda, m->table_sigma_inc, lambda);
+    }
     double sum = 0.0;
     int active = 0;
     for (int j = 0; j < m->n_families; ++j) {

@@ -63,6 +63,11 @@ typedef struct {
     const double* d;         /* A, canonical order (descending) */
     const int32_t* mult;
     const double* f2;        /* b per cell */
+    int32_t n_table;         /* 0, or rows of tabulated sigma_abs, sigma_inc */
+    int32_t table_pad;
+    const double* table_lambda;
+    const double* table_sigma_abs;
+    const double* table_sigma_inc;
 } orc_material;
 
 typedef struct {

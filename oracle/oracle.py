@@ -40,7 +40,9 @@ class orc_material(C.Structure):
     _fields_ = [("number_density", C.c_double), ("sigma_inc", C.c_double), ("sigma_abs_ref", C.c_double),
                 ("scatter_bias", C.c_double), ("abs_bias", C.c_double), ("cell_volume", C.c_double),
                 ("atoms_per_cell", C.c_int32), ("n_families", C.c_int32),
-                ("d", C.POINTER(C.c_double)), ("mult", C.POINTER(C.c_int32)), ("f2", C.POINTER(C.c_double))]
+                ("d", C.POINTER(C.c_double)), ("mult", C.POINTER(C.c_int32)), ("f2", C.POINTER(C.c_double)),
+                ("n_table", C.c_int32), ("table_pad", C.c_int32), ("table_lambda", C.POINTER(C.c_double)),
+                ("table_sigma_abs", C.POINTER(C.c_double)), ("table_sigma_inc", C.POINTER(C.c_double))]
 
 
 class orc_volume(C.Structure):
@@ -152,6 +154,11 @@ def make_material(m, keep: _Keep) -> orc_material:
     s.d = keep.dptr(m.d)
     s.mult = keep.iptr(m.mult)
     s.f2 = keep.dptr(m.f2)
+    if m.table_lambda is not None:
+        s.n_table = len(m.table_lambda)
+        s.table_lambda = keep.dptr(m.table_lambda)
+        s.table_sigma_abs = keep.dptr(m.table_sigma_abs)
+        s.table_sigma_inc = keep.dptr(m.table_sigma_inc)
     return s
 
 

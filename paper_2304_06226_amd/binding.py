@@ -50,7 +50,9 @@ class pr_material_desc(C.Structure):
     _fields_ = [("number_density", C.c_double), ("sigma_inc", C.c_double), ("sigma_abs_ref", C.c_double),
                 ("scatter_bias", C.c_double), ("abs_bias", C.c_double), ("cell_volume", C.c_double),
                 ("atoms_per_cell", C.c_int32), ("n_families", C.c_int32), ("d", C.POINTER(C.c_double)),
-                ("mult", C.POINTER(C.c_int32)), ("f2", C.POINTER(C.c_double))]
+                ("mult", C.POINTER(C.c_int32)), ("f2", C.POINTER(C.c_double)), ("n_table", C.c_int32),
+                ("table_pad", C.c_int32), ("table_lambda", C.POINTER(C.c_double)),
+                ("table_sigma_abs", C.POINTER(C.c_double)), ("table_sigma_inc", C.POINTER(C.c_double))]
 
 
 class pr_mirror_desc(C.Structure):
@@ -170,6 +172,14 @@ def material_desc(m: W.Material, keep: list) -> pr_material_desc:
     s.d = d.ctypes.data_as(C.POINTER(C.c_double))
     s.mult = mu.ctypes.data_as(C.POINTER(C.c_int32))
     s.f2 = f2.ctypes.data_as(C.POINTER(C.c_double))
+    if m.table_lambda is not None:
+        tl, ta, ti = (np.ascontiguousarray(a, dtype=np.float64)
+                      for a in (m.table_lambda, m.table_sigma_abs, m.table_sigma_inc))
+        keep += [tl, ta, ti]
+        s.n_table = len(tl)
+        s.table_lambda = tl.ctypes.data_as(C.POINTER(C.c_double))
+        s.table_sigma_abs = ta.ctypes.data_as(C.POINTER(C.c_double))
+        s.table_sigma_inc = ti.ctypes.data_as(C.POINTER(C.c_double))
     return s
 
 

@@ -25,6 +25,7 @@ struct Material {
     pr_material_desc desc;
     std::vector<double> d, f2;
     std::vector<int32_t> mult;
+    std::vector<double> tl, ta, ti;   // tabulated lambda, sigma_abs, sigma_inc (empty: analytic)
 };
 
 struct Geometry {
@@ -501,8 +502,27 @@ extern "C" int pr_create_material(pr_ctx* c, const pr_material_desc* d, int32_t*
             if (!finite_nonneg(d->f2[j])) return fail(c, PR_EINVAL, "material.f2[%d] must be >= 0", j);
         }
     }
+    if (d->n_table != 0) {
+        if (d->n_table < 2 || d->n_table > 4096) return fail(c, PR_EINVAL, "material.n_table must be 0 or in [2, 4096]");
+        if (!d->table_lambda || !d->table_sigma_abs || !d->table_sigma_inc)
+            return fail(c, PR_EINVAL, "material table arrays must not be null");
+        for (int j = 0; j < d->n_table; ++j) {
+            if (!(std::isfinite(d->table_lambda[j]) && d->table_lambda[j] > 0))
+                return fail(c, PR_EINVAL, "material.table_lambda[%d] must be > 0", j);
+            if (j > 0 && !(d->table_lambda[j] > d->table_lambda[j - 1]))
+                return fail(c, PR_EINVAL, "material.table_lambda must increase strictly (row %d)", j);
+            if (!finite_nonneg(d->table_sigma_abs[j]) || !finite_nonneg(d->table_sigma_inc[j]))
+                return fail(c, PR_EINVAL, "material table cross sections must be >= 0 (row %d)", j);
+        }
+    }
     Material m;
     m.desc = *d;
+    if (d->n_table > 0) {
+        m.tl.assign(d->table_lambda, d->table_lambda + d->n_table);
+        m.ta.assign(d->table_sigma_abs, d->table_sigma_abs + d->n_table);
+        m.ti.assign(d->table_sigma_inc, d->table_sigma_inc + d->n_table);
+    }
+    m.desc.table_lambda = m.desc.table_sigma_abs = m.desc.table_sigma_inc = nullptr;
     m.d.assign(d->d, d->d + d->n_families);
     m.mult.assign(d->mult, d->mult + d->n_families);
     m.f2.assign(d->f2, d->f2 + d->n_families);
@@ -696,10 +716,19 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
             fd.push_back(f);
             ff.push_back(FamT<float>{(float)f.edge, (float)f.cum, (float)f.inv2d2, 0.0f});
         }
+        // tabulated cross sections: rows (lambda, sigma_abs, sigma_inc) after the families
+        o.tab_begin = (int32_t)fd.size();
+        o.tab_n = (int32_t)M.tl.size();
+        o.tab_k = d.number_density * (1e-8 * 1e7);
+        for (size_t j = 0; j < M.tl.size(); ++j) {
+            fd.push_back(FamT<double>{M.tl[j], M.ta[j], M.ti[j], 0.0});
+            ff.push_back(FamT<float>{(float)M.tl[j], (float)M.ta[j], (float)M.ti[j], 0.0f});
+        }
         md.push_back(o);
         // the FP32 policy divides by its own (float) factors, in FP64
         mf.push_back(MatT<float>{(float)o.sa_per_lambda, (float)o.si, (float)o.sc_k, (float)o.ga, (float)o.gs,
-                                 o.fam_begin, o.nfam, 1.0 / (double)(float)o.ga, 1.0 / (double)(float)o.gs});
+                                 o.fam_begin, o.nfam, 1.0 / (double)(float)o.ga, 1.0 / (double)(float)o.gs,
+                                 o.tab_begin, o.tab_n, (float)o.tab_k});
     }
     g.vd = std::move(vd);
     g.vf = std::move(vf);

@@ -68,6 +68,11 @@ struct MatT {
     R sa_per_lambda, si, sc_k, ga, gs;
     int32_t fam_begin, nfam;
     double inv_ga, inv_gs;   // 1 / ga, 1 / gs in FP64 (weight factors of an interaction)
+    // tabulated sigma_abs(lambda), sigma_inc(lambda): tab_n rows (TabT) stored in the
+    // family row array at tab_begin (tab_n = 0: the 1/v law and constant sigma_inc);
+    // tab_k converts barn to 1/mm for this material's number density
+    int32_t tab_begin, tab_n;
+    R tab_k;
 };
 
 // Bragg family tables, all materials concatenated (canonical order per material)
@@ -93,6 +98,13 @@ constexpr uint32_t kItemVol = 0x0FFFFFFFu;
 constexpr int kItemKindShift = 28;
 constexpr uint32_t kItemDet = 0x80000000u;
 __host__ __device__ inline int item_kind(uint32_t it) { return (int)((it >> kItemKindShift) & 7u); }
+
+// A row of tabulated microscopic cross sections (b) at wavelength lam (A); rows
+// share the family row array (same size and alignment as FamT).
+template <class R>
+struct TabT {
+    R lam, sa, si, pad;
+};
 
 template <class R>
 struct SceneT {
@@ -820,8 +832,35 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
     s.cl = cl;
     s.ga = Mt.ga;
     s.gs = Mt.gs;
-    s.sa = Mt.ga > (R)0 ? Mt.sa_per_lambda * s.lam : (R)0;
-    s.si = Mt.gs > (R)0 ? Mt.si : (R)0;
+    R sa = Mt.sa_per_lambda * s.lam, si = Mt.si;
+    if (Mt.tab_n > 0) {
+        // linear interpolation between the rows around lambda, constant beyond the ends
+        const TabT<R>* T = (const TabT<R>*)(S.fams + Mt.tab_begin);
+        const int n = Mt.tab_n;
+        const R v = s.lam;
+        R a, b;
+        if (v <= T[0].lam) {
+            a = T[0].sa;
+            b = T[0].si;
+        } else if (v >= T[n - 1].lam) {
+            a = T[n - 1].sa;
+            b = T[n - 1].si;
+        } else {
+            int l = 0, h = n - 1;   // first row with lam >= v
+            while (l < h) {
+                const int mid = (l + h) >> 1;
+                if (T[mid].lam < v) l = mid + 1; else h = mid;
+            }
+            const TabT<R>& r0 = T[l - 1];
+            const TabT<R>& r1 = T[l];
+            a = r0.sa + M<R>::div_((r1.sa - r0.sa) * (v - r0.lam), r1.lam - r0.lam);
+            b = r0.si + M<R>::div_((r1.si - r0.si) * (v - r0.lam), r1.lam - r0.lam);
+        }
+        sa = Mt.tab_k * a;
+        si = Mt.tab_k * b;
+    }
+    s.sa = Mt.ga > (R)0 ? sa : (R)0;
+    s.si = Mt.gs > (R)0 ? si : (R)0;
     s.sc = Mt.gs > (R)0 ? Mt.sc_k * s.lam * s.lam * cl : (R)0;
     s.sig = s.sa + s.si + s.sc;
     s.sig_g = s.ga * s.sa + s.gs * (s.si + s.sc);

@@ -50,6 +50,11 @@ class Material:
     d: np.ndarray = field(default_factory=lambda: np.zeros(0))       # A, descending
     mult: np.ndarray = field(default_factory=lambda: np.zeros(0, dtype=np.int32))
     f2: np.ndarray = field(default_factory=lambda: np.zeros(0))      # b per cell
+    # optional tables (lambda [A] increasing, sigma_abs [b], sigma_inc [b]) replacing the
+    # 1/v absorption and the constant incoherent cross section by linear interpolation
+    table_lambda: Optional[np.ndarray] = None
+    table_sigma_abs: Optional[np.ndarray] = None
+    table_sigma_inc: Optional[np.ndarray] = None
 
     def biased(self, scatter_bias=None, abs_bias=None) -> "Material":
         m = dataclasses.replace(self)

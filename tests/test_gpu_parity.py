@@ -284,3 +284,33 @@ def test_paper_chopper_mono_fp64_elementwise(ctx):
 def test_paper_chopper_fp32_tally_agreement(ctx):
     _fp32_case(ctx, W.paper_chopper(1_000_000), 1_000_000)
     _fp32_case(ctx, W.paper_chopper(400_000, chopper=False), 400_000)
+
+
+# ---------------------------------------------------------------------------
+# Tabulated cross sections
+# ---------------------------------------------------------------------------
+
+def _tabulated_problem(n):
+    """The powder sample with absorption and incoherent cross sections given as
+    tables (curved in lambda) and a uniform 1-5 A beam crossing many table rows;
+    coherent scattering stays the Bragg sum."""
+    p = W.config0(n)
+    base = W.sample_material().biased(scatter_bias=2.0)
+    rows = np.linspace(0.8, 5.5, 24)
+    mat = dataclasses.replace(base, table_lambda=rows, table_sigma_abs=1.5 + 0.4 * rows ** 1.5,
+                              table_sigma_inc=3.0 + np.sin(rows))
+    p.materials = [mat]
+    p.source = dataclasses.replace(p.source, spectrum="uniform", lam_lo=1.0, lam_hi=5.0)
+    p.tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0, 180, 180), W.Axis("lambda", 1, 5, 8)]),
+                 W.Tally(trigger="escape", filter="unscattered", axes=[W.Axis("lambda", 1, 5, 40)]),
+                 W.Tally(trigger="absorb", axes=[W.Axis("lambda", 1, 5, 40)])]
+    p.name = "tabulated"
+    return p
+
+
+def test_tabulated_cross_sections_fp64_elementwise(ctx):
+    _fp64_case(ctx, _tabulated_problem(100_000), 31, 100_000)
+
+
+def test_tabulated_cross_sections_fp32(ctx):
+    _fp32_case(ctx, _tabulated_problem(1_000_000), 1_000_000)

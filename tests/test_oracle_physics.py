@@ -752,3 +752,67 @@ def test_chopper_tof_windows_repeat_at_400_hz():
         inwin = (edges[:-1] >= c_ - th / w / 2) & (edges[1:] <= c_ + th / w / 2)
         assert r.sumw[0][inwin].sum() > 0
     assert 6 <= len(centers) <= 8
+
+
+# ---------------------------------------------------------------------------
+# Tabulated cross sections
+# ---------------------------------------------------------------------------
+
+def _tabulated(mat, lam_rows, sa_rows, si_rows):
+    return dataclasses.replace(mat, table_lambda=np.asarray(lam_rows, float), table_sigma_abs=np.asarray(sa_rows, float),
+                               table_sigma_inc=np.asarray(si_rows, float))
+
+
+def test_table_of_the_analytic_law_reproduces_it():
+    """A table sampled from the 1/v absorption law (linear in lambda, so linear
+    interpolation is exact) and the constant incoherent cross section gives the
+    analytic macroscopic cross sections at every wavelength inside it, and the end
+    rows beyond it."""
+    mat = W.sample_material()
+    rows = np.linspace(0.5, 5.0, 10)
+    tab = _tabulated(mat, rows, mat.sigma_abs_ref * rows / 1.798, np.full(10, mat.sigma_inc))
+    for lam in np.linspace(0.55, 4.95, 37):
+        a, b = O.macro_xs(mat, lam), O.macro_xs(tab, lam)
+        assert np.allclose(a[:3], b[:3], rtol=1e-13), lam
+        assert a[3] == b[3]
+    lo, hi = O.macro_xs(tab, 0.2), O.macro_xs(tab, 7.0)
+    assert lo[0] == pytest.approx(0.1 * mat.number_density * mat.sigma_abs_ref * 0.5 / 1.798, rel=1e-13)
+    assert hi[0] == pytest.approx(0.1 * mat.number_density * mat.sigma_abs_ref * 5.0 / 1.798, rel=1e-13)
+
+
+def test_table_interpolation_error_of_a_quadratic():
+    """sigma_inc = 5 + 3 lambda^2 tabulated every 0.5 A: the oracle's values equal an
+    independent linear interpolation, and at the middle of each interval the
+    interpolation error is exactly the stated bound h^2 sigma'' / 8 = 0.1875 b."""
+    mat = W.Material(number_density=0.05, sigma_inc=0.0, sigma_abs_ref=0.0)
+    rows = np.arange(1.0, 6.01, 0.5)
+    tab = _tabulated(mat, rows, np.zeros_like(rows), 5 + 3 * rows ** 2)
+    k = 0.1 * mat.number_density
+    for lam in np.linspace(1.01, 5.99, 50):
+        assert O.macro_xs(tab, lam)[1] == pytest.approx(k * np.interp(lam, rows, 5 + 3 * rows ** 2), rel=1e-13)
+    mids = rows[:-1] + 0.25
+    err = np.array([O.macro_xs(tab, m)[1] / k for m in mids]) - (5 + 3 * mids ** 2)
+    assert np.allclose(err, 0.5 ** 2 * 6 / 8, rtol=1e-10)
+
+
+def test_table_transmission_spectrum():
+    """A uniform 1-6 A pencil through a 10 mm path of a tabulated absorber: the
+    transmitted fraction per wavelength bin is the bin average of
+    exp(-Sigma_interp(lambda) L), Sigma_interp from an independent interpolation."""
+    rows = np.array([1.0, 1.7, 2.5, 3.1, 4.4, 5.2, 6.0])
+    sa = np.array([3.0, 9.0, 4.0, 12.0, 7.0, 2.0, 10.0])
+    si = np.zeros_like(rows)
+    mat = _tabulated(W.Material(number_density=0.06, sigma_inc=0.0, sigma_abs_ref=0.0), rows, sa, si)
+    p = pencil_problem(mat)
+    p.source = dataclasses.replace(p.source, spectrum="uniform", lam_lo=1.0, lam_hi=6.0)
+    p.tallies = [W.Tally(trigger="escape", filter="unscattered", axes=[W.Axis("lambda", 1.0, 6.0, 25)])]
+    n = 400_000
+    r = O.run(p, n=n, threads=8)
+    edges = np.linspace(1.0, 6.0, 26)
+    fine = np.linspace(1.0, 6.0, 250001)
+    tr = np.exp(-0.1 * 0.06 * np.interp(fine, rows, sa) * 10.0)
+    expect = np.array([tr[(fine >= a) & (fine < b)].mean() for a, b in zip(edges[:-1], edges[1:])]) / 25
+    got = r.sumw[0] / n
+    var = expect * (1 - expect) / n
+    z = (got - expect) / np.sqrt(var)
+    assert stats.chi2.sf((z ** 2).sum(), len(z)) > 1e-3, z
