@@ -1041,6 +1041,11 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         }
     }
     P.cache_slots = slots;
+    // the time of flight is tracked only when a chopper or a TOF axis needs it
+    bool need_time = (g.kinds >> kChopperBit) & 1u;
+    for (int i = 0; i < nt; ++i)
+        for (int a = 0; a < P.tallies[i].naxes; ++a) need_time = need_time || P.tallies[i].quantity[a] == PR_Q_TOF;
+    if (need_time) P.kinds |= 1u << kTimeBit;
     P.lds_tally_doubles = lds_doubles;
     P.seed = c->seed;
     P.first = first;
@@ -1271,6 +1276,12 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
         o.n_cell_items = (int)g.cell_items.size();
         o.scene_in_lds = slds ? 1 : 0;
         o.kinds = g.kinds;
+        for (int t = 0; t < sm.n_tallies; ++t) {
+            const pr_tally_desc& tdsc = c->tallies[sm.tallies[t]].desc;
+            for (int a = 0; a < tdsc.naxes; ++a)
+                if (tdsc.axes[a].quantity == PR_Q_TOF) o.kinds |= 1u << kTimeBit;
+        }
+        if ((g.kinds >> kChopperBit) & 1u) o.kinds |= 1u << kTimeBit;
         if (slds) scene_bytes = std::max(scene_bytes, g.scene_lds_bytes);
         o.tally_begin = (int32_t)P.td.size();
         o.tally_count = sm.n_tallies;

@@ -20,6 +20,8 @@ constexpr int kMaxSteps = PR_MAX_STEPS;
 constexpr double kHOverMn = 6.62607015e-34 / 1.67492749804e-27 * 1e13;
 // bit of SceneT::kinds set when some volume carries a disk chopper
 constexpr int kChopperBit = 8;
+// bit of SceneT::kinds set when the run needs the time of flight (a chopper or a TOF tally)
+constexpr int kTimeBit = 9;
 constexpr int kMaxTallies = PR_MAX_TALLIES;
 constexpr int kWave = 64;
 
@@ -1025,7 +1027,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     s.p[0] += x * s.u[0];
     s.p[1] += x * s.u[1];
     s.p[2] += x * s.u[2];
-    s.t += M<R>::div_(x * s.lam, (R)kHOverMn);
+    if ((S.kinds >> kTimeBit) & 1u) s.t += M<R>::div_(x * s.lam, (R)kHOverMn);
     if (sig_g > (R)0) s.w *= (double)M<R>::exp_((sig_g - sig) * x);
 
     if (collide) {
