@@ -314,3 +314,54 @@ def test_tabulated_cross_sections_fp64_elementwise(ctx):
 
 def test_tabulated_cross_sections_fp32(ctx):
     _fp32_case(ctx, _tabulated_problem(1_000_000), 1_000_000)
+
+
+# ---------------------------------------------------------------------------
+# Edge cases: empty runs, the top of the history-id range
+# ---------------------------------------------------------------------------
+
+def test_empty_runs_change_nothing(ctx):
+    import torch
+    print("[case] empty runs", flush=True)
+    prob = W.config0(0)
+    sim = B.Simulation(ctx, prob)
+    ctx.reset_stats()
+    for prec in ("fp64", "fp32"):
+        sim.run(first=123, n=0, precision=prec)
+    batch = W.Batch([W.config0(0), W.config0(0)])
+    br = B.BatchRun(ctx, batch)
+    br.run()
+    pid = ctx.prepare_batch(br.descriptors(), stride=1)
+    ctx.run_prepared(pid)
+    torch.cuda.synchronize()
+    ctx.release_batch(pid)
+    assert ctx.read_stats()["histories"] == 0
+    for s in [sim] + br.sims:
+        for sw, sw2, nh in s.results():
+            assert nh == 0 and not sw.any() and not sw2.any()
+    # an empty simulation inside a batch leaves the others as run alone
+    one = B.BatchRun(ctx, W.Batch([W.config0(0), W.config0(2000)]))
+    alone = B.Simulation(ctx, W.config0(2000))
+    one.run()
+    alone.run(first=one.offsets[1], n=2000, precision="fp32")
+    torch.cuda.synchronize()
+    for (a, a2, na), (b, b2, nb) in zip(one.sims[1].results(), alone.results()):
+        assert na == nb == 2000
+        assert np.allclose(a, b, rtol=1e-12, atol=0) and np.allclose(a2, b2, rtol=1e-12, atol=0)
+
+
+def test_top_of_the_history_id_range_fp64(ctx):
+    """History ids up to 2^62 (the largest accepted first id) drive the counter's
+    high words: element-wise parity there too."""
+    first = (1 << 62) - 1000
+    _fp64_case(ctx, W.config1(1000), first, 1000, threads=4)
+
+
+def test_history_range_limits_are_enforced(ctx):
+    sim = B.Simulation(ctx, W.config0(10))
+    with pytest.raises(B.PromptError) as e:
+        sim.run(first=(1 << 62) + 1, n=10, precision="fp64")
+    assert e.value.code == -1
+    with pytest.raises(B.PromptError) as e:
+        sim.run(first=0, n=(1 << 48) + 1, precision="fp32")
+    assert e.value.code == -1
