@@ -114,7 +114,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the history range would be "
-              "sharded across GPUs with a final tally sum, which this build does not run.", file=sys.stderr)
+              "sharded across GPUs with a final tally sum, which this program does not do.", file=sys.stderr)
         sys.exit(2)
 
     import torch
