@@ -751,7 +751,7 @@ __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root
 
 template <class R, bool REC, bool GRID>
 __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const SceneT<R>& S, uint64_t seed, uint64_t h,
-                                       int root) {
+                                       int root, int start_region = -2) {
     s.h = h;
     s.k = 0;
     s.nbuf = 0;
@@ -811,7 +811,8 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
         s.u[i] = u[i];
     }
     s.lam = lam;
-    s.region = locate<R, GRID>(S, s.p, root);
+    // start_region >= -1: the caller located this (fixed) source point already
+    s.region = start_region >= -1 ? start_region : locate<R, GRID>(S, s.p, root);
     hash_ev<REC>(s.hash, EV_SOURCE, s.region);
     if (s.region < 0) s.term = PR_END_OUTSIDE;
 }

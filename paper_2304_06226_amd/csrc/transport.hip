@@ -215,6 +215,12 @@ __global__ __launch_bounds__(GRID ? 768 : 256) void k_mixed(Params P) {
     unsigned long long cnext = 0, cend = 0;
     const unsigned long long chunk = (unsigned long long)P.chunk;
     const int lane = lane_id();
+    // a pencil starts every history at the same point: locate it once
+    int start_region = -2;
+    if (P.src.kind == PR_PENCIL) {
+        const float o[3] = {(float)P.src.o[0], (float)P.src.o[1], (float)P.src.o[2]};
+        start_region = locate<float, GRID>(S, o, 0);
+    }
     for (;;) {
         const bool idle = s.term != 0;
         const unsigned long long idle_mask = __ballot(idle);
@@ -249,7 +255,8 @@ __global__ __launch_bounds__(GRID ? 768 : 256) void k_mixed(Params P) {
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<float, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0);
+                        source<float, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
+                                                 start_region);
                         pending = s.term != 0;   // born outside the world: counted at the next refill
                     }
                 }
@@ -426,6 +433,12 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
     bool pending = false;
     bool exhausted = false;
     unsigned long long cnext = 0, cend = 0;
+    // a pencil starts every history of the simulation at the same point: locate it once
+    int start_region = -2;
+    if (sd.src.kind == PR_PENCIL) {
+        const float o[3] = {(float)sd.src.o[0], (float)sd.src.o[1], (float)sd.src.o[2]};
+        start_region = locate<float, GRID>(S, o, 0);
+    }
     const unsigned long long end =
         ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ctl.end >> 32)) << 32) |
         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ctl.end);
@@ -465,7 +478,7 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
                         source<float, false, GRID>(s, sd.src, S, B.seed, sd.first + shift + cnext + (unsigned long long)rank,
-                                                   0);
+                                                   0, start_region);
                         pending = s.term != 0;
                     }
                 }
