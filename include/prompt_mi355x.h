@@ -277,9 +277,13 @@ typedef struct {
 } pr_sim;
 
 /* Run nsims independent simulations of uneven size and geometry in one
- * persistent launch of the PR_FP32_MIXED policy (the only policy accepted).
- * Waves claim chunks of one simulation at a time from a shared chunk space
- * spanning all simulations; each lane carries its history's simulation.
+ * persistent launch per class of simulations (scene staged in LDS or not,
+ * daughter grid or not) of the PR_FP32_MIXED policy (the only policy
+ * accepted).  Each block starts on the simulation under its share of the
+ * concatenated history ranges, stages that simulation's scene and tallies in
+ * LDS, and its waves claim chunks of that simulation's histories from the
+ * simulation's own counter until none are left; the block then merges its
+ * tallies and moves to the next simulation that still has histories.
  * Asynchronous on `stream`; each simulation's histories are exactly those of
  * pr_run_histories over the same range.  The descriptors are copied: sims may
  * be reused as soon as the call returns. */
@@ -296,8 +300,8 @@ int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precisi
  * span.  A run consists of kernel launches on `stream` only (no host copies,
  * allocations, memsets or synchronisation), so it may be captured into a HIP
  * graph and replayed; the histories of its tallies are counted on the device
- * and included in pr_read_tally's n_hist.  Runs of one context must not
- * overlap in time (they share its work counter).  Errors as pr_run_batch;
+ * and included in pr_read_tally's n_hist.  Runs of one prepared batch must
+ * not overlap in time (they share its work counters).  Errors as pr_run_batch;
  * PR_ENOTFOUND for an unknown or released batch.  pr_release_batch synchronises
  * the device and frees the batch's device memory. */
 int pr_prepare_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, uint64_t stride,
@@ -313,8 +317,8 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * privatised in order while they fit); bin_cache_slots: LDS bin-cache slots
  * given to each tally that is not privatised (0 or a power of two <= 4096);
  * chunk: history indices a wave claims from the shared counter per atomic;
- * superchunk: histories of one simulation a block claims per visit in
- * pr_run_batch (the block stages that simulation's scene and tallies in LDS).
+ * superchunk: reserved (validated as 1..2^30 and stored; batched runs hand
+ * out work per simulation, see pr_run_batch).
  * Scenes with a daughter grid whose grid, box bounds and tables are staged in
  * LDS run blocks of 256, 512 or 768 threads, whichever keeps the most waves
  * resident per CU, unless blocks_per_cu is set (then `block` is used).

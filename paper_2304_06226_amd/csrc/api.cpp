@@ -90,7 +90,7 @@ struct ClassPlan {
     BatchParams B{};        // device pointers set by bind_plan
     bool slds = false, grid_nav = false;
     int grid = 1, block = 256;
-    size_t b_sims = 0, b_tal = 0, total = 0;   // descriptor byte layout [sims | tallies | key bases]
+    size_t b_sims = 0, b_tal = 0, b_kb = 0, total = 0;   // descriptor layout [sims | tallies | key bases | counters]
 };
 
 // A batch uploaded once for repeated, capturable runs.
@@ -1250,8 +1250,7 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     P.kb.clear();
     P.slds = slds;
     P.grid_nav = grid_nav;
-    const uint64_t sc_size = (uint64_t)c->superchunk;
-    uint64_t scs = 0;
+    uint64_t total = 0;
     int tally_doubles = 0, scene_bytes = 0;
     bool any_cache = false;
     for (int q = 0; q < ns; ++q) {
@@ -1309,8 +1308,8 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
         }
         o.first = sm.first_history;
         o.n = sm.n;
-        o.sc_begin = scs;
-        scs += (sm.n + sc_size - 1) / sc_size;
+        o.hist_begin = total;
+        total += sm.n;
         make_source_dev(c->srcs[sm.src], o.src);
     }
     if (any_cache) tally_doubles = std::max(tally_doubles, 2 * nslots);
@@ -1318,7 +1317,8 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     P.b_sims = al(P.sd.size() * sizeof(SimDev));
     P.b_tal = al(std::max<size_t>(1, P.td.size()) * sizeof(TallyDev));
-    P.total = P.b_sims + P.b_tal + al(P.kb.size() * sizeof(uint64_t));
+    P.b_kb = al(P.kb.size() * sizeof(uint64_t));
+    P.total = P.b_sims + P.b_tal + P.b_kb + al(P.sd.size() * sizeof(uint64_t));   // + per-simulation claim counters
 
     BatchParams& B = P.B;
     memset(&B, 0, sizeof(B));
@@ -1328,12 +1328,11 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     B.cache_bits = any_cache ? cache_bits : 0;
     B.lds_scene_bytes = scene_bytes;
     B.refill_threshold = c->refill_threshold;
-    B.total_superchunks = scs;
-    B.superchunk = sc_size;
+    B.total_histories = total;
     B.chunk = (uint64_t)c->chunk;
     B.seed = c->seed;
     B.stats = trial ? c->scratch_stats : c->stats;
-    B.counter = c->counter;
+    B.sim_next = nullptr;
     B.shift = nullptr;
     const int lds = batch_lds_bytes(B);
     if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
@@ -1341,13 +1340,14 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     if (grid_nav && slds) P.block = grid_block(c, [&](int b) { return batch_occupancy(B, slds, grid_nav, b); });
     const int per_cu =
         c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, P.block);
-    uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, scs);
+    uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, (total + 255) / 256);
     P.grid = (int)std::max<uint64_t>(grid, 1);
     return PR_OK;
 }
 
 // host image of a plan's descriptors, laid out as on the device
 static void pack_plan(const ClassPlan& P, char* h) {
+    memset(h, 0, P.total);
     memcpy(h, P.sd.data(), P.sd.size() * sizeof(SimDev));
     if (!P.td.empty()) memcpy(h + P.b_sims, P.td.data(), P.td.size() * sizeof(TallyDev));
     memcpy(h + P.b_sims + P.b_tal, P.kb.data(), P.kb.size() * sizeof(uint64_t));
@@ -1357,6 +1357,7 @@ static void bind_plan(ClassPlan& P, void* dev) {
     P.B.sims = (const SimDev*)dev;
     P.B.tallies = (const TallyDev*)((char*)dev + P.b_sims);
     P.B.tally_key_base = (const uint64_t*)((char*)dev + P.b_sims + P.b_tal);
+    P.B.sim_next = (unsigned long long*)((char*)dev + P.b_sims + P.b_tal + P.b_kb);
 }
 
 // One persistent launch over the simulations idx of one class.
@@ -1365,7 +1366,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
     ClassPlan P;
     int rc = plan_batch_class(c, sims, idx, slds, grid_nav, trial, P);
     if (rc) return rc;
-    if (P.B.total_superchunks == 0) return PR_OK;
+    if (P.B.total_histories == 0) return PR_OK;
     // descriptors go through a ring slot: pinned staging, then one async copy
     DescSlot& sl = c->slots[c->next_slot];
     c->next_slot = (c->next_slot + 1) % 4;
@@ -1478,7 +1479,7 @@ extern "C" int pr_prepare_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, in
         if (idx.empty()) continue;
         ClassPlan P;
         if ((rc = plan_batch_class(c, sims, idx, (k & 1) != 0, (k & 2) != 0, false, P))) return bail(rc);
-        if (P.B.total_superchunks == 0) continue;
+        if (P.B.total_histories == 0) continue;
         std::vector<char> host(P.total, 0);
         pack_plan(P, host.data());
         void* dev = nullptr;
@@ -1629,7 +1630,7 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->mixed_blocks_per_cu, {0, 2, 3}},
         {&c->bin_cache_slots, {256, 1024, 2048}},
     };
-    if (batched) knobs.push_back({&c->superchunk, {512, 1024, 2048, 4096, 8192}});
+
     float cur = 0.f;
     rc = trial_ms(c, sample, batched, st, e0, e1, 2, &cur);
     for (int pass = 0; pass < 2 && rc == PR_OK; ++pass) {

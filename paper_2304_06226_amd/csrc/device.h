@@ -205,7 +205,7 @@ struct SimDev {
     uint32_t kinds;                // solid kinds present in the scene (bit per kind)
     uint64_t first;                // history id of the simulation's first history
     uint64_t n;                    // histories
-    uint64_t sc_begin;             // first super-chunk of this simulation
+    uint64_t hist_begin;           // position of this simulation's first history in its class
     SourceDev src;
 };
 
@@ -218,9 +218,9 @@ struct BatchParams {
     int32_t cache_bits;               // bin cache of 2^cache_bits slots (values in the tally region)
     int32_t lds_scene_bytes;          // LDS scene region
     int32_t refill_threshold;
-    uint64_t total_superchunks, superchunk, chunk, seed;
+    uint64_t total_histories, chunk, seed;
     unsigned long long* stats;
-    unsigned long long* counter;
+    unsigned long long* sim_next;     // per simulation: next history index to claim (zeroed per launch)
     const unsigned long long* shift;  // prepared batches: history-id offset added to every simulation (or null)
 };
 

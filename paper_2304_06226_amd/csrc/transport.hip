@@ -9,10 +9,10 @@
 //   materials, Bragg tables) is staged into LDS as FP32; small tallies are
 //   privatised in LDS and merged into global memory once per block; the
 //   weight product and every tally accumulation stay FP64.
-// Batched (k_batch): the mixed policy over many simulations at once; each
-//   lane carries its history's simulation, waves claim chunks of one
-//   simulation at a time from a shared chunk space, scenes are read from
-//   global memory and one LDS bin cache serves every simulation's tallies.
+// Batched (k_batch): the mixed policy over many simulations at once; a block
+//   stages one simulation's scene and tallies in LDS and its waves claim chunks
+//   of that simulation's histories from its own counter until none are left,
+//   then the block flushes and moves to the next simulation with work.
 #include "device.h"
 #include "launch.h"
 
@@ -338,17 +338,15 @@ int batch_scene_lds_bytes(int nv, int nm, int nf, int nc, int ng, int ncs, int n
 }
 
 struct BlockCtl {
-    unsigned long long next;   // sub-chunk counter within the current super-chunk
-    unsigned long long end;    // end of the current super-chunk (local history index)
-    unsigned long long sc;     // current super-chunk (>= total: no more work)
-    int sim;
+    int sim;   // simulation the block works on next (-1: no work left)
 };
 
-__device__ __forceinline__ int sim_of_superchunk(const BatchParams& B, unsigned long long j) {
+// simulation holding position pos of the class's concatenated history ranges
+__device__ __forceinline__ int sim_of_position(const BatchParams& B, unsigned long long pos) {
     int lo = 0, hi = B.nsims - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
-        if (B.sims[mid].sc_begin <= j) lo = mid; else hi = mid - 1;
+        if (B.sims[mid].hist_begin <= pos) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -411,10 +409,11 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
     }
 }
 
-// the block's waves run the histories of the current super-chunk
+// the block's waves run histories of simulation `sim`, claiming chunks from its
+// counter, until the simulation has none left
 template <bool SLDS, bool GRID>
-__device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDev& sd, BlockCtl& ctl, char* scene,
-                                               double* ltal, uint32_t* ckeys, Counters& cnt, unsigned long long shift) {
+__device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, int sim, char* scene, double* ltal,
+                                        uint32_t* ckeys, Counters& cnt, unsigned long long shift) {
     SceneT<float> S;
     if (SLDS) {
         const SceneLds L = scene_lds_layout(sd.n_vols, sd.n_mats, sd.n_fams, sd.n_children, sd.n_grids,
@@ -439,9 +438,8 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
         const float o[3] = {(float)sd.src.o[0], (float)sd.src.o[1], (float)sd.src.o[2]};
         start_region = locate<float, GRID>(S, o, 0);
     }
-    const unsigned long long end =
-        ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(ctl.end >> 32)) << 32) |
-        (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)ctl.end);
+    const unsigned long long end = sd.n;
+    unsigned long long* counter = B.sim_next + sim;
     const int lane = lane_id();
     for (;;) {
         const bool idle = s.term != 0;
@@ -461,7 +459,7 @@ __device__ __forceinline__ void run_superchunk(const BatchParams& B, const SimDe
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
                 unsigned long long got = 0;
-                if (lane == leader) got = atomicAdd(&ctl.next, B.chunk);
+                if (lane == leader) got = atomicAdd(counter, B.chunk);
                 got = __shfl(got, leader, kWave);
                 if (got >= end) {
                     exhausted = true;
@@ -508,24 +506,30 @@ __global__ __launch_bounds__(GRID ? 768 : 256) __attribute__((amdgpu_waves_per_e
     Counters cnt = {};
     int staged = -1;
     const unsigned long long shift = B.shift ? *B.shift : 0ull;
+    // Each block starts on the simulation under its share of the concatenated
+    // history ranges and stays with a simulation until its counter runs out, so
+    // LDS staging, tally flushes and block-wide waits happen once per visit.
+    if (threadIdx.x == 0) {
+        const unsigned long long pos =
+            (unsigned long long)((double)B.total_histories * (double)blockIdx.x / (double)gridDim.x);
+        ctl.sim = sim_of_position(B, pos < B.total_histories ? pos : B.total_histories - 1);
+    }
     for (;;) {
         if (threadIdx.x == 0) {
-            const unsigned long long j = atomicAdd(B.counter, 1ull);
-            ctl.sc = j;
-            if (j < B.total_superchunks) {
-                const int sim = sim_of_superchunk(B, j);
-                const SimDev& sd = B.sims[sim];
-                const unsigned long long a = (j - sd.sc_begin) * B.superchunk;
-                ctl.sim = sim;
-                ctl.next = a;
-                ctl.end = a + B.superchunk < sd.n ? a + B.superchunk : sd.n;
+            // the first simulation from ctl.sim on (cyclically) that still has histories
+            int sm = ctl.sim, tries = 0;
+            while (tries < B.nsims &&
+                   __hip_atomic_load(B.sim_next + sm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= B.sims[sm].n) {
+                sm = sm + 1 < B.nsims ? sm + 1 : 0;
+                ++tries;
             }
+            ctl.sim = tries < B.nsims ? sm : -1;
         }
         __syncthreads();
-        if (ctl.sc >= B.total_superchunks) break;
         // block-uniform: read once into scalar registers so the simulation's
         // descriptor is fetched with scalar loads
         const int sim = __builtin_amdgcn_readfirstlane(ctl.sim);
+        if (sim < 0) break;
         const SimDev& sd = B.sims[sim];
         if (sim != staged) {
             if (staged >= 0) {
@@ -549,8 +553,9 @@ __global__ __launch_bounds__(GRID ? 768 : 256) __attribute__((amdgpu_waves_per_e
             __syncthreads();
             staged = sim;
         }
-        run_superchunk<SLDS, GRID>(B, sd, ctl, scene, ltal, ckeys, cnt, shift);
+        run_sim<SLDS, GRID>(B, sd, sim, scene, ltal, ckeys, cnt, shift);
         __syncthreads();
+        if (threadIdx.x == 0) ctl.sim = sim + 1 < B.nsims ? sim + 1 : 0;
     }
     if (staged >= 0) flush_block(B, B.sims[staged], ltal, ckeys);
     flush_counters(cnt, B.stats);
@@ -638,8 +643,8 @@ int batch_lds_bytes(const BatchParams& B) {
 
 // one persistent launch per (scene placement, grid) class of simulations
 hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid, int block, hipStream_t st) {
-    if (B.total_superchunks == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, B.counter, 1);
+    if (B.total_histories == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B.sim_next, B.nsims);
     const int lds = batch_lds_bytes(B);
     const int v = (slds ? 1 : 0) + (grid_nav ? 2 : 0);
     switch (v) {
