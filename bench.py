@@ -47,8 +47,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # only for the kernel sources they were taken on (hash of transport.hip + device.h);
 # profiles/k_mixed_biased_sample_1e7.txt holds the summary.  Nearly all of it is
 # the 32-byte memory-side writes of FP64 tally atomics.
-MEASURED_TRAFFIC = {"source_hash": "0f6f4402a295cc9a",
-                    "k_mixed": 0.417e6 + 355.197e6, "k_plain": 0.486e6 + 669.999e6}
+MEASURED_TRAFFIC = {"source_hash": "756937a119fe60c4",
+                    "k_mixed": 0.433e6 + 355.109e6, "k_plain": 0.495e6 + 669.999e6}
 
 
 def kernel_source_hash() -> str:
@@ -108,7 +108,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "both"], default="both")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-paper-guide", action="store_true")
+    ap.add_argument("--paper-guide", action="store_true",
+                    help="also time the paper's guide benchmark (1e8 neutrons; same kernel as the headline)")
     ap.add_argument("--autotune", action="store_true", help="re-measure the launch tuning before timing")
     ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
@@ -211,7 +212,7 @@ def main():
                                       "1e4-1e6 histories each, odd ones in a vessel) + 1000-box imaging, 1e7 histories"}
         print(f"[bench] batched {bms:.3f} ms/step, {batch.total_histories / bms * 1e3:.4g} histories/s",
               file=sys.stderr, flush=True)
-    if not args.no_paper_guide:
+    if args.paper_guide:
         # the paper's m = 1 guide benchmark at its own size (1e8 neutrons), for context
         # with the paper's only timing (about 140 s on a laptop)
         pg = W.paper_guide()
