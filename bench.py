@@ -97,6 +97,26 @@ def time_policy(torch, sim, n, precision, steps, warmup):
     return ms, stats
 
 
+def time_one_by_one(torch, ctx, br, precision, shift, steps, tunings=None):
+    """The batch's simulations launched one after another with pr_run_histories
+    (history ids shifted by `shift`, then by the batch's span each step)."""
+    def one_pass(sh):
+        for k, (s, o) in enumerate(zip(br.sims, br.offsets)):
+            if tunings is not None:
+                ctx.set_tuning(**tunings[k])
+            s.run(first=o + sh, n=s.prob.n_histories, precision=precision)
+    one_pass(shift)   # warm-up
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for k in range(steps):
+        one_pass(shift + (k + 1) * br.span)
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +132,8 @@ def main():
                     help="also time the paper's guide benchmark (1e8 neutrons; same kernel as the headline)")
     ap.add_argument("--autotune", action="store_true", help="re-measure the launch tuning before timing")
     ap.add_argument("--batch-steps", type=int, default=3)
+    ap.add_argument("--one-by-one-steps", type=int, default=1,
+                    help="steps of the batch's simulations launched one by one (FP64 plain and FP32 mixed); 0 skips")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the history range would be "
@@ -212,6 +234,21 @@ def main():
                                       "1e4-1e6 histories each, odd ones in a vessel) + 1000-box imaging, 1e7 histories"}
         print(f"[bench] batched {bms:.3f} ms/step, {batch.total_histories / bms * 1e3:.4g} histories/s",
               file=sys.stderr, flush=True)
+        if args.one_by_one_steps > 0:
+            # the same simulations, one launch each: FP64 plain (the batch's precision
+            # baseline) and FP32 mixed with each workload's stored tuning (the gain of batching)
+            shift = 4 * br.span
+            ms64 = time_one_by_one(torch, ctx, br, "fp64", shift, args.one_by_one_steps)
+            shift += (args.one_by_one_steps + 1) * br.span
+            tunings = [TUNED["imaging"] if p.name.startswith("imaging") else TUNED["sample"] for p in batch.problems]
+            ms32 = time_one_by_one(torch, ctx, br, "fp32", shift, args.one_by_one_steps, tunings)
+            out["batched"]["one_by_one"] = {
+                "fp64_plain": {"value": batch.total_histories / ms64 * 1e3, "ms_per_step": ms64},
+                "fp32_mixed": {"value": batch.total_histories / ms32 * 1e3, "ms_per_step": ms32},
+                "launches_per_step": len(batch.problems)}
+            out["batched"]["speedup_vs_fp64_plain"] = ms64 / bms
+            print(f"[bench] one by one: fp64-plain {ms64:.3f} ms, fp32-mixed {ms32:.3f} ms per step",
+                  file=sys.stderr, flush=True)
     if args.paper_guide:
         # the paper's m = 1 guide benchmark at its own size (1e8 neutrons), for context
         # with the paper's only timing (about 140 s on a laptop)

@@ -126,7 +126,7 @@ struct pr_ctx {
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     DescSlot slots[4];
-    int superchunk = 2048;              // batched runs: histories a block claims per simulation visit
+    int superchunk = 2048;              // reserved tuning field: validated and stored, not used
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
     uint64_t scratch_bins = 0;
     unsigned long long* scratch_stats = nullptr;

@@ -429,6 +429,7 @@ struct Pieces {
     int n;
 };
 
+
 // component i of a 3-vector by selects (no dynamically indexed private array)
 template <class R>
 __device__ __forceinline__ R pick(const R v[3], int i) {
@@ -531,6 +532,34 @@ __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int 
 }
 
 // pieces of the ray q + t u (q relative to the centre) inside a box of half sides h
+// Shortest piece a history enters.  In FP32 a piece only a few ulps of the
+// position long (a ray grazing an edge or touching a curved surface) can be
+// crossed without the position changing at all; the next step would then find
+// the same piece ahead and re-enter it, for ever.  Pieces shorter than about
+// eight ulps of the largest coordinate are therefore passed by in FP32 (the
+// material skipped is under 1e-6 of the coordinate).  FP64 enters every piece.
+template <class R>
+__device__ __forceinline__ R sliver_tol(const R p[3]) {
+    if constexpr (sizeof(R) == 4)
+        return (__builtin_fabsf(p[0]) + __builtin_fabsf(p[1]) + __builtin_fabsf(p[2])) * 9.5367431640625e-07f;   // 2^-20
+    else
+        return (R)0;
+}
+
+// distance to where the ray enters a daughter's first piece ahead (rinf: none)
+template <class R>
+__device__ __forceinline__ R entry_distance(const Pieces<R>& P, R tol) {
+    if constexpr (sizeof(R) == 4) {
+        if (P.n > 0 && P.a0 > (R)0 && P.b0 - P.a0 > tol) return P.a0;
+        if (P.n > 1 && P.a1 > (R)0 && P.b1 - P.a1 > tol) return P.a1;
+        return rinf<R>();
+    } else {
+        if (P.n > 0 && P.a0 > (R)0) return P.a0;
+        if (P.n > 1 && P.a1 > (R)0) return P.a1;
+        return rinf<R>();
+    }
+}
+
 template <class R>
 __device__ __forceinline__ void box_pieces(const R q[3], const R u[3], const R h[3], Pieces<R>& P) {
     P.n = 0;
@@ -878,7 +907,7 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
 
 template <class R>
 __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>& G, const R p[3], const R u[3], R tmax,
-                                             R& d_child, int& child, int& child_det) {
+                                             R tol, R& d_child, int& child, int& child_det) {
     R t0 = (R)0, t1 = tmax;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -922,9 +951,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
             const uint32_t item = (uint32_t)S.cell_items[j];
             Pieces<R> Q;
             item_pieces<R>(S, item, p, u, Q);
-            R a = rinf<R>();
-            if (Q.n > 0 && Q.a0 > (R)0) a = Q.a0;
-            else if (Q.n > 1 && Q.a1 > (R)0) a = Q.a1;
+            const R a = entry_distance<R>(Q, tol);
             if (a < d_child) {
                 d_child = a;
                 child = (int)(item & kItemVol);
@@ -955,7 +982,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 // equal entry distances the lower daughter index wins, as in a scan in order.
 template <class R, int K, class ST>
 __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, const ST& s, uint32_t items, R& d_exit,
-                                          int& face, R& d_child, int& child, int& child_item, int& child_det) {
+                                          int& face, R tol, R& d_child, int& child, int& child_item, int& child_det) {
     if (((S.kinds >> K) & 1u) == 0u) return;
     while (__ballot(items != 0u) != 0ull) {
         if (items != 0u) {
@@ -968,9 +995,7 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
                 if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
                 if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
             } else {
-                R a = rinf<R>();
-                if (P.n > 0 && P.a0 > (R)0) a = P.a0;
-                else if (P.n > 1 && P.a1 > (R)0) a = P.a1;
+                const R a = entry_distance<R>(P, tol);
                 if (a < d_child || (a == d_child && a != rinf<R>() && i < child_item)) {
                     d_child = a;
                     child = vid;
@@ -1000,13 +1025,14 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     int face = -1;
     R d_child = rinf<R>();
     int child = -1, child_item = 0, child_det = 0;
-    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
-    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
-    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
-    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, d_child, child, child_item, child_det);
-    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    const R tol = sliver_tol<R>(s.p);
+    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, tol, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
-    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, d_child, child, child_det);
+    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, tol, d_child, child, child_det);
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
 

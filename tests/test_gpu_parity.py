@@ -102,6 +102,51 @@ def test_detector_and_tally_filters(ctx):
     _fp64_case(ctx, prob, 777, 50_000)
 
 
+def _grazing_problem(n, grid):
+    """A beam cutting the edge of a vacuum box (sides 20 mm at the origin) along the
+    diagonal of the x-z plane: the rays pass through pieces of the box from about
+    28 um long down to below one FP32 ulp of the position, or miss it.  With
+    grid=True nine small boxes away from the beam give the world a daughter grid."""
+    vols = [W.Volume("box", (0.0, 0.0, 0.0), (200.0, 200.0, 200.0)),
+            W.Volume("box", (0.0, 0.0, 0.0), (20.0, 20.0, 20.0), parent=0)]
+    if grid:
+        vols += [W.Volume("box", (x, 50.0, 50.0), (5.0, 5.0, 5.0), parent=0) for x in range(-80, 81, 20)]
+    c = float(np.sqrt(0.5))
+    src = W.Source("rect", origin=(-30.0, 0.0, 10.0), direction=(c, 0.0, -c), size=(4e-5, 1.0),
+                   spectrum="mono", lam0=2.0)
+    return W.Problem([], vols, src, [W.Tally(trigger="escape")], n_histories=n, name="grazing")
+
+
+@pytest.mark.parametrize("grid", [False, True])
+def test_grazing_edge_fp32_makes_progress(ctx, grid):
+    """A piece shorter than the position's rounding must not trap a history: every
+    ray enters and leaves the box (or misses it) and escapes within four steps."""
+    n = 100_000
+    prob = _grazing_problem(n, grid)
+    print(f"[case] grazing edge fp32 grid={grid} n={n}", flush=True)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=n, precision="fp32")
+    assert gst["capped"] == 0
+    assert np.all(grec["term"] == B.END_ESCAPE)
+    assert grec["n_steps"].max() <= 4
+    assert gres[0][2] == n and abs(gres[0][0][0] - n) < 1e-6
+
+
+def test_imaging_history_that_grazed_an_edge_fp32(ctx):
+    """History 21469436 of the 1000-box imaging problem (run seed 4096) grazes a box
+    edge after its first scattering; without the FP32 piece tolerance it re-entered
+    the same piece until the step cap."""
+    prob = W.imaging_problem(n=64)
+    print("[case] imaging fp32 histories 21469436..+64", flush=True)
+    gres, grec, gst = gpu_run(ctx, prob, first=21_469_436, n=64, precision="fp32")
+    assert gst["capped"] == 0 and grec["n_steps"].max() < 200
+
+
+@pytest.mark.parametrize("grid", [False, True])
+def test_grazing_edge_fp64_elementwise(ctx, grid):
+    _, grec, _, same = _fp64_case(ctx, _grazing_problem(20_000, grid), 0, 20_000)
+    assert grec["n_steps"].max() <= 4
+
+
 # ---------------------------------------------------------------------------
 # FP32 mixed policy
 # ---------------------------------------------------------------------------
