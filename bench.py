@@ -75,8 +75,16 @@ def cpu_baseline(prob, seconds: float) -> dict:
     t0 = time.perf_counter()
     O.run(prob, first=0, n=n, threads=threads)
     dt = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "histories/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n} histories of the same workload (FP64 oracle, {threads} threads, {dt:.1f} s)"}
+            "sample": f"first {n} histories of the same workload (FP64 oracle, {threads} threads, {dt:.1f} s)",
+            "single_thread_value": rate1, "single_thread_sample": "first 20000 histories, 1 thread",
+            "cpu_model": cpu, "nproc": os.cpu_count()}
 
 
 def time_policy(torch, sim, n, precision, steps, warmup):
