@@ -1628,7 +1628,7 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->refill_threshold, {4, 8, 16, 24, 32, 48}},
         {&c->chunk, {64, 128, 256, 512, 1024}},
         {&c->mixed_blocks_per_cu, {0, 2, 3}},
-        {&c->bin_cache_slots, {256, 1024, 2048}},
+        {&c->bin_cache_slots, {0, 256, 1024, 2048}},
     };
 
     float cur = 0.f;

@@ -1,20 +1,22 @@
 """Launch tunings of the PR_FP32_MIXED policy measured on one MI355X with
 pr_autotune (coordinate descent over the pr_tuning knobs, HIP-event timed), per
 named workload.  Results do not depend on them beyond floating-point summation
-order; Context.autotune re-measures them."""
+order; Context.autotune re-measures them.  Workloads whose large tallies are hit
+at random bins (guide, vessel, imaging) run without the LDS bin cache: it would
+rarely hit and every score would pay its probes."""
 
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
                "bin_cache_slots": 256, "chunk": 512, "superchunk": 2048},
     "guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 1024, "chunk": 1024, "superchunk": 2048},
+              "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 1024, "chunk": 256, "superchunk": 2048},
+               "bin_cache_slots": 0, "chunk": 256, "superchunk": 2048},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 1024, "chunk": 64, "superchunk": 2048},
+                "bin_cache_slots": 0, "chunk": 64, "superchunk": 2048},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 1024, "chunk": 1024, "superchunk": 2048},
+                    "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
               "bin_cache_slots": 2048, "chunk": 64, "superchunk": 2048},
 }
