@@ -8,7 +8,7 @@ rarely hit and every score would pay its probes."""
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 512, "superchunk": 2048},
+               "bin_cache_slots": 256, "chunk": 1024, "superchunk": 2048},
     "guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
               "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
