@@ -3,7 +3,9 @@ pr_autotune (coordinate descent over the pr_tuning knobs, HIP-event timed), per
 named workload.  Results do not depend on them beyond floating-point summation
 order; Context.autotune re-measures them.  Workloads whose large tallies are hit
 at random bins (guide, vessel, imaging) run without the LDS bin cache: it would
-rarely hit and every score would pay its probes."""
+rarely hit and every score would pay its probes.  The sample and batch entries
+were re-measured at full size: the autotuner's reduced samples shift where the
+last claims of a launch fall, which is what decides the best chunk there."""
 
 # workload name -> pr_tuning fields
 TUNED = {
@@ -18,5 +20,5 @@ TUNED = {
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
                     "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 2048, "chunk": 64, "superchunk": 2048},
+              "bin_cache_slots": 256, "chunk": 256, "superchunk": 2048},
 }
