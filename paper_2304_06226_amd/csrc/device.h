@@ -325,7 +325,8 @@ struct PState {
     R ub0, ub1, ub2, ub3, ub4;   // FP32 draws: buffered uniforms for draws k .. k+nbuf-1
     int32_t nbuf;
     int32_t region, nscat, steps, term;
-    // cross sections cached for material xs_mat (lambda is constant per history)
+    // cross sections cached for material xs_mat at wavelength lam (-2: none); a
+    // state must start with xs_mat = -2 before its first source()
     int32_t xs_mat, nact;
     R sa, si, sc, sig, sig_g, ga, gs, cl;
     R t;   // time since emission, s
@@ -789,7 +790,6 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     s.nscat = 0;
     s.steps = 0;
     s.term = 0;
-    s.xs_mat = -2;
     s.hash = 14695981039346656037ull;
     R p[3] = {(R)src.o[0], (R)src.o[1], (R)src.o[2]};
     R u[3] = {(R)src.u[0], (R)src.u[1], (R)src.u[2]};
@@ -839,6 +839,9 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
         s.p[i] = p[i];
         s.u[i] = u[i];
     }
+    // the cached cross sections depend on (material, lambda) only: a lane keeps
+    // them from its previous history when the wavelength is the same
+    if (!(lam == s.lam)) s.xs_mat = -2;
     s.lam = lam;
     // start_region >= -1: the caller located this (fixed) source point already
     s.region = start_region >= -1 ? start_region : locate<R, GRID>(S, s.p, root);

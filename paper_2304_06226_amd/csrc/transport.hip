@@ -75,6 +75,8 @@ __global__ __launch_bounds__(256) void k_plain(Params P) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < P.n) {
         PState<double> s;
+        s.xs_mat = -2;
+        s.lam = -1.0;
         source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
         while (s.term == 0) step<double, REC, GRID>(s, S, P.seed);
         if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
@@ -208,6 +210,8 @@ __global__ __launch_bounds__(GRID ? 768 : 256) void k_mixed(Params P) {
     Counters cnt = {};
     PState<float> s;
     s.term = 1;            // idle, no history
+    s.xs_mat = -2;         // no cached cross sections
+    s.lam = -1.f;
     bool pending = false;  // finished history not yet scored
     bool exhausted = false;
     // the wave's current chunk of history indices [cnext, cend), claimed with one
@@ -429,6 +433,8 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
     }
     PState<float> s;
     s.term = 1;
+    s.xs_mat = -2;   // material indices are the simulation's own
+    s.lam = -1.f;
     bool pending = false;
     bool exhausted = false;
     unsigned long long cnext = 0, cend = 0;
