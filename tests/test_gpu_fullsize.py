@@ -1,5 +1,6 @@
 """GPU parity at the workloads' full sizes, in the launch configuration the
-benchmark uses (autotuned FP32-mixed, or FP64 plain), checked on sampled
+benchmark and the runner use (the stored FP32-mixed tuning of each workload, or
+FP64 plain), checked on sampled
 histories the oracle recomputes one by one, against closed forms, and against
 oracle samples through the tally agreement test.
 """
@@ -12,6 +13,7 @@ from scipy import stats
 from oracle import oracle as O
 from paper_2304_06226_amd import binding as B
 from paper_2304_06226_amd import workloads as W
+from paper_2304_06226_amd.tuning import TUNED
 
 from parity import compare_records_fp64, tally_stat_test
 
@@ -32,9 +34,10 @@ def total_sigma(mat, lam):
     return xs[0] + xs[1] + xs[2]
 
 
-def _tuned(ctx, sim, n):
+def _tuned(ctx, name):
+    """Apply the stored tuning of workload `name`; returns the previous one."""
     base = ctx.get_tuning()
-    ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=0.2)
+    ctx.set_tuning(**TUNED[name])
     return base
 
 
@@ -44,7 +47,7 @@ def test_biased_sample_full_1e7_fp32(ctx):
     n = prob.n_histories
     print(f"[case] biased sample fp32 n={n}", flush=True)
     sim = B.Simulation(ctx, prob)
-    base = _tuned(ctx, sim, n)
+    base = _tuned(ctx, "sample")
     try:
         ctx.reset_stats()
         sim.run(first=0, n=n, precision="fp32")
@@ -91,7 +94,7 @@ def test_vessel_full_1e8_fp32(ctx):
     n = prob.n_histories
     print(f"[case] vessel fp32 n={n}", flush=True)
     sim = B.Simulation(ctx, prob)
-    base = _tuned(ctx, sim, n // 10)
+    base = _tuned(ctx, "vessel")
     try:
         ctx.reset_stats()
         sim.run(first=0, n=n, precision="fp32")
@@ -135,7 +138,7 @@ def test_guide_full_1e8_fp32_full_tally(ctx):
     print(f"[case] guide fp32 n={n}, 4e8-bin tally", flush=True)
     sim = B.Simulation(ctx, prob)
     assert ctx.tally_nbins(sim.tallies[0]) == 400_000_000
-    base = _tuned(ctx, sim, n // 10)
+    base = _tuned(ctx, "guide")
     try:
         ctx.reset_stats()
         sim.run(first=0, n=n, precision="fp32")
@@ -169,9 +172,8 @@ def test_batch_full_closed_forms(ctx):
     batch = W.config4()
     print(f"[case] full batch: {len(batch.problems)} simulations, {batch.total_histories} histories", flush=True)
     br = B.BatchRun(ctx, batch)
-    base = ctx.get_tuning()
+    base = _tuned(ctx, "batch")
     try:
-        ctx.autotune(br.descriptors(), sample_fraction=0.05)
         ctx.reset_stats()
         br.run()
         torch.cuda.synchronize()
@@ -257,7 +259,7 @@ def test_paper_guide_full_1e8_fp32(ctx):
     n = prob.n_histories
     print(f"[case] paper guide fp32 n={n}", flush=True)
     sim = B.Simulation(ctx, prob)
-    base = _tuned(ctx, sim, n // 10)
+    base = _tuned(ctx, "paper_guide")
     try:
         ctx.reset_stats()
         sim.run(first=0, n=n, precision="fp32")
