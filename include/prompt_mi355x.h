@@ -320,7 +320,7 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * superchunk: reserved (validated as 1..2^30 and stored; batched runs hand
  * out work per simulation, see pr_run_batch).
  * Scenes with a daughter grid whose grid, box bounds and tables are staged in
- * LDS run blocks of 256, 512 or 768 threads, whichever keeps the most waves
+ * LDS run blocks of 256 or 512 threads, whichever keeps the most waves
  * resident per CU, unless blocks_per_cu is set (then `block` is used).
  * Results do not depend on these settings beyond floating-point summation
  * order. */

@@ -941,14 +941,14 @@ static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
 constexpr int kLdsPerCu = 160 * 1024;
 
 // Block size for kernels that stage a grid scene into LDS: the staged copy is
-// large, so fewer, larger blocks share it; take the size (up to 768 threads)
+// large, so fewer, larger blocks share it; take the size (256 or 512 threads)
 // that keeps the most waves resident per CU, the smallest among equals.  A
 // block count per CU set by the tuning keeps the tuned block size.
 template <class Occ>
 static int grid_block(const pr_ctx* c, Occ occupancy) {
     if (c->mixed_blocks_per_cu > 0) return c->mixed_block;
     int best = c->mixed_block, best_waves = occupancy(best) * (best / 64);
-    for (int b = 256; b <= 768; b += 256) {
+    for (int b = 256; b <= 512; b += 256) {
         const int w = occupancy(b) * (b / 64);
         if (w > best_waves) { best = b; best_waves = w; }
     }
