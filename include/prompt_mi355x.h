@@ -319,6 +319,10 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * chunk: history indices a wave claims from the shared counter per atomic;
  * superchunk: reserved (validated as 1..2^30 and stored; batched runs hand
  * out work per simulation, see pr_run_batch).
+ * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
+ * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
+ * spilling some state to scratch; which is faster depends on the workload);
+ * kernels with a daughter grid always run 4.
  * Scenes with a daughter grid whose grid, box bounds and tables are staged in
  * LDS run blocks of 256 or 512 threads, whichever keeps the most waves
  * resident per CU, unless blocks_per_cu is set (then `block` is used).
@@ -332,6 +336,7 @@ typedef struct {
     int32_t bin_cache_slots;
     int32_t chunk;
     int32_t superchunk;
+    int32_t waves_per_simd;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);

@@ -127,6 +127,7 @@ struct pr_ctx {
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     DescSlot slots[4];
     int superchunk = 2048;              // reserved tuning field: validated and stored, not used
+    int waves_per_simd = 4;             // FP32 kernels without a grid: variant built for 4 or 5 waves per SIMD
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
     uint64_t scratch_bins = 0;
     unsigned long long* scratch_stats = nullptr;
@@ -1055,6 +1056,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.counter = c->counter;
     P.refill_threshold = c->refill_threshold;
     P.chunk = c->chunk;
+    P.waves = c->waves_per_simd;
     return PR_OK;
 }
 
@@ -1207,6 +1209,9 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
         return fail(c, PR_EINVAL, "tuning.bin_cache_slots must be 0 or a power of two up to 4096");
     if (t->chunk < 1 || t->chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.chunk must be 1..2^20");
     if (t->superchunk < 1 || t->superchunk > (1 << 30)) return fail(c, PR_EINVAL, "tuning.superchunk must be 1..2^30");
+    if (t->waves_per_simd != 0 && t->waves_per_simd != 4 && t->waves_per_simd != 5)
+        return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
+    c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
     c->superchunk = t->superchunk;
     c->mixed_block = t->block;
@@ -1226,6 +1231,7 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->bin_cache_slots = c->bin_cache_slots;
     t->chunk = c->chunk;
     t->superchunk = c->superchunk;
+    t->waves_per_simd = c->waves_per_simd;
     return PR_OK;
 }
 
@@ -1328,6 +1334,7 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     B.cache_bits = any_cache ? cache_bits : 0;
     B.lds_scene_bytes = scene_bytes;
     B.refill_threshold = c->refill_threshold;
+    B.waves = c->waves_per_simd;
     B.total_histories = total;
     B.chunk = (uint64_t)c->chunk;
     B.seed = c->seed;
@@ -1629,6 +1636,7 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->chunk, {64, 128, 256, 512, 1024}},
         {&c->mixed_blocks_per_cu, {0, 2, 3}},
         {&c->bin_cache_slots, {0, 256, 1024, 2048}},
+        {&c->waves_per_simd, {4, 5}},
     };
 
     float cur = 0.f;

@@ -180,14 +180,14 @@ struct Params {
     unsigned long long* counter;   // history counter of the persistent policy
     int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
+    int32_t waves;                 // persistent policy: waves per SIMD the launched variant is built for (4 or 5)
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)
-// in one launch.  A block works on one simulation at a time: it claims a
-// super-chunk of that simulation's histories, stages the simulation's FP32
-// scene and tallies into LDS (when they fit) and hands sub-chunks to its
-// waves through an LDS counter; it flushes and restages only when the next
-// super-chunk belongs to another simulation.
+// in one launch.  A block works on one simulation at a time: it stages the
+// simulation's FP32 scene and tallies into LDS (when they fit), its waves claim
+// chunks of that simulation's histories from the simulation's own counter until
+// none are left, and only then does the block flush and move on.
 struct SimDev {
     // the simulation's own FP32 scene (local indices; world = volume 0)
     const VolT<float>* vols;
@@ -218,6 +218,7 @@ struct BatchParams {
     int32_t cache_bits;               // bin cache of 2^cache_bits slots (values in the tally region)
     int32_t lds_scene_bytes;          // LDS scene region
     int32_t refill_threshold;
+    int32_t waves;                    // waves per SIMD the launched variant is built for (4 or 5)
     uint64_t total_histories, chunk, seed;
     unsigned long long* stats;
     unsigned long long* sim_next;     // per simulation: next history index to claim (zeroed per launch)

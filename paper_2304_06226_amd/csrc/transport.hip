@@ -178,11 +178,13 @@ __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes
     for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) d[i] = s[i];
 }
 
-template <bool REC, bool SLDS, bool GRID>
-// Four waves per SIMD for every variant: the grid variants would take 151 VGPRs
-// (three waves); held to 128 they spill a few values to scratch, and the extra
-// wave per SIMD hides the latency of the grid walk (1000-box imaging 10.3 -> 8.6 ms).
-__global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_mixed(Params P) {
+// WPE resident waves per SIMD (4 or 5; grid variants 4).  The grid variants would
+// take 151 VGPRs (three waves); held to 128 they spill a few values to scratch,
+// and the extra wave per SIMD hides the latency of the grid walk (1000-box
+// imaging 10.3 -> 8.6 ms).  Five waves (96 VGPRs) help some scenes and hurt
+// others, so it is a launch choice.
+template <bool REC, bool SLDS, bool GRID, int WPE>
+__global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_mixed(Params P) {
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
     char* base = (char*)lds;
@@ -503,8 +505,8 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
     }
 }
 
-template <bool SLDS, bool GRID>
-__global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_batch(
+template <bool SLDS, bool GRID, int WPE>
+__global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_batch(
     BatchParams B) {
     extern __shared__ double lds[];
     __shared__ BlockCtl ctl;
@@ -610,14 +612,20 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     return hipGetLastError();
 }
 
+// variant index: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five waves per SIMD (no grid only)
+static int mixed_variant(const Params& P) {
+    return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0);
+}
+
 template <bool REC>
 static void launch_mixed_t(const Params& P, int grid, int block, int lds, hipStream_t st) {
-    const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((k_mixed<REC, false, false>), dim3(grid), dim3(block), lds, st, P); break;
-    case 1: hipLaunchKernelGGL((k_mixed<REC, true, false>), dim3(grid), dim3(block), lds, st, P); break;
-    case 2: hipLaunchKernelGGL((k_mixed<REC, false, true>), dim3(grid), dim3(block), lds, st, P); break;
-    default: hipLaunchKernelGGL((k_mixed<REC, true, true>), dim3(grid), dim3(block), lds, st, P); break;
+    switch (mixed_variant(P)) {
+    case 0: hipLaunchKernelGGL((k_mixed<REC, false, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 1: hipLaunchKernelGGL((k_mixed<REC, true, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 2: hipLaunchKernelGGL((k_mixed<REC, false, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 3: hipLaunchKernelGGL((k_mixed<REC, true, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 4: hipLaunchKernelGGL((k_mixed<REC, false, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
+    default: hipLaunchKernelGGL((k_mixed<REC, true, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
     }
 }
 
@@ -633,13 +641,14 @@ hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStrea
 int mixed_occupancy(const Params& P, int block) {
     int nb = 0;
     const int lds = mixed_lds_bytes(P);
-    const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0);
     hipError_t e;
-    switch (v) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false>, block, lds); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false>, block, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, true>, block, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, true>, block, lds); break;
+    switch (mixed_variant(P)) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false, 4>, block, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false, 4>, block, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, true, 4>, block, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, true, 4>, block, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false, 5>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false, 5>, block, lds); break;
     }
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
@@ -650,17 +659,23 @@ int batch_lds_bytes(const BatchParams& B) {
     return B.lds_tally_doubles * 8 + align16(nslots * 4) + B.lds_scene_bytes;
 }
 
+// variant index: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five waves per SIMD (no grid only)
+static int batch_variant(const BatchParams& B, bool slds, bool grid_nav) {
+    return (slds ? 1 : 0) + (grid_nav ? 2 : 0) + (B.waves == 5 && !grid_nav ? 4 : 0);
+}
+
 // one persistent launch per (scene placement, grid) class of simulations
 hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid, int block, hipStream_t st) {
     if (B.total_histories == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3((B.nsims + 63) / 64), dim3(64), 0, st, B.sim_next, B.nsims);
     const int lds = batch_lds_bytes(B);
-    const int v = (slds ? 1 : 0) + (grid_nav ? 2 : 0);
-    switch (v) {
-    case 0: hipLaunchKernelGGL((k_batch<false, false>), dim3(grid), dim3(block), lds, st, B); break;
-    case 1: hipLaunchKernelGGL((k_batch<true, false>), dim3(grid), dim3(block), lds, st, B); break;
-    case 2: hipLaunchKernelGGL((k_batch<false, true>), dim3(grid), dim3(block), lds, st, B); break;
-    default: hipLaunchKernelGGL((k_batch<true, true>), dim3(grid), dim3(block), lds, st, B); break;
+    switch (batch_variant(B, slds, grid_nav)) {
+    case 0: hipLaunchKernelGGL((k_batch<false, false, 4>), dim3(grid), dim3(block), lds, st, B); break;
+    case 1: hipLaunchKernelGGL((k_batch<true, false, 4>), dim3(grid), dim3(block), lds, st, B); break;
+    case 2: hipLaunchKernelGGL((k_batch<false, true, 4>), dim3(grid), dim3(block), lds, st, B); break;
+    case 3: hipLaunchKernelGGL((k_batch<true, true, 4>), dim3(grid), dim3(block), lds, st, B); break;
+    case 4: hipLaunchKernelGGL((k_batch<false, false, 5>), dim3(grid), dim3(block), lds, st, B); break;
+    default: hipLaunchKernelGGL((k_batch<true, false, 5>), dim3(grid), dim3(block), lds, st, B); break;
     }
     return hipGetLastError();
 }
@@ -668,13 +683,14 @@ hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid
 int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block) {
     int nb = 0;
     const int lds = batch_lds_bytes(B);
-    const int v = (slds ? 1 : 0) + (grid_nav ? 2 : 0);
     hipError_t e;
-    switch (v) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, false>, block, lds); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, false>, block, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, true>, block, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, true>, block, lds); break;
+    switch (batch_variant(B, slds, grid_nav)) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, false, 4>, block, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, false, 4>, block, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, true, 4>, block, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, true, 4>, block, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<false, false, 5>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch<true, false, 5>, block, lds); break;
     }
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;

@@ -5,20 +5,22 @@ order; Context.autotune re-measures them.  Workloads whose large tallies are hit
 at random bins (guide, vessel, imaging) run without the LDS bin cache: it would
 rarely hit and every score would pay its probes.  The sample and batch entries
 were re-measured at full size: the autotuner's reduced samples shift where the
-last claims of a launch fall, which is what decides the best chunk there."""
+last claims of a launch fall, which is what decides the best chunk there.
+waves_per_simd 5 (kernels held to 96 VGPRs) is faster for the vessel, the
+paper's guide and the batch's powder simulations, slower for the others."""
 
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 1024, "superchunk": 2048},
+               "bin_cache_slots": 256, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 4},
     "guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
+              "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 4},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 0, "chunk": 256, "superchunk": 2048},
+               "bin_cache_slots": 0, "chunk": 256, "superchunk": 2048, "waves_per_simd": 5},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 0, "chunk": 64, "superchunk": 2048},
+                "bin_cache_slots": 0, "chunk": 64, "superchunk": 2048, "waves_per_simd": 4},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048},
+                    "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 5},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 256, "chunk": 256, "superchunk": 2048},
+              "bin_cache_slots": 256, "chunk": 256, "superchunk": 2048, "waves_per_simd": 5},
 }

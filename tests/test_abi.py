@@ -146,8 +146,11 @@ def test_tuning_validation(ctx):
     assert code_of(lambda: ctx.set_tuning(block=512)) == -1
     assert code_of(lambda: ctx.set_tuning(bin_cache_slots=1000)) == -1
     assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
-    ctx.set_tuning(refill_threshold=8)
-    assert ctx.get_tuning()["refill_threshold"] == 8
+    assert code_of(lambda: ctx.set_tuning(waves_per_simd=3)) == -1
+    ctx.set_tuning(refill_threshold=8, waves_per_simd=5)
+    assert ctx.get_tuning()["refill_threshold"] == 8 and ctx.get_tuning()["waves_per_simd"] == 5
+    ctx.set_tuning(waves_per_simd=0)
+    assert ctx.get_tuning()["waves_per_simd"] == 4
 
 
 def test_prepared_batch_validation(ctx):
