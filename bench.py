@@ -156,7 +156,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     n = args.histories
-    prob = W.config1(n=n)
+    prob = W.biased_sample(n=n)
     ctx = B.Context(device=0, seed=W.RUN_SEED)
     sim = B.Simulation(ctx, prob)
 
@@ -200,7 +200,7 @@ def main():
     if not args.no_batch:
         # the batched workload: 256 uneven powder simulations + the 1000-box imaging setup,
         # prepared once and stepped by replaying a HIP graph of one prepared run
-        batch = W.config4()
+        batch = W.sample_batch()
         br = B.BatchRun(ctx, batch, base=1 << 40)
         if args.autotune:
             tuned = ctx.autotune(br.descriptors(), sample_fraction=0.05)

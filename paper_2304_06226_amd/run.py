@@ -37,7 +37,7 @@ def main(argv=None):
     if args.workload in TUNED:
         ctx.set_tuning(**TUNED[args.workload])
     if args.workload == "batch":
-        batch = W.config4()
+        batch = W.sample_batch()
         br = B.BatchRun(ctx, batch)
         n = batch.total_histories
         if args.autotune:
@@ -46,7 +46,7 @@ def main(argv=None):
         def go(k):
             br.run(shift=k * br.span)
     else:
-        prob = {"sample": W.config1, "vessel": W.config2, "guide": W.config3, "imaging": W.imaging_problem,
+        prob = {"sample": W.biased_sample, "vessel": W.vessel_sample, "guide": W.m3_guide, "imaging": W.imaging_problem,
                 "paper_guide": W.paper_guide, "paper_chopper": W.paper_chopper}[args.workload]()
         n = int(args.histories) if args.histories else prob.n_histories
         sim = B.Simulation(ctx, prob)

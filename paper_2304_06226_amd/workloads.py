@@ -12,11 +12,11 @@ Units everywhere: lengths in mm, wavelengths in Angstrom, cross sections in
 barn, number densities in atoms per Angstrom^3, angles in degrees, kT in eV.
 
 Workloads (synthetic stand-ins for the paper's benchmark setups, section 4):
-  config0  plain FP64 powder sample, pencil beam, 1e5 histories
-  config1  same sample, scattering bias 4, 1e7 histories, 2theta x lambda
-  config2  sample inside a cylindrical vessel shell, Maxwellian white beam
-  config3  straight 10 m mirror guide (m=3, piecewise-linear reflectivity)
-  config4  batch of small simulations plus an imaging setup of boxes
+  analog_sample  plain FP64 powder sample, pencil beam, 1e5 histories
+  biased_sample  same sample, scattering bias 4, 1e7 histories, 2theta x lambda
+  vessel_sample  sample inside a cylindrical vessel shell, Maxwellian white beam
+  m3_guide  straight 10 m mirror guide (m=3, piecewise-linear reflectivity)
+  sample_batch  batch of small simulations plus an imaging setup of boxes
 """
 from __future__ import annotations
 
@@ -222,7 +222,7 @@ def _angle_tally_2theta(nbins=1800) -> Tally:
     return Tally(trigger="escape", filter="scattered", axes=[Axis("theta2", 0.0, 180.0, nbins)])
 
 
-def config0(n: int = 100_000) -> Problem:
+def analog_sample(n: int = 100_000) -> Problem:
     """Plain FP64, no biasing: pencil beam lambda=1.8 A onto a solid cylinder (r=5, h=20 mm, axis y)."""
     mats = [sample_material()]
     vols = [Volume("sphere", (0.0, 0.0, 0.0), (1000.0,)),
@@ -231,22 +231,22 @@ def config0(n: int = 100_000) -> Problem:
     tallies = [_angle_tally_2theta(),
                Tally(trigger="escape", filter="unscattered"),   # transmitted
                Tally(trigger="absorb", filter="all")]           # absorbed
-    return Problem(mats, vols, src, tallies, n_histories=n, name="config0")
+    return Problem(mats, vols, src, tallies, n_histories=n, name="analog_sample")
 
 
-def config1(n: int = 10_000_000, scatter_bias: float = 4.0) -> Problem:
+def biased_sample(n: int = 10_000_000, scatter_bias: float = 4.0) -> Problem:
     """Same sample with scattering biased by 4; 2theta(1800) x lambda(100 on [0.5,5] A)."""
-    p = config0(n)
+    p = analog_sample(n)
     p.materials = [p.materials[0].biased(scatter_bias=scatter_bias)]
     p.tallies = [Tally(trigger="escape", filter="scattered",
                        axes=[Axis("theta2", 0.0, 180.0, 1800), Axis("lambda", 0.5, 5.0, 100)]),
                  Tally(trigger="escape", filter="unscattered"),
                  Tally(trigger="absorb", filter="all")]
-    p.name = "config1"
+    p.name = "biased_sample"
     return p
 
 
-def config2(n: int = 100_000_000) -> Problem:
+def vessel_sample(n: int = 100_000_000) -> Problem:
     """Powder diffractometer: sample (bias 2) inside an Al-like vessel shell, 300 K Maxwellian
     clipped to 0.5-5 A over a 10x10 mm square; 2theta(3600) x lambda(1000)."""
     mats = [sample_material().biased(scatter_bias=2.0), vessel_material()]
@@ -259,7 +259,7 @@ def config2(n: int = 100_000_000) -> Problem:
                      axes=[Axis("theta2", 0.0, 180.0, 3600), Axis("lambda", 0.5, 5.0, 1000)]),
                Tally(trigger="escape", filter="unscattered"),
                Tally(trigger="absorb", filter="all")]
-    return Problem(mats, vols, src, tallies, n_histories=n, name="config2")
+    return Problem(mats, vols, src, tallies, n_histories=n, name="vessel_sample")
 
 
 def guide_mirror() -> Mirror:
@@ -267,7 +267,7 @@ def guide_mirror() -> Mirror:
     return Mirror(model="linear", R0=0.99, Qc=0.0219, alpha=10.0, m=3.0, W=0.003)
 
 
-def config3(n: int = 100_000_000, nbins_xy: int = 200, nbins_div: int = 100) -> Problem:
+def m3_guide(n: int = 100_000_000, nbins_xy: int = 200, nbins_div: int = 100) -> Problem:
     """Straight rectangular guide 50x50 mm, 10 m long, mirrors on the four side walls."""
     vols = [Volume("box", (0.0, 0.0, 5000.0), (50.0, 50.0, 10000.0), mirror_mask=0b001111,
                    mirror=guide_mirror())]
@@ -276,7 +276,7 @@ def config3(n: int = 100_000_000, nbins_xy: int = 200, nbins_div: int = 100) -> 
     tallies = [Tally(trigger="escape", filter="all",
                      axes=[Axis("x", -25.0, 25.0, nbins_xy), Axis("y", -25.0, 25.0, nbins_xy),
                            Axis("div_x", -1.0, 1.0, nbins_div), Axis("div_y", -1.0, 1.0, nbins_div)])]
-    return Problem([], vols, src, tallies, n_histories=n, name="config3")
+    return Problem([], vols, src, tallies, n_histories=n, name="m3_guide")
 
 
 def paper_guide(n: int = 100_000_000, det_side: float = 100.0, det_bins: int = 100) -> Problem:
@@ -340,9 +340,6 @@ def with_histories(p: Problem, n: int) -> Problem:
     q = dataclasses.replace(p)
     q.n_histories = int(n)
     return q
-
-
-CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3}
 
 
 # --------------------------------------------------------------------------
@@ -427,11 +424,10 @@ def imaging_problem(n: int = 10_000_000, n_boxes: int = 1000, rng: Optional[np.r
     return Problem(mats, vols, src, tallies, n_histories=n, name="imaging")
 
 
-def config4(scale: float = 1.0, imaging_histories: int = 10_000_000, n_sims: int = 256) -> Batch:
+def sample_batch(scale: float = 1.0, imaging_histories: int = 10_000_000, n_sims: int = 256) -> Batch:
     """Batched: 256 uneven powder simulations plus the 1000-box imaging setup."""
     sims = batch_sample_sims(n_sims, scale)
     sims.append(imaging_problem(int(imaging_histories)))
-    return Batch(sims, name="config4")
+    return Batch(sims, name="sample_batch")
 
 
-CONFIGS[4] = config4

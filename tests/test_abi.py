@@ -91,7 +91,7 @@ def test_material_validation(ctx):
 
 
 def test_geometry_validation(ctx):
-    p = W.config2()
+    p = W.vessel_sample()
     ids = [ctx.create_material(m) for m in p.materials]
     assert ctx.create_geometry(p.volumes, ids) == 0
     # sample touching the vessel's bore
@@ -119,7 +119,7 @@ def test_geometry_validation(ctx):
 
 
 def test_source_and_tally_validation(ctx):
-    s = W.config3().source
+    s = W.m3_guide().source
     assert ctx.create_source(s) == 0
     assert code_of(lambda: ctx.create_source(dataclasses.replace(s, direction=(0.0, 1.0, 1.0)))) == -1
     assert code_of(lambda: ctx.create_source(dataclasses.replace(s, lam_lo=5.0, lam_hi=1.0))) == -1
@@ -133,7 +133,7 @@ def test_source_and_tally_validation(ctx):
 
 
 def test_run_needs_a_device(ctx):
-    p = W.config0()
+    p = W.analog_sample()
     sim = B.Simulation(ctx, p)
     with pytest.raises(B.PromptError) as e:
         ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, "fp64", None, 0)
@@ -154,7 +154,7 @@ def test_tuning_validation(ctx):
 
 
 def test_prepared_batch_validation(ctx):
-    p = W.config0()
+    p = W.analog_sample()
     sim = B.Simulation(ctx, p)
     desc = [(sim.geom, sim.src, sim.tallies, 0, 1000)]
     # a validation-only context has no device to hold a prepared batch

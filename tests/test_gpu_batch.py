@@ -55,7 +55,7 @@ def test_imaging_fp32_tally_agreement(ctx, imaging):
 
 
 def _small_batch():
-    return W.config4(scale=0.01, imaging_histories=50_000, n_sims=24)
+    return W.sample_batch(scale=0.01, imaging_histories=50_000, n_sims=24)
 
 
 def test_batch_equals_individual_runs(ctx):
@@ -108,7 +108,7 @@ def test_batch_against_oracle(ctx):
 
 def test_batch_tuning_and_validation(ctx):
     import torch
-    batch = W.config4(scale=0.003, imaging_histories=20_000, n_sims=8)
+    batch = W.sample_batch(scale=0.003, imaging_histories=20_000, n_sims=8)
     base = ctx.get_tuning()
     res = []
     try:
@@ -132,7 +132,7 @@ def test_batch_tuning_and_validation(ctx):
 
 def test_autotune_leaves_tallies_untouched(ctx):
     import torch
-    batch = W.config4(scale=0.003, imaging_histories=20_000, n_sims=8)
+    batch = W.sample_batch(scale=0.003, imaging_histories=20_000, n_sims=8)
     br = B.BatchRun(ctx, batch)
     br.run()
     torch.cuda.synchronize()

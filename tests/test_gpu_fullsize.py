@@ -43,7 +43,7 @@ def _tuned(ctx, name):
 
 def test_biased_sample_full_1e7_fp32(ctx):
     import torch
-    prob = W.config1()
+    prob = W.biased_sample()
     n = prob.n_histories
     print(f"[case] biased sample fp32 n={n}", flush=True)
     sim = B.Simulation(ctx, prob)
@@ -72,7 +72,7 @@ def test_biased_sample_full_1e7_fp32(ctx):
 
 def test_biased_sample_full_1e7_fp64_sampled_histories(ctx):
     import torch
-    prob = W.config1()
+    prob = W.biased_sample()
     n = prob.n_histories
     print(f"[case] biased sample fp64 n={n} with records", flush=True)
     sim = B.Simulation(ctx, prob)
@@ -90,7 +90,7 @@ def test_biased_sample_full_1e7_fp64_sampled_histories(ctx):
 
 def test_vessel_full_1e8_fp32(ctx):
     import torch
-    prob = W.config2()
+    prob = W.vessel_sample()
     n = prob.n_histories
     print(f"[case] vessel fp32 n={n}", flush=True)
     sim = B.Simulation(ctx, prob)
@@ -133,7 +133,7 @@ def _guide_coarse(ctx, tally, fine=(200, 200, 100, 100), coarse=(50, 50, 20, 20)
 
 def test_guide_full_1e8_fp32_full_tally(ctx):
     import torch
-    prob = W.config3()
+    prob = W.m3_guide()
     n = prob.n_histories
     print(f"[case] guide fp32 n={n}, 4e8-bin tally", flush=True)
     sim = B.Simulation(ctx, prob)
@@ -150,7 +150,7 @@ def test_guide_full_1e8_fp32_full_tally(ctx):
     gw, gw2 = _guide_coarse(ctx, sim.tallies[0])
     # the sparse 4-D tally is compared on coarse bins (x,y 50x50, divergences 20x20)
     # merged to >= 100 entries per group, where the per-group z is close to normal
-    small = W.config3(nbins_xy=50, nbins_div=20)
+    small = W.m3_guide(nbins_xy=50, nbins_div=20)
     o = O.run(small, first=0, n=10_000_000, threads=16)
     p, z = tally_stat_test(gw, gw2, n, o.sumw[0], o.sumw2[0], o.n, min_count=100)
     assert p > 1e-3, p
@@ -169,7 +169,7 @@ def test_guide_full_1e8_fp32_full_tally(ctx):
 
 def test_batch_full_closed_forms(ctx):
     import torch
-    batch = W.config4()
+    batch = W.sample_batch()
     print(f"[case] full batch: {len(batch.problems)} simulations, {batch.total_histories} histories", flush=True)
     br = B.BatchRun(ctx, batch)
     base = _tuned(ctx, "batch")

@@ -41,23 +41,23 @@ def _fp64_case(ctx, prob, first, n, threads=8):
     return gres, grec, ores, same
 
 
-def test_config0_fp64_elementwise(ctx):
-    _, grec, ores, same = _fp64_case(ctx, W.config0(), 0, 100_000)
+def test_analog_sample_fp64_elementwise(ctx):
+    _, grec, ores, same = _fp64_case(ctx, W.analog_sample(), 0, 100_000)
     assert same.mean() >= 0.999
 
 
-def test_config1_fp64_elementwise_first_1e6(ctx):
-    _fp64_case(ctx, W.config1(), 0, 1_000_000)
+def test_biased_sample_fp64_elementwise_first_1e6(ctx):
+    _fp64_case(ctx, W.biased_sample(), 0, 1_000_000)
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 257, 4097])
 def test_ragged_sizes_fp64(ctx, n):
-    _fp64_case(ctx, W.config1(), 12345, n, threads=1)
+    _fp64_case(ctx, W.biased_sample(), 12345, n, threads=1)
 
 
 def test_split_resume_fp64(ctx):
     import torch
-    prob = W.config1()
+    prob = W.biased_sample()
     sim = B.Simulation(ctx, prob)
     sim.run(first=0, n=30_000, precision="fp64")
     sim.run(first=30_000, n=70_001, precision="fp64")
@@ -69,12 +69,12 @@ def test_split_resume_fp64(ctx):
         np.testing.assert_allclose(sw, o.sumw[t], rtol=1e-9, atol=1e-9)
 
 
-def test_config2_fp64_elementwise(ctx):
-    _fp64_case(ctx, W.config2(), 0, 100_000)
+def test_vessel_sample_fp64_elementwise(ctx):
+    _fp64_case(ctx, W.vessel_sample(), 0, 100_000)
 
 
-def test_config3_fp64_elementwise(ctx):
-    _fp64_case(ctx, W.config3(nbins_xy=50, nbins_div=20), 0, 100_000)
+def test_m3_guide_fp64_elementwise(ctx):
+    _fp64_case(ctx, W.m3_guide(nbins_xy=50, nbins_div=20), 0, 100_000)
 
 
 def test_capped_and_outside(ctx):
@@ -86,14 +86,14 @@ def test_capped_and_outside(ctx):
     gres, grec, ores, same = _fp64_case(ctx, prob, 0, 64, threads=1)
     assert np.all(grec["term"] == B.END_CAPPED) and np.all(grec["n_steps"] == 10000)
     # a source outside the world is terminated at birth and scores nothing
-    prob2 = W.config0(10)
+    prob2 = W.analog_sample(10)
     prob2.source = dataclasses.replace(prob2.source, origin=(0.0, 0.0, -2000.0))
     gres, grec, ores, same = _fp64_case(ctx, prob2, 0, 10, threads=1)
     assert np.all(grec["term"] == B.END_OUTSIDE)
 
 
 def test_detector_and_tally_filters(ctx):
-    prob = W.config0(50_000)
+    prob = W.analog_sample(50_000)
     prob.volumes.append(W.Volume("box", (0.0, 0.0, 300.0), (200.0, 200.0, 2.0), parent=0, detector=True))
     prob.tallies = [W.Tally(trigger="detect", trigger_volume=2, axes=[W.Axis("x", -100, 100, 40), W.Axis("y", -100, 100, 40)]),
                     W.Tally(trigger="escape", filter="nscat_eq", filter_arg=2, axes=[W.Axis("theta2", 0, 180, 90)]),
@@ -165,8 +165,8 @@ def _fp32_case(ctx, prob, n, n_oracle=None, threads=8):
     return gres, grec, ores
 
 
-def test_config0_fp32_tally_agreement(ctx):
-    gres, grec, ores = _fp32_case(ctx, W.config0(), 100_000)
+def test_analog_sample_fp32_tally_agreement(ctx):
+    gres, grec, ores = _fp32_case(ctx, W.analog_sample(), 100_000)
     # common random numbers: most histories follow the same event sequence
     same = grec["hash"] == ores.records["hash"]
     assert same.mean() > 0.95
@@ -174,8 +174,8 @@ def test_config0_fp32_tally_agreement(ctx):
     assert np.all(grec["term"] > 0)
 
 
-def test_config1_fp32_tally_agreement(ctx):
-    gres, grec, ores = _fp32_case(ctx, W.config1(), 1_000_000)
+def test_biased_sample_fp32_tally_agreement(ctx):
+    gres, grec, ores = _fp32_case(ctx, W.biased_sample(), 1_000_000)
     same = grec["hash"] == ores.records["hash"]
     assert same.mean() > 0.95
     d = np.abs(grec["w"][same] - ores.records["w"][same]) / ores.records["w"][same]
@@ -184,7 +184,7 @@ def test_config1_fp32_tally_agreement(ctx):
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 4097])
 def test_ragged_sizes_fp32(ctx, n):
-    prob = W.config1()
+    prob = W.biased_sample()
     gres, grec, gst = gpu_run(ctx, prob, first=0, n=n, precision="fp32")
     ores = O.run(prob, first=0, n=n, threads=1, records=True)
     assert gst["histories"] == n
@@ -192,12 +192,12 @@ def test_ragged_sizes_fp32(ctx, n):
     assert np.array_equal(np.sort(grec["n_draws"] >= 1), np.sort(ores.records["n_draws"] >= 1))
 
 
-def test_config2_fp32_tally_agreement(ctx):
-    _fp32_case(ctx, W.config2(), 300_000)
+def test_vessel_sample_fp32_tally_agreement(ctx):
+    _fp32_case(ctx, W.vessel_sample(), 300_000)
 
 
-def test_config3_fp32_tally_agreement(ctx):
-    _fp32_case(ctx, W.config3(nbins_xy=50, nbins_div=20), 300_000)
+def test_m3_guide_fp32_tally_agreement(ctx):
+    _fp32_case(ctx, W.m3_guide(nbins_xy=50, nbins_div=20), 300_000)
 
 
 def test_fp32_results_independent_of_launch_tuning(ctx):
@@ -205,7 +205,7 @@ def test_fp32_results_independent_of_launch_tuning(ctx):
     lane or block runs it: tallies agree across launch tunings up to the
     order of floating-point summation."""
     import torch
-    prob = W.config1(n=300_000)
+    prob = W.biased_sample(n=300_000)
     base = ctx.get_tuning()
     results = []
     tunings = [dict(), dict(refill_threshold=1, chunk=64, block=64), dict(bin_cache_slots=0, lds_tally_bytes=0),
@@ -237,7 +237,7 @@ def _q_orders_problem(mat, n):
     """The biased sample with momentum-transfer tallies resolved by scattering
     order (DeltaMomentum with a scattering-number filter) and a scattering-number
     histogram of escapes (MultiScat)."""
-    p = W.config0(n)
+    p = W.analog_sample(n)
     p.materials = [mat]
     p.tallies = [W.Tally(trigger="escape", filter="nscat_eq", filter_arg=1, axes=[W.Axis("q", 0.0, 8.0, 400)]),
                  W.Tally(trigger="escape", filter="nscat_eq", filter_arg=2, axes=[W.Axis("q", 0.0, 8.0, 200)]),
@@ -339,7 +339,7 @@ def _tabulated_problem(n):
     """The powder sample with absorption and incoherent cross sections given as
     tables (curved in lambda) and a uniform 1-5 A beam crossing many table rows;
     coherent scattering stays the Bragg sum."""
-    p = W.config0(n)
+    p = W.analog_sample(n)
     base = W.sample_material().biased(scatter_bias=2.0)
     rows = np.linspace(0.8, 5.5, 24)
     mat = dataclasses.replace(base, table_lambda=rows, table_sigma_abs=1.5 + 0.4 * rows ** 1.5,
@@ -368,12 +368,12 @@ def test_tabulated_cross_sections_fp32(ctx):
 def test_empty_runs_change_nothing(ctx):
     import torch
     print("[case] empty runs", flush=True)
-    prob = W.config0(0)
+    prob = W.analog_sample(0)
     sim = B.Simulation(ctx, prob)
     ctx.reset_stats()
     for prec in ("fp64", "fp32"):
         sim.run(first=123, n=0, precision=prec)
-    batch = W.Batch([W.config0(0), W.config0(0)])
+    batch = W.Batch([W.analog_sample(0), W.analog_sample(0)])
     br = B.BatchRun(ctx, batch)
     br.run()
     pid = ctx.prepare_batch(br.descriptors(), stride=1)
@@ -385,8 +385,8 @@ def test_empty_runs_change_nothing(ctx):
         for sw, sw2, nh in s.results():
             assert nh == 0 and not sw.any() and not sw2.any()
     # an empty simulation inside a batch leaves the others as run alone
-    one = B.BatchRun(ctx, W.Batch([W.config0(0), W.config0(2000)]))
-    alone = B.Simulation(ctx, W.config0(2000))
+    one = B.BatchRun(ctx, W.Batch([W.analog_sample(0), W.analog_sample(2000)]))
+    alone = B.Simulation(ctx, W.analog_sample(2000))
     one.run()
     alone.run(first=one.offsets[1], n=2000, precision="fp32")
     torch.cuda.synchronize()
@@ -399,11 +399,11 @@ def test_top_of_the_history_id_range_fp64(ctx):
     """History ids up to 2^62 (the largest accepted first id) drive the counter's
     high words: element-wise parity there too."""
     first = (1 << 62) - 1000
-    _fp64_case(ctx, W.config1(1000), first, 1000, threads=4)
+    _fp64_case(ctx, W.biased_sample(1000), first, 1000, threads=4)
 
 
 def test_history_range_limits_are_enforced(ctx):
-    sim = B.Simulation(ctx, W.config0(10))
+    sim = B.Simulation(ctx, W.analog_sample(10))
     with pytest.raises(B.PromptError) as e:
         sim.run(first=(1 << 62) + 1, n=10, precision="fp64")
     assert e.value.code == -1

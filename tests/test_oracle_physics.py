@@ -91,7 +91,7 @@ def test_energy_wavelength_pairs_from_paper():
 # --------------------------------------------------------------------------
 
 def pencil_problem(mat, lam=1.8, radius=5.0):
-    p = W.config0()
+    p = W.analog_sample()
     p.materials = [mat]
     p.volumes[1] = dataclasses.replace(p.volumes[1], size=(radius, 20.0))
     p.source = dataclasses.replace(p.source, lam0=lam)
@@ -239,8 +239,8 @@ def merged_chi2(m1, v1, c1, m2, v2, c2, min_count=25):
 
 def test_biased_equals_unbiased():
     n = 400_000
-    p1 = W.config0()
-    pb = W.config1(n=n)
+    p1 = W.analog_sample()
+    pb = W.biased_sample(n=n)
     pb.tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0, 180, 1800)])] + pb.tallies[1:]
     ra = O.run(p1, n=n, threads=8, seed=4096)
     rb = O.run(pb, n=n, threads=8, seed=4097)
@@ -282,7 +282,7 @@ def R_linear(Q, R0=0.99, Qc=0.0219, alpha=10.0, m=3.0):
 
 
 def test_mirror_reflectivity_values():
-    g = W.config3().volumes[0]
+    g = W.m3_guide().volumes[0]
     assert O.mirror_reflectivity(g, 0.0) == 0.99
     assert O.mirror_reflectivity(g, 0.0219) == 0.99
     assert O.mirror_reflectivity(g, 3 * 0.0219) == pytest.approx(0.99 - 10 * 2 * 0.0219, rel=1e-12)
@@ -306,7 +306,7 @@ def _fold(s, half):
 
 
 def test_guide_method_of_images():
-    p = W.config3(n=20_000)
+    p = W.m3_guide(n=20_000)
     n = 20_000
     r = O.run(p, n=n, threads=8, records=True)
     rec = r.records
@@ -346,7 +346,7 @@ def test_guide_method_of_images():
 # --------------------------------------------------------------------------
 
 def test_maxwellian_spectrum():
-    p = W.config2(n=200_000)
+    p = W.vessel_sample(n=200_000)
     p.materials = []
     p.volumes = p.volumes[:1]
     p.tallies = []
@@ -369,7 +369,7 @@ def test_maxwellian_spectrum():
 
 
 def test_rect_sources_uniform():
-    p = W.config3(n=100_000)
+    p = W.m3_guide(n=100_000)
     p.tallies = []
     p.volumes = [dataclasses.replace(p.volumes[0], mirror_mask=0)]
     r = O.run(p, n=100_000, threads=8, records=True)
@@ -391,7 +391,7 @@ def test_rect_sources_uniform():
 # --------------------------------------------------------------------------
 
 def test_vessel_shell_transmission():
-    p = W.config2(n=200_000)
+    p = W.vessel_sample(n=200_000)
     vessel = p.materials[1]
     p.volumes = p.volumes[:2]          # world + vessel only
     p.source = W.Source("pencil", origin=(0.0, 0.0, -100.0), spectrum="mono", lam0=1.8)
@@ -405,7 +405,7 @@ def test_vessel_shell_transmission():
 
 
 def test_split_resume_and_threads_identical():
-    p = W.config2(n=20_000)
+    p = W.vessel_sample(n=20_000)
     full = O.run(p, n=20_000, threads=1, records=True)
     a = O.run(p, first=0, n=7_000, threads=3, records=True)
     b = O.run(p, first=7_000, n=13_000, threads=5, records=True)

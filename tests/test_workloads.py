@@ -53,7 +53,7 @@ def test_seeded_materials_reproducible():
 
 
 def test_configs_shapes():
-    assert W.config0().tallies[0].nbins == 1800
-    assert W.config1().tallies[0].shape == (1800, 100)
-    assert W.config2().tallies[0].shape == (3600, 1000)
-    assert W.config3().tallies[0].nbins == 200 * 200 * 100 * 100
+    assert W.analog_sample().tallies[0].nbins == 1800
+    assert W.biased_sample().tallies[0].shape == (1800, 100)
+    assert W.vessel_sample().tallies[0].shape == (3600, 1000)
+    assert W.m3_guide().tallies[0].nbins == 200 * 200 * 100 * 100
