@@ -83,6 +83,32 @@ def test_batch_equals_individual_runs(ctx):
             np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
 
 
+def test_batch_results_independent_of_waves_per_simd(ctx):
+    """The four- and five-wave builds of the batched kernels give the same
+    tallies (up to summation order) and the same counts."""
+    import torch
+    batch = _small_batch()
+    base = ctx.get_tuning()
+    out = []
+    try:
+        for w in (4, 5):
+            ctx.set_tuning(waves_per_simd=w)
+            br = B.BatchRun(ctx, batch)
+            ctx.reset_stats()
+            br.run()
+            torch.cuda.synchronize()
+            out.append(([s.results() for s in br.sims], ctx.read_stats()))
+    finally:
+        ctx.set_tuning(**base)
+    (a, sa), (b, sb) = out
+    assert sa == sb
+    for ra, rb in zip(a, b):
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(ra, rb):
+            assert nh == rn
+            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+
+
 def test_batch_against_oracle(ctx):
     import torch
     batch = _small_batch()

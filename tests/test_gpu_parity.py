@@ -208,8 +208,9 @@ def test_fp32_results_independent_of_launch_tuning(ctx):
     prob = W.biased_sample(n=300_000)
     base = ctx.get_tuning()
     results = []
-    tunings = [dict(), dict(refill_threshold=1, chunk=64, block=64), dict(bin_cache_slots=0, lds_tally_bytes=0),
-               dict(refill_threshold=64, chunk=4096, blocks_per_cu=1, bin_cache_slots=4096)]
+    tunings = [dict(waves_per_simd=4), dict(refill_threshold=1, chunk=64, block=64), dict(bin_cache_slots=0, lds_tally_bytes=0),
+               dict(refill_threshold=64, chunk=4096, blocks_per_cu=1, bin_cache_slots=4096),
+               dict(waves_per_simd=5), dict(waves_per_simd=5, refill_threshold=8, chunk=128, bin_cache_slots=0)]
     try:
         for t in tunings:
             ctx.set_tuning(**{**base, **t})
