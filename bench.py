@@ -44,7 +44,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 # HBM bytes per launch of the dominant kernels from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE passes (scaled by a 256 MiB copy: fetch x2.000, write x1.000), valid
-# only for the kernel sources they were taken on (hash of transport.hip + device.h);
+# only for the kernel build they were taken on (hash of transport.hip, device.h and
+# the compiler flags);
 # profiles/k_mixed_biased_sample_1e7.txt holds the summary.  Nearly all of it is
 # the 32-byte memory-side writes of FP64 tally atomics.
 MEASURED_TRAFFIC = {"source_hash": "c75605e2ef6d684b",
@@ -52,11 +53,14 @@ MEASURED_TRAFFIC = {"source_hash": "c75605e2ef6d684b",
 
 
 def kernel_source_hash() -> str:
+    """Hash of the kernel sources and the compiler flags they are built with."""
     import hashlib
+    from paper_2304_06226_amd.build import HIPCC_FLAGS
     h = hashlib.sha256()
     for f in ("paper_2304_06226_amd/csrc/transport.hip", "paper_2304_06226_amd/csrc/device.h"):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 

@@ -19,6 +19,7 @@ HEADERS = [os.path.join(HERE, "csrc", "device.h"), os.path.join(HERE, "csrc", "l
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",                                  # hardware FP64 atomics
+    "-fgpu-flush-denormals-to-zero",                        # FP32 denormals flushed (weights and tallies are FP64)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]
