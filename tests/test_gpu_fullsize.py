@@ -56,7 +56,7 @@ def test_biased_sample_full_1e7_fp32(ctx):
         st = ctx.read_stats()
     finally:
         ctx.set_tuning(**base)
-    assert st["histories"] == n
+    assert st["histories"] == n and st["capped"] == 0
     # Beer-Lambert through the 10 mm diameter
     T = np.exp(-total_sigma(prob.materials[0], 1.8) * 10.0)
     sw, sw2, nh = res[1]
@@ -103,7 +103,7 @@ def test_vessel_full_1e8_fp32(ctx):
         st = ctx.read_stats()
     finally:
         ctx.set_tuning(**base)
-    assert st["histories"] == n
+    assert st["histories"] == n and st["capped"] == 0
     o = O.run(prob, first=0, n=3_000_000, threads=16)
     for t, (gw, gw2, gn) in enumerate(res):
         if t == 0:
@@ -146,7 +146,7 @@ def test_guide_full_1e8_fp32_full_tally(ctx):
         st = ctx.read_stats()
     finally:
         ctx.set_tuning(**base)
-    assert st["histories"] == n
+    assert st["histories"] == n and st["capped"] == 0
     gw, gw2 = _guide_coarse(ctx, sim.tallies[0])
     # the sparse 4-D tally is compared on coarse bins (x,y 50x50, divergences 20x20)
     # merged to >= 100 entries per group, where the per-group z is close to normal
@@ -180,7 +180,7 @@ def test_batch_full_closed_forms(ctx):
         st = ctx.read_stats()
     finally:
         ctx.set_tuning(**base)
-    assert st["histories"] == batch.total_histories
+    assert st["histories"] == batch.total_histories and st["capped"] == 0
     # transmitted counter of every powder simulation: exp(-Sigma_S 2r - Sigma_V 2 mm)
     zs = []
     for s, prob in zip(br.sims[:-1], batch.problems[:-1]):
@@ -268,7 +268,7 @@ def test_paper_guide_full_1e8_fp32(ctx):
         st = ctx.read_stats()
     finally:
         ctx.set_tuning(**base)
-    assert st["histories"] == n
+    assert st["histories"] == n and st["capped"] == 0
     assert st["detected"] + st["escaped"] + st["absorbed"] + st["killed"] == n
     o = O.run(prob, first=0, n=10_000_000, threads=16)
 
