@@ -316,9 +316,8 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * lds_tally_bytes: LDS per block for privatised tallies (tallies are
  * privatised in order while they fit); bin_cache_slots: LDS bin-cache slots
  * given to each tally that is not privatised (0 or a power of two <= 4096);
- * chunk: history indices a wave claims from the shared counter per atomic;
- * superchunk: reserved (validated as 1..2^30 and stored; batched runs hand
- * out work per simulation, see pr_run_batch).
+ * chunk: history indices a wave claims from the shared counter (batched
+ * runs: from the simulation's own counter) per atomic;
  * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
  * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
  * spilling some state to scratch; which is faster depends on the workload);
@@ -335,7 +334,6 @@ typedef struct {
     int32_t lds_tally_bytes;
     int32_t bin_cache_slots;
     int32_t chunk;
-    int32_t superchunk;
     int32_t waves_per_simd;
 } pr_tuning;
 

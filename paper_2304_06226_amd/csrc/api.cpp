@@ -126,7 +126,6 @@ struct pr_ctx {
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     DescSlot slots[4];
-    int superchunk = 2048;              // reserved tuning field: validated and stored, not used
     int waves_per_simd = 4;             // FP32 kernels without a grid: variant built for 4 or 5 waves per SIMD
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
     uint64_t scratch_bins = 0;
@@ -1208,12 +1207,10 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
     if (t->bin_cache_slots < 0 || t->bin_cache_slots > 4096 || (t->bin_cache_slots & (t->bin_cache_slots - 1)))
         return fail(c, PR_EINVAL, "tuning.bin_cache_slots must be 0 or a power of two up to 4096");
     if (t->chunk < 1 || t->chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.chunk must be 1..2^20");
-    if (t->superchunk < 1 || t->superchunk > (1 << 30)) return fail(c, PR_EINVAL, "tuning.superchunk must be 1..2^30");
     if (t->waves_per_simd != 0 && t->waves_per_simd != 4 && t->waves_per_simd != 5)
         return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
     c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
-    c->superchunk = t->superchunk;
     c->mixed_block = t->block;
     c->mixed_blocks_per_cu = t->blocks_per_cu;
     c->refill_threshold = t->refill_threshold;
@@ -1230,7 +1227,6 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->lds_tally_bytes = c->lds_tally_budget;
     t->bin_cache_slots = c->bin_cache_slots;
     t->chunk = c->chunk;
-    t->superchunk = c->superchunk;
     t->waves_per_simd = c->waves_per_simd;
     return PR_OK;
 }

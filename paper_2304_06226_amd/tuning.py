@@ -12,15 +12,15 @@ paper's guide and the batch's powder simulations, slower for the others."""
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 4},
+               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4},
     "guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 4},
+              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 0, "chunk": 256, "superchunk": 2048, "waves_per_simd": 5},
+               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 0, "chunk": 64, "superchunk": 2048, "waves_per_simd": 4},
+                "bin_cache_slots": 0, "chunk": 64, "waves_per_simd": 4},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 0, "chunk": 1024, "superchunk": 2048, "waves_per_simd": 5},
+                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 256, "chunk": 256, "superchunk": 2048, "waves_per_simd": 5},
+              "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 5},
 }

@@ -168,7 +168,7 @@ def test_autotune_leaves_tallies_untouched(ctx):
     try:
         best = ctx.autotune(br.descriptors(), sample_fraction=0.5)
         assert best == ctx.get_tuning()
-        assert best["refill_threshold"] >= 1 and best["chunk"] >= 1 and best["superchunk"] >= 1
+        assert best["refill_threshold"] >= 1 and best["chunk"] >= 1 and best["waves_per_simd"] in (4, 5)
         single = br.sims[0]
         best1 = ctx.autotune([(single.geom, single.src, single.tallies, 0, 20_000)], sample_fraction=1.0)
         assert best1["chunk"] >= 1
