@@ -200,6 +200,29 @@ def test_m3_guide_fp32_tally_agreement(ctx):
     _fp32_case(ctx, W.m3_guide(nbins_xy=50, nbins_div=20), 300_000)
 
 
+@pytest.mark.parametrize("name", ["biased_sample", "paper_chopper"])
+def test_fp32_error_against_fp64_per_tally(ctx, name):
+    """Both policies on the same history ids: every tally's total weight agrees to
+    2e-5 relative and less than 2e-3 of the weight lands in another bin (FP32
+    rounding only; the random numbers are shared)."""
+    import torch
+    prob = W.biased_sample(n=1_000_000) if name == "biased_sample" else W.paper_chopper(n=500_000)
+    n = prob.n_histories
+    print(f"[case] {name} fp32 vs fp64 n={n}", flush=True)
+    out = {}
+    for prec in ("fp32", "fp64"):
+        sim = B.Simulation(ctx, prob)
+        sim.run(first=0, n=n, precision=prec)
+        torch.cuda.synchronize()
+        out[prec] = sim.results()
+    for (w32, _, n32), (w64, _, n64) in zip(out["fp32"], out["fp64"]):
+        assert n32 == n64 == n
+        tot = np.abs(w64).sum()
+        assert tot > 0
+        assert abs(w32.sum() - w64.sum()) < 2e-5 * tot
+        assert np.abs(w32 - w64).sum() < 2e-3 * tot
+
+
 def test_fp32_results_independent_of_launch_tuning(ctx):
     """Each history's outcome depends only on (seed, history id), not on which
     lane or block runs it: tallies agree across launch tunings up to the
