@@ -171,7 +171,7 @@ def main():
                       "histories_per_step": n, "seed": W.RUN_SEED}}
     fp32 = fp64 = None
     if args.autotune:
-        out["tuning"] = ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=0.2)
+        out["tuning"] = ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=1.0)
     else:
         ctx.set_tuning(**TUNED["sample"])
         out["tuning"] = ctx.get_tuning()
@@ -207,7 +207,7 @@ def main():
         batch = W.sample_batch()
         br = B.BatchRun(ctx, batch, base=1 << 40)
         if args.autotune:
-            tuned = ctx.autotune(br.descriptors(), sample_fraction=0.05)
+            tuned = ctx.autotune(br.descriptors(shift=8 * br.span), sample_fraction=1.0)
         else:
             ctx.set_tuning(**TUNED["batch"])
             tuned = ctx.get_tuning()

@@ -341,8 +341,8 @@ int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
 int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
 
 /* Pick the launch tuning for a workload by measurement: coordinate descent
- * (two passes) over refill threshold, chunk, resident blocks per CU and
- * bin-cache slots, each candidate timed with HIP events on
+ * (two passes) over refill threshold, chunk, resident blocks per CU,
+ * bin-cache slots, waves per SIMD and block size, each candidate timed with HIP events on
  * `stream` over a sample of the workload (every simulation's history count
  * times sample_fraction, at least 1).  nsims = 1 tunes pr_run_histories'
  * PR_FP32_MIXED policy, nsims > 1 tunes pr_run_batch.  Trial runs score into

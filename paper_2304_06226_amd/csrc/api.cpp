@@ -1633,6 +1633,7 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->mixed_blocks_per_cu, {0, 2, 3}},
         {&c->bin_cache_slots, {0, 256, 1024, 2048}},
         {&c->waves_per_simd, {4, 5}},
+        {&c->mixed_block, {64, 128, 256}},
     };
 
     float cur = 0.f;

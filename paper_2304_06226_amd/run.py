@@ -41,7 +41,7 @@ def main(argv=None):
         br = B.BatchRun(ctx, batch)
         n = batch.total_histories
         if args.autotune:
-            ctx.autotune(br.descriptors(), sample_fraction=0.05)
+            ctx.autotune(br.descriptors(), sample_fraction=1.0)
 
         def go(k):
             br.run(shift=k * br.span)
@@ -51,7 +51,7 @@ def main(argv=None):
         n = int(args.histories) if args.histories else prob.n_histories
         sim = B.Simulation(ctx, prob)
         if args.autotune and args.precision == "fp32":
-            ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=0.2)
+            ctx.autotune([(sim.geom, sim.src, sim.tallies, 1 << 44, n)], sample_fraction=1.0)
 
         def go(k):
             sim.run(first=k * n, n=n, precision=args.precision)
