@@ -65,7 +65,10 @@ enum {
     PR_FP64_PLAIN = 0,   /* one thread per history, everything in FP64, global tables and atomics */
     PR_FP32_MIXED = 1    /* persistent lanes refilled from a wave-shared history counter; FP32
                             positions, directions, cross sections and sampling; FP64 weight
-                            product and tallies; LDS-staged tables, LDS-privatised small tallies */
+                            product and tallies; LDS-staged tables, LDS-privatised small tallies.
+                            A daughter's piece shorter than 2^-20 (|x|+|y|+|z|) along the ray is
+                            passed by rather than entered (an FP32 position would not move
+                            across it) */
 };
 /* termination codes written to history records */
 enum { PR_END_ESCAPE = 1, PR_END_ABSORB = 2, PR_END_KILL = 3, PR_END_DETECT = 4, PR_END_CAPPED = 5,
@@ -176,7 +179,7 @@ typedef struct {
  * PR_MAXWELL energy density ~ sqrt(E) exp(-E/kT), rejected to [lam_lo, lam_hi]
  * (at most 64 tries of three draws).  Draw order: position, divergence, lambda. */
 typedef struct {
-    int32_t kind;             /* PR_PENCIL, PR_RECT, PR_RECT_DIVERGENT */
+    int32_t kind;             /* PR_PENCIL, PR_RECT, PR_RECT_DIVERGENT, PR_MODERATOR */
     int32_t spectrum;         /* PR_MONO, PR_UNIFORM, PR_MAXWELL */
     double origin[3];         /* mm */
     double dir[3];            /* non-zero; PR_RECT_DIVERGENT requires +z */
@@ -342,9 +345,10 @@ int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
 
 /* Pick the launch tuning for a workload by measurement: coordinate descent
  * (two passes) over refill threshold, chunk, resident blocks per CU,
- * bin-cache slots, waves per SIMD and block size, each candidate timed with HIP events on
- * `stream` over a sample of the workload (every simulation's history count
- * times sample_fraction, at least 1).  nsims = 1 tunes pr_run_histories'
+ * bin-cache slots, waves per SIMD and block size, each candidate timed with
+ * HIP events on `stream` over a sample of the workload (every simulation's
+ * history count times sample_fraction, at least 1; the best claim size depends
+ * on the launch's size, so 1 tunes for the full workload).  nsims = 1 tunes pr_run_histories'
  * PR_FP32_MIXED policy, nsims > 1 tunes pr_run_batch.  Trial runs score into
  * a context-owned scratch buffer and scratch statistics: the caller's tallies
  * and run statistics are untouched.  The best tuning is set on the context and
