@@ -235,6 +235,51 @@ def test_mixed_kind_grid_fp32_tally_agreement(ctx):
         assert p > 1e-3, (t, p)
 
 
+def _nested_grid_problem(n):
+    """Grids inside grids: a 3x3 lattice of 120 mm boxes in the world (one grid),
+    the middle one vacuum and holding its own 3x3 lattice of 25 mm sample boxes
+    (a second grid).  A tilted beam starts inside the middle box, so histories are
+    born in it or in one of its daughters (located through both grids)."""
+    mats = [W.sample_material(), W.vessel_material()]
+    vols = [W.Volume("box", (0.0, 0.0, 0.0), (600.0, 600.0, 600.0))]
+    for x in (-150.0, 0.0, 150.0):
+        for y in (-150.0, 0.0, 150.0):
+            mid = x == 0.0 and y == 0.0
+            vols.append(W.Volume("box", (x, y, 0.0), (120.0, 120.0, 120.0), parent=0, material=-1 if mid else 1))
+    middle = 1 + 4
+    for x in (-35.0, 0.0, 35.0):
+        for y in (-35.0, 0.0, 35.0):
+            vols.append(W.Volume("box", (x, y, 5.0), (25.0, 25.0, 25.0), parent=middle, material=0))
+    u = np.array([0.3, 0.2, 1.0])
+    u = tuple(u / np.linalg.norm(u))
+    src = W.Source("rect", origin=(0.0, 0.0, 0.0), direction=u, size=(100.0, 100.0), spectrum="mono", lam0=1.8)
+    tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0.0, 180.0, 180)]),
+               W.Tally(trigger="escape", filter="unscattered"),
+               W.Tally(trigger="absorb")]
+    return W.Problem(mats, vols, src, tallies, n_histories=n, name="nested-grid")
+
+
+def test_nested_grid_fp64_elementwise(ctx):
+    print("[case] nested grids fp64 n=20000", flush=True)
+    prob = _nested_grid_problem(20_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+    ores = O.run(prob, first=0, n=20_000, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+    assert gst["scatters"] > 1000
+
+
+def test_nested_grid_fp32_tally_agreement(ctx):
+    print("[case] nested grids fp32 n=400000", flush=True)
+    prob = _nested_grid_problem(400_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
+    assert gst["capped"] == 0
+    ores = O.run(prob, first=0, n=400_000, threads=8)
+    for t, (sw, sw2, nh) in enumerate(gres):
+        p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
+        assert p > 1e-3, (t, p)
+
+
 def _close(a, b, rtol=1e-12):
     return np.allclose(a, b, rtol=rtol, atol=1e-300)
 
