@@ -280,6 +280,72 @@ def test_nested_grid_fp32_tally_agreement(ctx):
         assert p > 1e-3, (t, p)
 
 
+def _deep_scene_problem(n):
+    """Three levels of seven boxes in a row (1 + 7 + 49 + 343 volumes, no volume
+    with a grid): the FP32 scene is far larger than the 16 KB staged in LDS, so
+    the kernels read it from global memory.  A beam along x crosses the rows."""
+    mats = [W.sample_material(), W.vessel_material()]
+    vols = [W.Volume("box", (0.0, 0.0, 0.0), (1000.0, 200.0, 200.0))]
+
+    def row(parent, centre, side, level):
+        step = side / 7.0
+        kids = []
+        for i in range(7):
+            c = (centre[0] - side / 2 + step * (i + 0.5), centre[1], centre[2])
+            vols.append(W.Volume("box", c, (0.8 * step, 0.8 * side if level else 150.0, 0.8 * side if level else 150.0),
+                                 parent=parent, material=(i + level) % 2 if level < 3 else 0))
+            kids.append((len(vols) - 1, c, 0.8 * step))
+        return kids
+
+    for v1, c1, s1 in row(0, (0.0, 0.0, 0.0), 900.0, 0):
+        for v2, c2, s2 in row(v1, c1, s1, 1):
+            row(v2, c2, s2, 2)
+    src = W.Source("rect", origin=(-480.0, 0.0, 0.0), direction=(1.0, 0.0, 0.0), size=(20.0, 20.0),
+                   spectrum="mono", lam0=1.8)
+    tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0.0, 180.0, 180)]),
+               W.Tally(trigger="escape", filter="unscattered"),
+               W.Tally(trigger="absorb")]
+    return W.Problem(mats, vols, src, tallies, n_histories=n, name="deep-scene")
+
+
+def test_deep_scene_fp64_elementwise(ctx):
+    print("[case] deep scene (400 volumes, scene in global memory) fp64 n=20000", flush=True)
+    prob = _deep_scene_problem(20_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+    ores = O.run(prob, first=0, n=20_000, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+
+
+def test_deep_scene_fp32_and_batched(ctx):
+    """The FP32 kernels with the scene in global memory: tally agreement with the
+    oracle, and a batch mixing the deep scene with an LDS-staged simulation
+    equals the two run one by one."""
+    import torch
+    print("[case] deep scene fp32 n=200000 + batch", flush=True)
+    prob = _deep_scene_problem(200_000)
+    gres, _, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
+    assert gst["capped"] == 0
+    ores = O.run(prob, first=0, n=200_000, threads=8)
+    for t, (sw, sw2, nh) in enumerate(gres):
+        p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
+        assert p > 1e-3, (t, p)
+    batch = W.Batch([_deep_scene_problem(50_000), W.analog_sample(30_000)])
+    br = B.BatchRun(ctx, batch)
+    br.run()
+    torch.cuda.synchronize()
+    got = [s.results() for s in br.sims]
+    single = B.BatchRun(ctx, batch)
+    for s, (g, sr, ts, first, n) in zip(single.sims, single.descriptors()):
+        s.run(first=first, n=n, precision="fp32")
+    torch.cuda.synchronize()
+    for a, b in zip(got, [s.results() for s in single.sims]):
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+            assert nh == rn
+            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+
+
 def _close(a, b, rtol=1e-12):
     return np.allclose(a, b, rtol=rtol, atol=1e-300)
 
