@@ -346,6 +346,71 @@ def test_deep_scene_fp32_and_batched(ctx):
             np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
 
 
+def _big_grid_problem(n):
+    """3072 boxes (sides 5-20 mm) on a jittered 16x16x12 lattice of 30 mm pitch:
+    the world navigates them through a grid whose cells, cell lists and box table
+    (about 180 KB) exceed what is staged in LDS, so they are read from global
+    memory.  A 1.9 A beam along z over 480x480 mm."""
+    rng = np.random.default_rng(11)
+    mats = [W.sample_material(), W.vessel_material()]
+    vols = [W.Volume("box", (0.0, 0.0, 0.0), (700.0, 700.0, 600.0))]
+    k = 0
+    for i in range(16):
+        for j in range(16):
+            for l in range(12):
+                c = (-225.0 + 30.0 * i + rng.uniform(-3, 3), -225.0 + 30.0 * j + rng.uniform(-3, 3),
+                     -165.0 + 30.0 * l + rng.uniform(-3, 3))
+                side = tuple(rng.uniform(5.0, 20.0, 3))
+                vols.append(W.Volume("box", c, side, parent=0, material=k % 2))
+                k += 1
+    # 1.9 A: no Bragg angle of the sample falls on an edge of the 2-degree bins (at
+    # 2.0 A the (200) reflection scatters at exactly 60 degrees)
+    src = W.Source("rect", origin=(0.0, 0.0, -250.0), direction=(0.0, 0.0, 1.0), size=(480.0, 480.0),
+                   spectrum="mono", lam0=1.9)
+    tallies = [W.Tally(trigger="escape", filter="scattered", axes=[W.Axis("theta2", 0.0, 180.0, 90)]),
+               W.Tally(trigger="escape", filter="unscattered", axes=[W.Axis("x", -240.0, 240.0, 16)]),
+               W.Tally(trigger="absorb")]
+    return W.Problem(mats, vols, src, tallies, n_histories=n, name="big-grid")
+
+
+def test_big_grid_fp64_elementwise(ctx):
+    print("[case] big grid (3072 boxes, grid in global memory) fp64 n=20000", flush=True)
+    prob = _big_grid_problem(20_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+    ores = O.run(prob, first=0, n=20_000, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+
+
+def test_big_grid_fp32_and_batched(ctx):
+    """The FP32 grid kernels with the grid in global memory: tally agreement with
+    the oracle, and batched beside an LDS-staged simulation, equal to the two run
+    one by one."""
+    import torch
+    print("[case] big grid fp32 n=300000 + batch", flush=True)
+    prob = _big_grid_problem(300_000)
+    gres, _, gst = gpu_run(ctx, prob, first=0, n=300_000, precision="fp32", records=False)
+    assert gst["capped"] == 0
+    ores = O.run(prob, first=0, n=300_000, threads=8)
+    for t, (sw, sw2, nh) in enumerate(gres):
+        p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
+        assert p > 1e-3, (t, p)
+    batch = W.Batch([_big_grid_problem(100_000), W.analog_sample(30_000)])
+    br = B.BatchRun(ctx, batch)
+    br.run()
+    torch.cuda.synchronize()
+    got = [s.results() for s in br.sims]
+    single = B.BatchRun(ctx, batch)
+    for s, (g, sr, ts, first, n) in zip(single.sims, single.descriptors()):
+        s.run(first=first, n=n, precision="fp32")
+    torch.cuda.synchronize()
+    for a, b in zip(got, [s.results() for s in single.sims]):
+        for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+            assert nh == rn
+            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+
+
 def _close(a, b, rtol=1e-12):
     return np.allclose(a, b, rtol=rtol, atol=1e-300)
 
