@@ -320,7 +320,7 @@ def test_deep_scene_fp64_elementwise(ctx):
 def test_deep_scene_fp32_and_batched(ctx):
     """The FP32 kernels with the scene in global memory: tally agreement with the
     oracle, and a batch mixing the deep scene with an LDS-staged simulation
-    equals the two run one by one."""
+    equals the two run one by one, with the four- and the five-wave builds."""
     import torch
     print("[case] deep scene fp32 n=200000 + batch", flush=True)
     prob = _deep_scene_problem(200_000)
@@ -331,19 +331,25 @@ def test_deep_scene_fp32_and_batched(ctx):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
     batch = W.Batch([_deep_scene_problem(50_000), W.analog_sample(30_000)])
-    br = B.BatchRun(ctx, batch)
-    br.run()
-    torch.cuda.synchronize()
-    got = [s.results() for s in br.sims]
-    single = B.BatchRun(ctx, batch)
-    for s, (g, sr, ts, first, n) in zip(single.sims, single.descriptors()):
-        s.run(first=first, n=n, precision="fp32")
-    torch.cuda.synchronize()
-    for a, b in zip(got, [s.results() for s in single.sims]):
-        for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
-            assert nh == rn
-            np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
-            np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+    base = ctx.get_tuning()
+    try:
+        for waves in (4, 5):
+            ctx.set_tuning(waves_per_simd=waves)
+            br = B.BatchRun(ctx, batch)
+            br.run()
+            torch.cuda.synchronize()
+            got = [s.results() for s in br.sims]
+            single = B.BatchRun(ctx, batch)
+            for s, (g, sr, ts, first, n) in zip(single.sims, single.descriptors()):
+                s.run(first=first, n=n, precision="fp32")
+            torch.cuda.synchronize()
+            for a, b in zip(got, [s.results() for s in single.sims]):
+                for (sw, sw2, nh), (rw, rw2, rn) in zip(a, b):
+                    assert nh == rn
+                    np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+                    np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
+    finally:
+        ctx.set_tuning(**base)
 
 
 def _big_grid_problem(n):
