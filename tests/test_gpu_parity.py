@@ -92,6 +92,27 @@ def test_capped_and_outside(ctx):
     assert np.all(grec["term"] == B.END_OUTSIDE)
 
 
+def test_run_seed_fp64_elementwise(ctx):
+    """pr_set_seed: with another run seed (one above 2^32, so both key words
+    matter) the histories are those of the oracle under that seed, and they
+    differ from the default seed's; setting the default seed back restores them."""
+    prob = W.analog_sample(20_000)
+    base = O.run(prob, seed=4096, first=0, n=20_000, threads=8, records=True).records
+    try:
+        for sd in (12345, (1 << 40) + 7):
+            ctx.set_seed(sd)
+            print(f"[case] analog sample fp64, seed {sd}", flush=True)
+            gres, grec, gst = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+            ores = O.run(prob, seed=sd, first=0, n=20_000, threads=8, records=True)
+            same = compare_records_fp64(grec, ores.records)
+            compare_tallies_fp64(gres, ores, grec, ores.records, same)
+            assert (grec["hash"] != base["hash"]).mean() > 0.5
+    finally:
+        ctx.set_seed(4096)
+    _, grec, _ = gpu_run(ctx, prob, first=0, n=20_000, precision="fp64")
+    assert (grec["hash"] == base["hash"]).mean() >= 0.999
+
+
 def test_detector_and_tally_filters(ctx):
     prob = W.analog_sample(50_000)
     prob.volumes.append(W.Volume("box", (0.0, 0.0, 300.0), (200.0, 200.0, 2.0), parent=0, detector=True))
