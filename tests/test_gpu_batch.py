@@ -417,6 +417,30 @@ def test_big_grid_fp32_and_batched(ctx):
             np.testing.assert_allclose(sw2, rw2, rtol=1e-9, atol=1e-12)
 
 
+def test_contexts_release_their_device_memory():
+    """Ten contexts, each holding a 57.6 MB tally, batch descriptors, a prepared
+    batch and the autotuner's scratch, created, used and destroyed in turn:
+    the device's free memory comes back to where it started."""
+    import torch
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    for _ in range(10):
+        c = B.Context(device=0, seed=4096)
+        sim = B.Simulation(c, W.vessel_sample(n=20_000))
+        sim.run(first=0, n=20_000, precision="fp32")
+        br = B.BatchRun(c, W.sample_batch(scale=0.002, imaging_histories=5_000, n_sims=4))
+        br.run()
+        pid = c.prepare_batch(br.descriptors(), stride=br.span)
+        c.run_prepared(pid)
+        c.autotune([(sim.geom, sim.src, sim.tallies, 0, 5_000)], sample_fraction=1.0)
+        torch.cuda.synchronize()
+        c.release_batch(pid)
+        c.close()
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    assert free0 - free1 < 256 * 2**20, (free0, free1)
+
+
 def _close(a, b, rtol=1e-12):
     return np.allclose(a, b, rtol=rtol, atol=1e-300)
 
