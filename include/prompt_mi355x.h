@@ -23,8 +23,9 @@
  *     The context owns every object it creates (freed by pr_destroy),
  *     including the device storage of tallies.
  *   - "stream" arguments are hipStream_t values passed as void* (NULL = the
- *     default stream).  Runs are asynchronous on that stream; pr_read_* calls
- *     synchronise it.
+ *     default stream).  Runs and resets are asynchronous on that stream;
+ *     pr_read_* calls wait for the whole device, so results are complete
+ *     whichever streams the runs were issued on.
  *   - One context per host thread.  A context is bound to one HIP device.
  *   - Random numbers: draw k of history h is taken from Philox4x32-10 with
  *     key = seed and counter = (k/2, h); even draws use words 0-1, odd draws
@@ -357,16 +358,16 @@ int pr_autotune(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, double sample_fr
                 void* stream);
 
 /* ---- results ---- */
-/* Synchronise `stream` and copy the tally into host arrays of nbins doubles
- * each (either may be NULL); *n_hist receives the histories run since the
- * last reset.  The mean per source neutron is sum_w / n_hist. */
+/* Wait for the device (every stream) and copy the tally into host arrays of
+ * nbins doubles each (either may be NULL); *n_hist receives the histories run
+ * since the last reset.  The mean per source neutron is sum_w / n_hist. */
 int pr_read_tally(pr_ctx* ctx, int32_t tally, double* sum_w, double* sum_w2, uint64_t* n_hist, size_t nbins,
                   void* stream);
 /* As pr_read_tally for bins [offset, offset + count). */
 int pr_read_tally_range(pr_ctx* ctx, int32_t tally, uint64_t offset, uint64_t count, double* sum_w,
                         double* sum_w2, void* stream);
 int pr_reset_tally(pr_ctx* ctx, int32_t tally, void* stream);
-/* Run statistics accumulated since the last pr_reset_stats (synchronises). */
+/* Run statistics accumulated since the last pr_reset_stats (waits for the device). */
 int pr_read_stats(pr_ctx* ctx, pr_run_stats* out, void* stream);
 int pr_reset_stats(pr_ctx* ctx, void* stream);
 

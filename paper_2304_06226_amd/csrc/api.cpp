@@ -1113,7 +1113,8 @@ extern "C" int pr_read_tally_range(pr_ctx* c, int32_t tally, uint64_t offset, ui
     if (offset > T.nbins || count > T.nbins - offset) return fail(c, PR_EWORKSPACE, "range beyond the tally's bins");
     int rc = set_device(c);
     if (rc) return rc;
-    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    (void)stream;   // reads wait for the whole device: runs may be on any stream
+    HIPCHK(c, hipDeviceSynchronize());
     if (count == 0) return PR_OK;
     // device layout is (sum w, sum w^2) interleaved per bin: copy in slices and split
     const uint64_t slice = 1ull << 22;
@@ -1143,7 +1144,8 @@ extern "C" int pr_read_tally(pr_ctx* c, int32_t tally, double* sw, double* sw2, 
         return fail(c, PR_EWORKSPACE, "tally %d has %llu bins, buffer holds %zu", tally, (unsigned long long)T.nbins, nbins);
     int rc = set_device(c);
     if (rc) return rc;
-    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    (void)stream;   // reads wait for the whole device: runs may be on any stream
+    HIPCHK(c, hipDeviceSynchronize());
     if (n_hist) {
         unsigned long long d = 0;
         if (T.dev_nhist) HIPCHK(c, hipMemcpy(&d, T.dev_nhist, sizeof(d), hipMemcpyDeviceToHost));
@@ -1170,7 +1172,8 @@ extern "C" int pr_read_stats(pr_ctx* c, pr_run_stats* out, void* stream) {
     int rc = set_device(c);
     if (rc) return rc;
     unsigned long long h[ST_N];
-    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    (void)stream;   // reads wait for the whole device: runs may be on any stream
+    HIPCHK(c, hipDeviceSynchronize());
     HIPCHK(c, hipMemcpy(h, c->stats, sizeof(h), hipMemcpyDeviceToHost));
     out->histories = h[ST_HIST];
     out->escaped = h[ST_ESC];

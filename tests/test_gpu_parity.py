@@ -113,6 +113,24 @@ def test_run_seed_fp64_elementwise(ctx):
     assert (grec["hash"] == base["hash"]).mean() >= 0.999
 
 
+def test_reads_wait_for_runs_on_any_stream(ctx):
+    """A run issued on a side stream and read back from the default stream gives
+    the same tallies as a run on the default stream: reads wait for the device."""
+    import torch
+    prob = W.biased_sample(n=2_000_000)
+    ref = B.Simulation(ctx, prob)
+    ref.run(first=0, n=prob.n_histories, precision="fp32")
+    expect = ref.results()
+    side = torch.cuda.Stream()
+    sim = B.Simulation(ctx, prob)
+    with torch.cuda.stream(side):
+        sim.run(first=0, n=prob.n_histories, precision="fp32")
+    got = sim.results()          # read from the default stream, no explicit synchronisation
+    for (sw, sw2, nh), (rw, rw2, rn) in zip(got, expect):
+        assert nh == rn == prob.n_histories
+        np.testing.assert_allclose(sw, rw, rtol=1e-9, atol=1e-12)
+
+
 def test_detector_and_tally_filters(ctx):
     prob = W.analog_sample(50_000)
     prob.volumes.append(W.Volume("box", (0.0, 0.0, 300.0), (200.0, 200.0, 2.0), parent=0, detector=True))
