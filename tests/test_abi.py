@@ -132,6 +132,31 @@ def test_source_and_tally_validation(ctx):
     assert code_of(lambda: ctx.tally_nbins(5)) == -2
 
 
+def test_size_limits_are_enforced(ctx):
+    """Each documented size limit is checked just beyond it (and accepted at it)."""
+    # tally bins: at most 2^36 over all axes
+    big = [W.Axis("x", 0, 1, 1024)] * 3
+    assert code_of(lambda: ctx.create_tally(W.Tally(axes=big + [W.Axis("y", 0, 1, 65)]))) == -1
+    # Bragg families: at most 1024
+    m = W.sample_material()
+    def families(k):
+        d = np.linspace(3.0, 0.5, k)
+        return dataclasses.replace(m, d=d, mult=np.full(k, 6, dtype=np.int32), f2=np.full(k, 2.0))
+    assert ctx.create_material(families(1024)) >= 0
+    assert code_of(lambda: ctx.create_material(families(1025))) == -1
+    # tables: 2..4096 rows
+    def table(k):
+        lam = np.linspace(0.5, 10.0, k)
+        return dataclasses.replace(m, table_lambda=lam, table_sigma_abs=np.ones(k), table_sigma_inc=np.ones(k))
+    assert ctx.create_material(table(4096)) >= 0
+    assert code_of(lambda: ctx.create_material(table(4097))) == -1
+    assert code_of(lambda: ctx.create_material(table(1))) == -1
+    # geometry: at least one volume
+    assert code_of(lambda: ctx.create_geometry([], [])) == -1
+    # batches: at least one simulation
+    assert code_of(lambda: ctx.run_batch([], stream=0)) == -1
+
+
 def test_run_needs_a_device(ctx):
     p = W.analog_sample()
     sim = B.Simulation(ctx, p)
