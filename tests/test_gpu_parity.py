@@ -428,6 +428,33 @@ def test_tabulated_cross_sections_fp32(ctx):
 # Edge cases: empty runs, the top of the history-id range
 # ---------------------------------------------------------------------------
 
+def _largest_material_problem(n):
+    """The largest material the library accepts: 1024 Bragg families (d from 6 A
+    down to 0.5 A, so every 1.2-2.4 A wavelength sees hundreds of active edges)
+    and 4096-row absorption/incoherent tables, in the sample cylinder under a
+    uniform 1.2-2.4 A pencil beam, scattering biased by 2."""
+    rng = np.random.default_rng(7)
+    k = 1024
+    d = np.sort(rng.uniform(0.5, 6.0, k))[::-1].copy()
+    lam = np.linspace(0.4, 12.0, 4096)
+    m = dataclasses.replace(W.sample_material(), d=d, mult=rng.integers(1, 49, k).astype(np.int32),
+                            f2=rng.uniform(0.0, 0.3, k), table_lambda=lam,
+                            table_sigma_abs=1.5 + 0.8 * lam, table_sigma_inc=4.0 + 0.1 * np.sin(lam))
+    prob = W.analog_sample(n)
+    prob.materials = [m.biased(scatter_bias=2.0)]
+    prob.source = dataclasses.replace(prob.source, spectrum="uniform", lam_lo=1.2, lam_hi=2.4)
+    prob.name = "largest-material"
+    return prob
+
+
+def test_largest_material_fp64_elementwise(ctx):
+    _fp64_case(ctx, _largest_material_problem(20_000), 0, 20_000)
+
+
+def test_largest_material_fp32(ctx):
+    _fp32_case(ctx, _largest_material_problem(200_000), 200_000)
+
+
 def test_empty_runs_change_nothing(ctx):
     import torch
     print("[case] empty runs", flush=True)
