@@ -311,10 +311,13 @@ def _q_orders_problem(mat, n):
     return p
 
 
-@pytest.mark.parametrize("gs,ga", [(4.0, 0.5), (1.0, 0.0), (0.0, 1.0)])
+@pytest.mark.parametrize("gs,ga", [(4.0, 0.5), (1.0, 0.0), (0.0, 1.0), (0.0, 0.0)])
 def test_q_orders_and_bias_factors_fp64_elementwise(ctx, gs, ga):
     mat = W.sample_material().biased(scatter_bias=gs, abs_bias=ga)
-    _fp64_case(ctx, _q_orders_problem(mat, 50_000), 4242, 50_000)
+    _, grec, _, _ = _fp64_case(ctx, _q_orders_problem(mat, 50_000), 4242, 50_000)
+    if gs == 0.0 and ga == 0.0:
+        # every process removed: the sample is vacuum, every history passes with weight 1
+        assert np.all(grec["n_scat"] == 0) and np.all(grec["w"] == 1.0) and np.all(grec["term"] == B.END_ESCAPE)
 
 
 @pytest.mark.parametrize("gs,ga", [(4.0, 0.5), (1.0, 0.0)])
