@@ -240,6 +240,10 @@ def main():
         out["batched"] = {"value": batch.total_histories / bms * 1e3, "unit": "histories/s", "ms_per_step": bms,
                           "histories_per_step": batch.total_histories, "simulations": len(batch.problems),
                           "steps_per_history": bst["steps"] / max(1, bst["histories"]), "tuning": tuned,
+                          "roofline": {"bound": "alu", "unit": "TOP/s", "peak": VALU_PEAK_TOPS,
+                                       "achieved": algorithmic_ops(bst) / (args.batch_steps * bms * 1e-3) / 1e12,
+                                       "frac": algorithmic_ops(bst) / (args.batch_steps * bms * 1e-3) / 1e12
+                                       / VALU_PEAK_TOPS, "kernel": "k_batch"},
                           "step": "HIP graph replay of a prepared batch run",
                           "host_ms_per_step": {"graph_replay": h_graph, "pr_run_batch": h_run_batch},
                           "workload": "256 powder simulations (r 1-20 mm, a 3.5-6 A, lambda 1-5 A, bias 1/2/4/8, "
