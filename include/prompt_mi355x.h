@@ -69,7 +69,9 @@ enum {
                             product and tallies; LDS-staged tables, LDS-privatised small tallies.
                             A daughter's piece shorter than 2^-20 (|x|+|y|+|z|) along the ray is
                             passed by rather than entered (an FP32 position would not move
-                            across it) */
+                            across it), so volumes should be thicker than about 1e-6 of their
+                            distance from the origin (0.1 mm at 100 m); use PR_FP64_PLAIN for
+                            thinner foils far from the origin */
 };
 /* termination codes written to history records */
 enum { PR_END_ESCAPE = 1, PR_END_ABSORB = 2, PR_END_KILL = 3, PR_END_DETECT = 4, PR_END_CAPPED = 5,
