@@ -64,7 +64,7 @@ enum { PR_ACC_FP64 = 0, PR_ACC_KAHAN_FP32 = 1 };
 /* precision policies of pr_run_histories */
 enum {
     PR_FP64_PLAIN = 0,   /* one thread per history, everything in FP64, global tables and atomics */
-    PR_FP32_MIXED = 1    /* persistent lanes refilled from a wave-shared history counter; FP32
+    PR_FP32_MIXED = 1,   /* persistent lanes refilled from a wave-shared history counter; FP32
                             positions, directions, cross sections and sampling; FP64 weight
                             product and tallies; LDS-staged tables, LDS-privatised small tallies.
                             A daughter's piece shorter than 2^-20 (|x|+|y|+|z|) along the ray is
@@ -72,6 +72,14 @@ enum {
                             across it), so volumes should be thicker than about 1e-6 of their
                             distance from the origin (0.1 mm at 100 m); use PR_FP64_PLAIN for
                             thinner foils far from the origin */
+    PR_FP64_PERSISTENT = 2  /* the persistent lanes, LDS-privatised tallies and bin cache of
+                            PR_FP32_MIXED around the FP64 step of PR_FP64_PLAIN: every
+                            history's events, final weight and exit state equal
+                            PR_FP64_PLAIN's bit for bit, and tallies agree to the rounding
+                            of the order of summation.  Scene tables are read from global
+                            memory; the launch tuning (block, blocks per CU, refill
+                            threshold, chunk, bin cache) is the one PR_FP32_MIXED uses,
+                            waves_per_simd excepted */
 };
 /* termination codes written to history records */
 enum { PR_END_ESCAPE = 1, PR_END_ABSORB = 2, PR_END_KILL = 3, PR_END_DETECT = 4, PR_END_CAPPED = 5,
@@ -260,7 +268,7 @@ int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
 /* ---- running ---- */
 /* Run histories [first_history, first_history + n) of source `src` through
  * geometry `geom`, scoring into the n_tallies tallies listed.  precision is
- * PR_FP64_PLAIN or PR_FP32_MIXED.  records_dev is NULL or a device buffer of
+ * PR_FP64_PLAIN, PR_FP32_MIXED or PR_FP64_PERSISTENT.  records_dev is NULL or a device buffer of
  * n pr_history_record entries (record i is history first_history + i).
  * Asynchronous on `stream`; tallies and run statistics accumulate across runs
  * until reset. */
@@ -315,7 +323,7 @@ int pr_prepare_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t pre
 int pr_run_prepared(pr_ctx* ctx, int32_t batch, void* stream);
 int pr_release_batch(pr_ctx* ctx, int32_t batch);
 
-/* ---- launch tuning of PR_FP32_MIXED ---- */
+/* ---- launch tuning of the persistent policies (PR_FP32_MIXED, PR_FP64_PERSISTENT) ---- */
 /* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
  * blocks per compute unit of the persistent grid (0 = occupancy limit);
  * refill_threshold: idle lanes of a wave that trigger a refill (1..64);
@@ -327,7 +335,8 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
  * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
  * spilling some state to scratch; which is faster depends on the workload);
- * kernels with a daughter grid always run 4.
+ * kernels with a daughter grid always run 4, and PR_FP64_PERSISTENT runs 2
+ * (3 with a daughter grid), as PR_FP64_PLAIN does.
  * Scenes with a daughter grid whose grid, box bounds and tables are staged in
  * LDS run blocks of 256 or 512 threads, whichever keeps the most waves
  * resident per CU, unless blocks_per_cu is set (then `block` is used).

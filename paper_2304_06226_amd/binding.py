@@ -19,8 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprompt_mi355x.so")
 
 PR_OK = 0
-PR_FP64_PLAIN, PR_FP32_MIXED = 0, 1
-PRECISION = {"fp64": PR_FP64_PLAIN, "fp64_plain": PR_FP64_PLAIN, "fp32": PR_FP32_MIXED, "fp32_mixed": PR_FP32_MIXED}
+PR_FP64_PLAIN, PR_FP32_MIXED, PR_FP64_PERSISTENT = 0, 1, 2
+PRECISION = {"fp64": PR_FP64_PLAIN, "fp64_plain": PR_FP64_PLAIN, "fp32": PR_FP32_MIXED, "fp32_mixed": PR_FP32_MIXED,
+             "fp64_persistent": PR_FP64_PERSISTENT}
 
 SOLID = {"box": 0, "cylinder": 1, "cyl_shell": 2, "sphere": 3, "sph_shell": 4}
 SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}

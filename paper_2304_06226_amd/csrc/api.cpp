@@ -961,7 +961,8 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     if (src < 0 || src >= (int)c->srcs.size()) return fail(c, PR_ENOTFOUND, "source %d unknown", src);
     if (nt < 0 || nt > kMaxTallies) return fail(c, PR_EINVAL, "n_tallies must be in [0, %d]", kMaxTallies);
     if (nt > 0 && !tallies) return fail(c, PR_EINVAL, "tallies is null");
-    if (precision != PR_FP64_PLAIN && precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "precision invalid");
+    if (precision != PR_FP64_PLAIN && precision != PR_FP32_MIXED && precision != PR_FP64_PERSISTENT)
+        return fail(c, PR_EINVAL, "precision invalid");
     if (n > (1ull << 48) || first > (1ull << 62)) return fail(c, PR_EINVAL, "history range too large");
     const Geometry& g = c->geoms[geom];
     memset(&P, 0, sizeof(P));
@@ -986,12 +987,15 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n_cell_start = (int)g.cell_start.size();
     P.n_cell_items = (int)g.cell_items.size();
     P.has_grid = g.gd.empty() ? 0 : 1;
-    P.scene_in_lds = g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget) ? 1 : 0;
+    // the FP32 scene may be staged into LDS; the FP64 one is read from global memory
+    P.scene_in_lds = precision == PR_FP32_MIXED &&
+                     g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget);
+    P.fp64 = precision == PR_FP64_PERSISTENT ? 1 : 0;
     P.kinds = g.kinds;
     make_source_dev(c->srcs[src], P.src);
     P.n_tallies = nt;
     int lds_doubles = 0;
-    const int budget = precision == PR_FP32_MIXED ? c->lds_tally_budget / 8 : 0;
+    const int budget = precision != PR_FP64_PLAIN ? c->lds_tally_budget / 8 : 0;
     for (int i = 0; i < nt; ++i) {
         int t = tallies[i];
         if (t < 0 || t >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", t);
@@ -1027,9 +1031,9 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
             lds_doubles += 2 * (int)T.nbins;
         }
     }
-    // tallies too large to privatise get an LDS bin cache (mixed policy)
+    // tallies too large to privatise get an LDS bin cache (persistent policies)
     int slots = 0;
-    if (precision == PR_FP32_MIXED && c->bin_cache_slots > 0) {
+    if (precision != PR_FP64_PLAIN && c->bin_cache_slots > 0) {
         int bits = 0;
         while ((1 << (bits + 1)) <= c->bin_cache_slots) ++bits;
         for (int i = 0; i < nt; ++i) {

@@ -168,7 +168,7 @@ struct Params {
                                    // grid scenes stage all but the volume table, plus the box bounds
     int32_t has_grid;              // some volume navigates its daughters through a grid
     uint32_t kinds;                // solid kinds present in the scene (bit per kind)
-    int32_t pad2;
+    int32_t fp64;                  // persistent policy with FP64 transport (FP64 scene, read from global memory)
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
     int32_t cache_slots;           // LDS bin-cache slots over all cached tallies (mixed policy)
@@ -180,7 +180,7 @@ struct Params {
     unsigned long long* counter;   // history counter of the persistent policy
     int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
-    int32_t waves;                 // persistent policy: waves per SIMD the launched variant is built for (4 or 5)
+    int32_t waves;                 // FP32 persistent policy: waves per SIMD the launched variant is built for (4 or 5)
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)

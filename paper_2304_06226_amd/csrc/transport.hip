@@ -9,6 +9,9 @@
 //   materials, Bragg tables) is staged into LDS as FP32; small tallies are
 //   privatised in LDS and merged into global memory once per block; the
 //   weight product and every tally accumulation stay FP64.
+// PR_FP64_PERSISTENT: the same persistent waves and LDS tallies around the
+//   FP64 step of the plain kernel, so each history's events, weight and exit
+//   state equal the plain kernel's bit for bit.
 // Batched (k_batch): the mixed policy over many simulations at once; a block
 //   stages one simulation's scene and tallies in LDS and its waves claim chunks
 //   of that simulation's histories from its own counter until none are left,
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
 }
 
 // ------------------------------------------------------------------------
-// FP32 mixed, persistent
+// Persistent policies (FP32 mixed, FP64)
 // ------------------------------------------------------------------------
 
 // LDS of a mixed-policy block: [privatised tallies (doubles)] [bin-cache values
@@ -181,12 +184,41 @@ __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes
     for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) d[i] = s[i];
 }
 
-// WPE resident waves per SIMD (4 or 5; grid variants 4).  The grid variants would
-// take 151 VGPRs (three waves); held to 128 they spill a few values to scratch,
-// and the extra wave per SIMD hides the latency of the grid walk (1000-box
-// imaging 10.3 -> 8.6 ms).  Five waves (96 VGPRs) help some scenes and hurt
-// others, so it is a launch choice.
-template <bool REC, bool SLDS, bool GRID, int WPE>
+// Scene of a persistent launch: the FP32 tables, staged in LDS (SLDS) or read
+// from global memory, or the FP64 tables in global memory.
+template <class R, bool SLDS, bool GRID>
+struct PersistentScene;
+
+template <bool SLDS, bool GRID>
+struct PersistentScene<float, SLDS, GRID> {
+    static __device__ __forceinline__ SceneT<float> get(const Params& P, char* base, const LdsLayout& L) {
+        return SLDS ? SceneT<float>{GRID ? P.vols_f : (const VolT<float>*)(base + L.vols),
+                                    (const MatT<float>*)(base + L.mats), (const FamT<float>*)(base + L.fams),
+                                    (const int32_t*)(base + L.children), (const GridT<float>*)(base + L.grids),
+                                    (const int32_t*)(base + L.cell_start), (const int32_t*)(base + L.cell_items),
+                                    GRID ? (const BoxT<float>*)(base + L.boxes) : P.boxes_f, P.kinds}
+                    : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items,
+                                    P.boxes_f, P.kinds};
+    }
+};
+
+template <bool GRID>
+struct PersistentScene<double, false, GRID> {
+    static __device__ __forceinline__ SceneT<double> get(const Params& P, char*, const LdsLayout&) {
+        return SceneT<double>{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items,
+                              P.boxes_d, P.kinds};
+    }
+};
+
+// R = float: the FP32 mixed policy; R = double: the persistent FP64 policy, whose
+// histories take exactly the arithmetic of the plain kernel.
+// WPE resident waves per SIMD (FP32: 4 or 5, grid variants 4; FP64: 2, grid 3,
+// as the plain kernel).  The FP32 grid variants would take 151 VGPRs (three
+// waves); held to 128 they spill a few values to scratch, and the extra wave
+// per SIMD hides the latency of the grid walk (1000-box imaging 10.3 -> 8.6 ms).
+// Five waves (96 VGPRs) help some scenes and hurt others, so it is a launch
+// choice.
+template <class R, bool REC, bool SLDS, bool GRID, int WPE>
 __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_mixed(Params P) {
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
@@ -206,20 +238,13 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
     for (int i = threadIdx.x; i < P.lds_tally_doubles + 2 * P.cache_slots; i += blockDim.x) lds[i] = 0.0;
     for (int i = threadIdx.x; i < P.cache_slots; i += blockDim.x) ckeys[i] = kEmptyKey;
     __syncthreads();
-    const SceneT<float> S =
-        SLDS ? SceneT<float>{GRID ? P.vols_f : (const VolT<float>*)(base + L.vols), (const MatT<float>*)(base + L.mats),
-                             (const FamT<float>*)(base + L.fams), (const int32_t*)(base + L.children),
-                             (const GridT<float>*)(base + L.grids), (const int32_t*)(base + L.cell_start),
-                             (const int32_t*)(base + L.cell_items),
-                             GRID ? (const BoxT<float>*)(base + L.boxes) : P.boxes_f, P.kinds}
-             : SceneT<float>{P.vols_f, P.mats_f, P.fams_f, P.children, P.grids_f, P.cell_start, P.cell_items,
-                             P.boxes_f, P.kinds};
+    const SceneT<R> S = PersistentScene<R, SLDS, GRID>::get(P, base, L);
 
     Counters cnt = {};
-    PState<float> s;
+    PState<R> s;
     s.term = 1;            // idle, no history
     s.xs_mat = -2;         // no cached cross sections
-    s.lam = -1.f;
+    s.lam = (R)-1;
     bool pending = false;  // finished history not yet scored
     bool exhausted = false;
     // the wave's current chunk of history indices [cnext, cend), claimed with one
@@ -230,8 +255,8 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
     // a pencil starts every history at the same point: locate it once
     int start_region = -2;
     if (P.src.kind == PR_PENCIL) {
-        const float o[3] = {(float)P.src.o[0], (float)P.src.o[1], (float)P.src.o[2]};
-        start_region = locate<float, GRID>(S, o, 0);
+        const R o[3] = {(R)P.src.o[0], (R)P.src.o[1], (R)P.src.o[2]};
+        start_region = locate<R, GRID>(S, o, 0);
     }
     for (;;) {
         const bool idle = s.term != 0;
@@ -243,12 +268,12 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
                     for (int t = 0; t < P.n_tallies; ++t) {
                         const TallyDev& T = P.tallies[t];
-                        int64_t b = tally_bin<float>(T, s);
+                        int64_t b = tally_bin<R>(T, s);
                         if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
                     }
                 }
-                if (REC) write_record<float>(P.records + (s.h - P.first), s);
-                count_end<float>(cnt, s);
+                if (REC) write_record<R>(P.records + (s.h - P.first), s);
+                count_end<R>(cnt, s);
                 pending = false;
             }
             if (!exhausted && cnext >= cend) {
@@ -267,8 +292,8 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<float, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
-                                                 start_region);
+                        source<R, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
+                                             start_region);
                         pending = s.term != 0;   // born outside the world: counted at the next refill
                     }
                 }
@@ -281,7 +306,7 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
             continue;
         }
         if (s.term == 0) {
-            step<float, REC, GRID>(s, S, P.seed);
+            step<R, REC, GRID>(s, S, P.seed);
             pending = s.term != 0;
         }
     }
@@ -615,20 +640,24 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     return hipGetLastError();
 }
 
-// variant index: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five waves per SIMD (no grid only)
+// variant index: FP32: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five
+// waves per SIMD (no grid only); FP64 (scene in global memory): 6, grid 7
 static int mixed_variant(const Params& P) {
+    if (P.fp64) return P.has_grid ? 7 : 6;
     return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0);
 }
 
 template <bool REC>
 static void launch_mixed_t(const Params& P, int grid, int block, int lds, hipStream_t st) {
     switch (mixed_variant(P)) {
-    case 0: hipLaunchKernelGGL((k_mixed<REC, false, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 1: hipLaunchKernelGGL((k_mixed<REC, true, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 2: hipLaunchKernelGGL((k_mixed<REC, false, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 3: hipLaunchKernelGGL((k_mixed<REC, true, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 4: hipLaunchKernelGGL((k_mixed<REC, false, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
-    default: hipLaunchKernelGGL((k_mixed<REC, true, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
+    case 0: hipLaunchKernelGGL((k_mixed<float, REC, false, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 1: hipLaunchKernelGGL((k_mixed<float, REC, true, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 2: hipLaunchKernelGGL((k_mixed<float, REC, false, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 3: hipLaunchKernelGGL((k_mixed<float, REC, true, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
+    case 4: hipLaunchKernelGGL((k_mixed<float, REC, false, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
+    case 5: hipLaunchKernelGGL((k_mixed<float, REC, true, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
+    case 6: hipLaunchKernelGGL((k_mixed<double, REC, false, false, 2>), dim3(grid), dim3(block), lds, st, P); break;
+    default: hipLaunchKernelGGL((k_mixed<double, REC, false, true, 3>), dim3(grid), dim3(block), lds, st, P); break;
     }
 }
 
@@ -646,12 +675,14 @@ int mixed_occupancy(const Params& P, int block) {
     const int lds = mixed_lds_bytes(P);
     hipError_t e;
     switch (mixed_variant(P)) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false, 4>, block, lds); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false, 4>, block, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, true, 4>, block, lds); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, true, 4>, block, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, false, false, 5>, block, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<false, true, false, 5>, block, lds); break;
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, false, 4>, block, lds); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, false, 4>, block, lds); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, true, 4>, block, lds); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, true, 4>, block, lds); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, false, 5>, block, lds); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, false, 5>, block, lds); break;
+    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<double, false, false, false, 2>, block, lds); break;
+    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<double, false, false, true, 3>, block, lds); break;
     }
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;

@@ -158,11 +158,15 @@ def test_size_limits_are_enforced(ctx):
 
 
 def test_run_needs_a_device(ctx):
+    """Every precision policy passes argument checks and then needs the device;
+    an unknown policy is rejected first."""
     p = W.analog_sample()
     sim = B.Simulation(ctx, p)
-    with pytest.raises(B.PromptError) as e:
-        ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, "fp64", None, 0)
-    assert e.value.code == -5
+    for prec in ("fp64", "fp32", "fp64_persistent"):
+        with pytest.raises(B.PromptError) as e:
+            ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, prec, None, 0)
+        assert e.value.code == -5
+    assert code_of(lambda: ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, 3, None, 0)) == -1
 
 
 def test_tuning_validation(ctx):
