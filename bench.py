@@ -48,8 +48,8 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 # the compiler flags);
 # profiles/k_mixed_biased_sample_1e7.txt holds the summary.  Nearly all of it is
 # the 32-byte memory-side writes of FP64 tally atomics.
-MEASURED_TRAFFIC = {"source_hash": "6842c06954f03ba6",
-                    "k_mixed": 0.456e6 + 354.892e6, "k_plain": 0.550e6 + 669.999e6}
+MEASURED_TRAFFIC = {"source_hash": "857083d4215e3e4a",
+                    "k_mixed<float>": 0.439e6 + 354.918e6, "k_plain": 0.526e6 + 669.999e6}
 
 
 def kernel_source_hash() -> str:
@@ -179,10 +179,16 @@ def main():
         ms, st = time_policy(torch, sim, n, "fp32", args.steps, args.warmup)
         fp32 = (ms, st)
         print(f"[bench] fp32-mixed {ms:.3f} ms/step, {n / ms * 1e3:.4g} histories/s", file=sys.stderr, flush=True)
+    fp64p = None
     if args.only in ("fp64", "both"):
         ms64, st64 = time_policy(torch, sim, n, "fp64", args.fp64_steps, 1)
         fp64 = (ms64, st64)
         print(f"[bench] fp64-plain {ms64:.3f} ms/step, {n / ms64 * 1e3:.4g} histories/s", file=sys.stderr, flush=True)
+        # the same FP64 histories (identical records) on persistent lanes with LDS tallies
+        ms64p, _ = time_policy(torch, sim, n, "fp64_persistent", args.fp64_steps, 1)
+        fp64p = ms64p
+        print(f"[bench] fp64-persistent {ms64p:.3f} ms/step, {n / ms64p * 1e3:.4g} histories/s", file=sys.stderr,
+              flush=True)
 
     head_ms, head_st = fp32 if fp32 else fp64
     out["value"] = n / head_ms * 1e3
@@ -190,7 +196,7 @@ def main():
     out["dtype"] = "f32" if fp32 else "f64"
     per_launch_ops = algorithmic_ops(head_st) / max(1, head_st["histories"]) * n
     achieved = per_launch_ops / (head_ms * 1e-3) / 1e12
-    kname = "k_mixed" if fp32 else "k_plain"
+    kname = "k_mixed<float>" if fp32 else "k_plain"
     traffic = MEASURED_TRAFFIC[kname] if kernel_source_hash() == MEASURED_TRAFFIC["source_hash"] else None
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
                        "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
@@ -198,6 +204,10 @@ def main():
     if fp32 and fp64:
         out["fp64_plain"] = {"value": n / fp64[0] * 1e3, "ms_per_step": fp64[0]}
         out["speedup_vs_fp64_plain"] = fp64[0] / fp32[0]
+        out["fp64_persistent"] = {"value": n / fp64p * 1e3, "ms_per_step": fp64p,
+                                  "note": "the plain kernel's FP64 step on persistent lanes with LDS tallies; "
+                                          "records identical to FP64 plain"}
+        out["speedup_vs_fp64_persistent"] = fp64p / fp32[0]
     out["events_per_history"] = {"steps": head_st["steps"] / head_st["histories"],
                                  "draws": head_st["draws"] / head_st["histories"],
                                  "scatters": head_st["scatters"] / head_st["histories"]}

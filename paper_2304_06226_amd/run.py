@@ -22,7 +22,7 @@ def main(argv=None):
                                            "batch"],
                     default="sample")
     ap.add_argument("--histories", type=float, default=None)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "fp64_persistent"], default="fp32")
     ap.add_argument("--repeat", type=int, default=3)
     ap.add_argument("--autotune", action="store_true")
     args = ap.parse_args(argv)
