@@ -10,8 +10,9 @@ absorbed counter.  One step = one pr_run_histories call over 1e7 histories
 (source, flights, collisions, scoring all inside the timed kernel) with the
 inputs already resident on the GPU.
 
-The FP32-mixed policy is the headline value; the FP64-plain policy is timed
-beside it.  The oracle is timed on the host's cores on a bounded sample.  The
+The FP32-mixed policy is the headline value; the FP64-plain policy and the
+persistent FP64 policy (the same FP64 histories, bit for bit) are timed beside
+it.  The oracle is timed on the host's cores on a bounded sample.  The
 mixed policy runs with the launch tuning stored per workload (measured with
 pr_autotune on MI355X); --autotune measures it afresh before timing.
 """
