@@ -156,7 +156,7 @@ def main():
     import torch
     from paper_2304_06226_amd import binding as B
     from paper_2304_06226_amd import workloads as W
-    from paper_2304_06226_amd.tuning import TUNED
+    from paper_2304_06226_amd.tuning import TUNED, TUNED_FP64_PERSISTENT
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -185,9 +185,14 @@ def main():
         ms64, st64 = time_policy(torch, sim, n, "fp64", args.fp64_steps, 1)
         fp64 = (ms64, st64)
         print(f"[bench] fp64-plain {ms64:.3f} ms/step, {n / ms64 * 1e3:.4g} histories/s", file=sys.stderr, flush=True)
-        # the same FP64 histories (identical records) on persistent lanes with LDS tallies
+        # the same FP64 histories (identical records) on persistent lanes with LDS tallies,
+        # with that policy's stored tuning
+        if not args.autotune:
+            ctx.set_tuning(**TUNED_FP64_PERSISTENT["sample"])
+        fp64p_tuning = ctx.get_tuning()
         ms64p, _ = time_policy(torch, sim, n, "fp64_persistent", args.fp64_steps, 1)
         fp64p = ms64p
+        ctx.set_tuning(**out["tuning"])
         print(f"[bench] fp64-persistent {ms64p:.3f} ms/step, {n / ms64p * 1e3:.4g} histories/s", file=sys.stderr,
               flush=True)
 
@@ -205,7 +210,7 @@ def main():
     if fp32 and fp64:
         out["fp64_plain"] = {"value": n / fp64[0] * 1e3, "ms_per_step": fp64[0]}
         out["speedup_vs_fp64_plain"] = fp64[0] / fp32[0]
-        out["fp64_persistent"] = {"value": n / fp64p * 1e3, "ms_per_step": fp64p,
+        out["fp64_persistent"] = {"value": n / fp64p * 1e3, "ms_per_step": fp64p, "tuning": fp64p_tuning,
                                   "note": "the plain kernel's FP64 step on persistent lanes with LDS tallies; "
                                           "records identical to FP64 plain"}
         out["speedup_vs_fp64_persistent"] = fp64p / fp32[0]

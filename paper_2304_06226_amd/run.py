@@ -30,12 +30,13 @@ def main(argv=None):
     import torch
     from . import binding as B
     from . import workloads as W
-    from .tuning import TUNED
+    from .tuning import TUNED, TUNED_FP64_PERSISTENT
 
     torch.cuda.set_device(0)
     ctx = B.Context(0, seed=W.RUN_SEED)
-    if args.workload in TUNED:
-        ctx.set_tuning(**TUNED[args.workload])
+    stored = TUNED_FP64_PERSISTENT if args.precision == "fp64_persistent" else TUNED
+    if args.workload in stored:
+        ctx.set_tuning(**stored[args.workload])
     if args.workload == "batch":
         batch = W.sample_batch()
         br = B.BatchRun(ctx, batch)

@@ -24,3 +24,18 @@ TUNED = {
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
               "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 5},
 }
+
+# Launch tunings of the PR_FP64_PERSISTENT policy (the same knobs; waves_per_simd
+# does not apply to it), measured at each workload's full size by coordinate
+# descent over refill threshold, chunk, blocks per CU, block size and bin-cache
+# slots, starting from the FP32 entries.  Its lanes run longer steps, so more of
+# them may wait before a refill (guide: 16 -> 48 idle lanes, -17 %).
+TUNED_FP64_PERSISTENT = {
+    "sample": dict(TUNED["sample"], chunk=256),
+    "guide": dict(TUNED["guide"], refill_threshold=48),
+    "vessel": dict(TUNED["vessel"], chunk=1024),
+    "imaging": dict(TUNED["imaging"]),
+    "paper_guide": dict(TUNED["paper_guide"], refill_threshold=32),
+    "paper_chopper": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
+                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4},
+}

@@ -182,6 +182,15 @@ def test_tuning_validation(ctx):
     assert ctx.get_tuning()["waves_per_simd"] == 4
 
 
+def test_stored_tunings_are_valid(ctx):
+    """Every stored launch tuning (both persistent policies) is accepted as is."""
+    from paper_2304_06226_amd.tuning import TUNED, TUNED_FP64_PERSISTENT
+    for table in (TUNED, TUNED_FP64_PERSISTENT):
+        for name, t in table.items():
+            ctx.set_tuning(**t)
+            assert ctx.get_tuning() == t, name
+
+
 def test_prepared_batch_validation(ctx):
     p = W.analog_sample()
     sim = B.Simulation(ctx, p)
