@@ -146,7 +146,8 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="re-measure the launch tuning before timing")
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--one-by-one-steps", type=int, default=1,
-                    help="steps of the batch's simulations launched one by one (FP64 plain and FP32 mixed); 0 skips")
+                    help="steps of the batch's simulations launched one by one (FP64 plain, FP32 mixed, "
+                         "FP64 persistent); 0 skips")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the history range would be "
@@ -268,7 +269,8 @@ def main():
               file=sys.stderr, flush=True)
         if args.one_by_one_steps > 0:
             # the same simulations, one launch each: FP64 plain (the batch's precision
-            # baseline) and FP32 mixed with each workload's stored tuning (the gain of batching)
+            # baseline), FP32 mixed with each workload's stored tuning (the gain of batching)
+            # and persistent FP64 with its own stored tunings
             shift = 4 * br.span
             ms64 = time_one_by_one(torch, ctx, br, "fp64", shift, args.one_by_one_steps)
             shift += (args.one_by_one_steps + 1) * br.span
@@ -278,13 +280,21 @@ def main():
                        dict(TUNED["sample"], chunk=int(min(TUNED["sample"]["chunk"], max(64, p.n_histories // 8192))))
                        for p in batch.problems]
             ms32 = time_one_by_one(torch, ctx, br, "fp32", shift, args.one_by_one_steps, tunings)
+            shift += (args.one_by_one_steps + 1) * br.span
+            tunings64 = [TUNED_FP64_PERSISTENT["imaging"] if p.name.startswith("imaging") else
+                         dict(TUNED_FP64_PERSISTENT["sample"],
+                              chunk=int(min(TUNED_FP64_PERSISTENT["sample"]["chunk"], max(64, p.n_histories // 8192))))
+                         for p in batch.problems]
+            ms64p = time_one_by_one(torch, ctx, br, "fp64_persistent", shift, args.one_by_one_steps, tunings64)
             out["batched"]["one_by_one"] = {
                 "fp64_plain": {"value": batch.total_histories / ms64 * 1e3, "ms_per_step": ms64},
+                "fp64_persistent": {"value": batch.total_histories / ms64p * 1e3, "ms_per_step": ms64p},
                 "fp32_mixed": {"value": batch.total_histories / ms32 * 1e3, "ms_per_step": ms32},
                 "launches_per_step": len(batch.problems)}
             out["batched"]["speedup_vs_fp64_plain"] = ms64 / bms
-            print(f"[bench] one by one: fp64-plain {ms64:.3f} ms, fp32-mixed {ms32:.3f} ms per step",
-                  file=sys.stderr, flush=True)
+            out["batched"]["speedup_vs_fp64_persistent"] = ms64p / bms
+            print(f"[bench] one by one: fp64-plain {ms64:.3f} ms, fp64-persistent {ms64p:.3f} ms, "
+                  f"fp32-mixed {ms32:.3f} ms per step", file=sys.stderr, flush=True)
     if args.paper_guide:
         # the paper's m = 1 guide benchmark at its own size (1e8 neutrons), for context
         # with the paper's only timing (about 140 s on a laptop)
