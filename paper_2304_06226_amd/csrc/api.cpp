@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <map>
 #include <new>
 #include <string>
@@ -913,29 +914,49 @@ static void make_source_dev(const pr_source_desc& s, SourceDev& d) {
     d.slit_size[1] = s.slit_size[1];
 }
 
+static uint32_t tally_qmask(const pr_tally_desc& td);
+
 static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
     memset(&o, 0, sizeof(o));
     const pr_tally_desc& td = T.desc;
-    o.trigger = td.trigger;
-    o.trigger_volume = td.trigger_volume >= 0 ? td.trigger_volume + vol_offset : -1;
-    o.filter = td.filter;
-    o.filter_arg = td.filter_arg;
-    o.naxes = td.naxes;
+    TallyHead& h = o.head;
+    h.term_mask = td.trigger == PR_TRIG_ESCAPE ? 1u << PR_END_ESCAPE
+                  : td.trigger == PR_TRIG_ABSORB ? 1u << PR_END_ABSORB : 1u << PR_END_DETECT;
+    h.volume = td.trigger == PR_TRIG_DETECT && td.trigger_volume >= 0 ? td.trigger_volume + vol_offset : -1;
+    const int32_t big = std::numeric_limits<int32_t>::max();
+    h.nscat_lo = td.filter == PR_FILT_SCATTERED ? 1 : td.filter == PR_FILT_NSCAT_EQ ? td.filter_arg : 0;
+    h.nscat_hi = td.filter == PR_FILT_UNSCATTERED ? 0 : td.filter == PR_FILT_NSCAT_EQ ? td.filter_arg : big;
+    h.naxes = td.naxes;
+    h.qmask = tally_qmask(td);
     for (int a = 0; a < td.naxes; ++a) {
-        o.quantity[a] = td.axes[a].quantity;
-        o.nbins[a] = td.axes[a].nbins;
-        o.lo[a] = td.axes[a].lo;
-        o.hi[a] = td.axes[a].hi;
-        o.scale[a] = td.axes[a].nbins / (td.axes[a].hi - td.axes[a].lo);
+        TallyAxis& A = o.ax[a];
+        A.quantity = td.axes[a].quantity;
+        A.nbins = td.axes[a].nbins;
+        A.lo = td.axes[a].lo;
+        A.hi = td.axes[a].hi;
+        A.scale = td.axes[a].nbins / (td.axes[a].hi - td.axes[a].lo);
+        A.lo_f = (float)A.lo;
+        A.hi_f = (float)A.hi;
+        A.scale_f = (float)A.scale;
     }
     double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
-    for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
+    for (int k = 0; k < 3; ++k) {
+        o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
+        o.beam_f[k] = (float)o.beam[k];
+    }
     o.sw = T.dev;
     o.sw2 = T.dev ? T.dev + 1 : nullptr;
     o.total = (int64_t)T.nbins;
     o.lds_offset = -1;
     o.cache_base = -1;
     o.cache_bits = 0;
+}
+
+// quantities a tally bins, one bit per PR_Q_* value
+static uint32_t tally_qmask(const pr_tally_desc& td) {
+    uint32_t m = 0;
+    for (int a = 0; a < td.naxes; ++a) m |= 1u << td.axes[a].quantity;
+    return m;
 }
 
 constexpr int kLdsPerCu = 160 * 1024;
@@ -1006,26 +1027,8 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= g.nv)
             return fail(c, PR_EINVAL, "tally %d: trigger_volume beyond the geometry", t);
         TallyDev& o = P.tallies[i];
-        o.trigger = td.trigger;
-        o.trigger_volume = td.trigger_volume;
-        o.filter = td.filter;
-        o.filter_arg = td.filter_arg;
-        o.naxes = td.naxes;
-        for (int a = 0; a < td.naxes; ++a) {
-            o.quantity[a] = td.axes[a].quantity;
-            o.nbins[a] = td.axes[a].nbins;
-            o.lo[a] = td.axes[a].lo;
-            o.hi[a] = td.axes[a].hi;
-            o.scale[a] = td.axes[a].nbins / (td.axes[a].hi - td.axes[a].lo);
-        }
-        double bn = std::sqrt(td.beam[0] * td.beam[0] + td.beam[1] * td.beam[1] + td.beam[2] * td.beam[2]);
-        for (int k = 0; k < 3; ++k) o.beam[k] = bn > 0 ? td.beam[k] / bn : 0.0;
-        o.sw = T.dev;
-        o.sw2 = T.dev ? T.dev + 1 : nullptr;
-        o.total = (int64_t)T.nbins;
-        o.lds_offset = -1;
-        o.cache_base = -1;
-        o.cache_bits = 0;
+        make_tally_dev(T, 0, o);
+        P.qmask |= tally_qmask(td);
         if ((int64_t)lds_doubles + 2 * (int64_t)T.nbins <= budget) {
             o.lds_offset = lds_doubles;
             lds_doubles += 2 * (int)T.nbins;
@@ -1048,7 +1051,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     // the time of flight is tracked only when a chopper or a TOF axis needs it
     bool need_time = (g.kinds >> kChopperBit) & 1u;
     for (int i = 0; i < nt; ++i)
-        for (int a = 0; a < P.tallies[i].naxes; ++a) need_time = need_time || P.tallies[i].quantity[a] == PR_Q_TOF;
+        for (int a = 0; a < P.tallies[i].head.naxes; ++a) need_time = need_time || P.tallies[i].ax[a].quantity == PR_Q_TOF;
     if (need_time) P.kinds |= 1u << kTimeBit;
     P.lds_tally_doubles = lds_doubles;
     P.seed = c->seed;

@@ -131,14 +131,47 @@ struct SourceDev {
     double slit[3], slit_size[2];   // moderator source: slit centre and sides
 };
 
+// One axis of a tally.  The FP32 copies of its range and scale are the FP64
+// values rounded to nearest, as a conversion on the device would round them,
+// so the FP32 policy bins with them directly.
+struct TallyAxis {
+    int32_t quantity, nbins;
+    float lo_f, hi_f, scale_f;
+    int32_t pad;
+    double lo, hi, scale;   // scale = nbins / (hi - lo)
+};
+
+template <class R>
+__device__ __forceinline__ void axis_range(const TallyAxis& A, R& lo, R& hi, R& scale);
+template <>
+__device__ __forceinline__ void axis_range<double>(const TallyAxis& A, double& lo, double& hi, double& scale) {
+    lo = A.lo; hi = A.hi; scale = A.scale;
+}
+template <>
+__device__ __forceinline__ void axis_range<float>(const TallyAxis& A, float& lo, float& hi, float& scale) {
+    lo = A.lo_f; hi = A.hi_f; scale = A.scale_f;
+}
+
+// Which finished histories a tally takes, in a form one scalar load brings in:
+// its trigger as a set of termination codes (plus the detector volume for a
+// detection trigger) and its scattering-count filter as an inclusive range.
+struct TallyHead {
+    uint32_t term_mask;           // bit per PR_END_* code that triggers the tally
+    int32_t volume;               // detection trigger: required final region (-1: any)
+    int32_t nscat_lo, nscat_hi;   // scattering-count filter
+    int32_t naxes;
+    uint32_t qmask;               // quantities its axes bin (bit per PR_Q_* value)
+    int32_t pad[2];
+};
+
 struct TallyDev {
-    int32_t trigger, trigger_volume, filter, filter_arg, naxes;
+    TallyHead head;
     int32_t lds_offset;   // privatised copy in LDS (offset in doubles), -1 = none
     int32_t cache_base;   // first slot of this tally's LDS bin cache, -1 = none
     int32_t cache_bits;   // log2 of its slot count
-    int32_t quantity[4];
-    int32_t nbins[4];
-    double lo[4], hi[4], scale[4];   // scale = nbins / (hi - lo)
+    int32_t pad;
+    float beam_f[4];      // the beam direction rounded to FP32 (the FP32 policy's copy)
+    TallyAxis ax[4];
     double beam[3];                  // unit vector
     double* sw;      // device storage: (sum w, sum w^2) interleaved per bin
     double* sw2;     // = sw + 1
@@ -172,7 +205,7 @@ struct Params {
     SourceDev src;
     int32_t n_tallies, lds_tally_doubles;
     int32_t cache_slots;           // LDS bin-cache slots over all cached tallies (mixed policy)
-    int32_t pad1;
+    uint32_t qmask;                // quantities the tallies bin (bit per PR_Q_* value)
     TallyDev tallies[kMaxTallies];
     uint64_t seed, first, n;
     pr_history_record* records;
@@ -1166,47 +1199,67 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
 // Tally bin of a finished history (-1: not scored)
 // -------------------------------------------------------------------------
 
+// Divergence angles of a finished history (they do not depend on the tally),
+// computed once per scoring pass and only when some tally of the launch bins
+// them: qmask is uniform, so the guards are scalar branches.
 template <class R>
-__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s) {
-    if (T.trigger == PR_TRIG_ESCAPE && s.term != PR_END_ESCAPE) return -1;
-    if (T.trigger == PR_TRIG_ABSORB && s.term != PR_END_ABSORB) return -1;
-    if (T.trigger == PR_TRIG_DETECT) {
-        if (s.term != PR_END_DETECT) return -1;
-        if (T.trigger_volume >= 0 && T.trigger_volume != s.region) return -1;
+struct HistAngles {
+    R divx, divy;
+};
+
+template <class R>
+__device__ __forceinline__ HistAngles<R> hist_angles(const PState<R>& s, uint32_t qmask) {
+    HistAngles<R> q{(R)0, (R)0};
+    if (qmask & (1u << PR_Q_DIVX)) q.divx = M<R>::atan2_deg(s.u[0], s.u[2]);
+    if (qmask & (1u << PR_Q_DIVY)) q.divy = M<R>::atan2_deg(s.u[1], s.u[2]);
+    return q;
+}
+
+template <class R>
+__device__ __forceinline__ R beam_component(const TallyDev& T, int k);
+template <>
+__device__ __forceinline__ double beam_component<double>(const TallyDev& T, int k) { return T.beam[k]; }
+template <>
+__device__ __forceinline__ float beam_component<float>(const TallyDev& T, int k) { return T.beam_f[k]; }
+
+// q: the history's divergence angles, computed once for all tallies (PRE), or
+// left to each divergence axis to compute (fewer values live across the loop)
+template <class R, bool PRE = true>
+__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s, const HistAngles<R>& q) {
+    const TallyHead h = T.head;
+    if (!(((h.term_mask >> s.term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
+          (h.volume < 0 || h.volume == s.region)))
+        return -1;
+    // cosine of the angle to the beam, for the 2-theta and momentum-transfer axes
+    R c = (R)0;
+    if (h.qmask & ((1u << PR_Q_THETA2) | (1u << PR_Q_Q))) {
+        c = s.u[0] * beam_component<R>(T, 0) + s.u[1] * beam_component<R>(T, 1) + s.u[2] * beam_component<R>(T, 2);
+        c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
     }
-    if (T.filter == PR_FILT_UNSCATTERED && s.nscat != 0) return -1;
-    if (T.filter == PR_FILT_SCATTERED && s.nscat < 1) return -1;
-    if (T.filter == PR_FILT_NSCAT_EQ && s.nscat != T.filter_arg) return -1;
     int64_t flat = 0;
-    for (int a = 0; a < T.naxes; ++a) {
+    for (int a = 0; a < h.naxes; ++a) {
+        const TallyAxis& A = T.ax[a];
+        const int32_t quantity = A.quantity, n = A.nbins;
+        R lo, hi, scale;
+        axis_range<R>(A, lo, hi, scale);
         R x;
-        switch (T.quantity[a]) {
-        case PR_Q_THETA2: {
-            R c = s.u[0] * (R)T.beam[0] + s.u[1] * (R)T.beam[1] + s.u[2] * (R)T.beam[2];
-            c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
-            x = M<R>::acos_deg(c);
-            break;
-        }
+        switch (quantity) {
+        case PR_Q_THETA2: x = M<R>::acos_deg(c); break;
         case PR_Q_LAMBDA: x = s.lam; break;
         case PR_Q_X: x = s.p[0]; break;
         case PR_Q_Y: x = s.p[1]; break;
         case PR_Q_Z: x = s.p[2]; break;
-        case PR_Q_DIVX: x = M<R>::atan2_deg(s.u[0], s.u[2]); break;
-        case PR_Q_DIVY: x = M<R>::atan2_deg(s.u[1], s.u[2]); break;
+        case PR_Q_DIVX: x = PRE ? q.divx : M<R>::atan2_deg(s.u[0], s.u[2]); break;
+        case PR_Q_DIVY: x = PRE ? q.divy : M<R>::atan2_deg(s.u[1], s.u[2]); break;
         case PR_Q_TOF: x = s.t; break;
-        case PR_Q_Q: {
+        case PR_Q_Q:
             // momentum transfer from the beam direction: (4 pi / lambda) sin(alpha / 2)
-            R c = s.u[0] * (R)T.beam[0] + s.u[1] * (R)T.beam[1] + s.u[2] * (R)T.beam[2];
-            c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
             x = M<R>::div_((R)(4.0 * 3.14159265358979323846), s.lam) * M<R>::sqrt_(((R)1 - c) / (R)2);
             break;
-        }
         default: x = (R)s.nscat; break;
         }
-        R lo = (R)T.lo[a], hi = (R)T.hi[a];
         if (!(x >= lo && x <= hi)) return -1;
-        int n = T.nbins[a];
-        int b = (int)__builtin_floor((double)((x - lo) * (R)T.scale[a]));
+        int b = (int)__builtin_floor((double)((x - lo) * scale));
         if (x == hi || b >= n) b = n - 1;
         if (b < 0) b = 0;
         flat = flat * n + b;

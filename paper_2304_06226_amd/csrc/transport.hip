@@ -86,9 +86,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
         source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
         while (s.term == 0) step<double, REC, GRID>(s, S, P.seed);
         if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+            const HistAngles<double> q = hist_angles<double>(s, P.qmask);
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
-                int64_t b = tally_bin<double>(T, s);
+                int64_t b = tally_bin<double>(T, s, q);
                 if (b >= 0) {
                     add_global(T, b, s.w, s.w * s.w);
                 }
@@ -266,9 +267,10 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
             // score the histories that ended since the last refill, all together
             if (pending) {
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+                    const HistAngles<R> q = hist_angles<R>(s, P.qmask);
                     for (int t = 0; t < P.n_tallies; ++t) {
                         const TallyDev& T = P.tallies[t];
-                        int64_t b = tally_bin<R>(T, s);
+                        int64_t b = tally_bin<R>(T, s, q);
                         if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
                     }
                 }
@@ -487,8 +489,9 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
         if (n_idle >= B.refill_threshold || n_idle == kWave) {
             if (pending) {
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+                    const HistAngles<float> q{0.f, 0.f};
                     for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
-                        int64_t b = tally_bin<float>(B.tallies[t], s);
+                        int64_t b = tally_bin<float, false>(B.tallies[t], s, q);
                         if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
                     }
                 }
