@@ -332,6 +332,9 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * given to each tally that is not privatised (0 or a power of two <= 4096);
  * chunk: history indices a wave claims from the shared counter (batched
  * runs: from the simulation's own counter) per atomic;
+ * grid_chunk: the claim size for scenes that navigate a daughter grid (their
+ * histories vary more in length, so smaller claims balance the waves), 0 =
+ * chunk; in a batch it applies to the class of grid scenes;
  * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
  * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
  * spilling some state to scratch; which is faster depends on the workload);
@@ -350,6 +353,7 @@ typedef struct {
     int32_t bin_cache_slots;
     int32_t chunk;
     int32_t waves_per_simd;
+    int32_t grid_chunk;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
@@ -357,7 +361,8 @@ int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
 
 /* Pick the launch tuning for a workload by measurement: coordinate descent
  * (two passes) over refill threshold, chunk, resident blocks per CU,
- * bin-cache slots, waves per SIMD and block size, each candidate timed with
+ * bin-cache slots, waves per SIMD, block size and (when a scene has a daughter
+ * grid) the grid claim size, each candidate timed with
  * HIP events on `stream` over a sample of the workload (every simulation's
  * history count times sample_fraction, at least 1; the best claim size depends
  * on the launch's size, so 1 tunes for the full workload).  nsims = 1 tunes pr_run_histories'

@@ -124,6 +124,7 @@ struct pr_ctx {
     int lds_tally_budget = 32768;       // bytes of LDS per block for privatised tallies
     int bin_cache_slots = 1024;         // LDS bin-cache slots per non-privatised tally (power of two, 0 = off)
     int chunk = 256;                    // history indices a wave claims per atomic
+    int grid_chunk = 0;                 // claim size for scenes with a daughter grid (0: chunk)
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     DescSlot slots[4];
@@ -1061,7 +1062,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.stats = c->stats;
     P.counter = c->counter;
     P.refill_threshold = c->refill_threshold;
-    P.chunk = c->chunk;
+    P.chunk = P.has_grid && c->grid_chunk > 0 ? c->grid_chunk : c->chunk;
     P.waves = c->waves_per_simd;
     return PR_OK;
 }
@@ -1217,10 +1218,12 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
     if (t->bin_cache_slots < 0 || t->bin_cache_slots > 4096 || (t->bin_cache_slots & (t->bin_cache_slots - 1)))
         return fail(c, PR_EINVAL, "tuning.bin_cache_slots must be 0 or a power of two up to 4096");
     if (t->chunk < 1 || t->chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.chunk must be 1..2^20");
+    if (t->grid_chunk < 0 || t->grid_chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.grid_chunk must be 0..2^20");
     if (t->waves_per_simd != 0 && t->waves_per_simd != 4 && t->waves_per_simd != 5)
         return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
     c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
+    c->grid_chunk = t->grid_chunk;
     c->mixed_block = t->block;
     c->mixed_blocks_per_cu = t->blocks_per_cu;
     c->refill_threshold = t->refill_threshold;
@@ -1238,6 +1241,7 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->bin_cache_slots = c->bin_cache_slots;
     t->chunk = c->chunk;
     t->waves_per_simd = c->waves_per_simd;
+    t->grid_chunk = c->grid_chunk;
     return PR_OK;
 }
 
@@ -1342,7 +1346,7 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     B.refill_threshold = c->refill_threshold;
     B.waves = c->waves_per_simd;
     B.total_histories = total;
-    B.chunk = (uint64_t)c->chunk;
+    B.chunk = (uint64_t)(grid_nav && c->grid_chunk > 0 ? c->grid_chunk : c->chunk);
     B.seed = c->seed;
     B.stats = trial ? c->scratch_stats : c->stats;
     B.sim_next = nullptr;
@@ -1645,6 +1649,10 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->waves_per_simd, {4, 5}},
         {&c->mixed_block, {64, 128, 256}},
     };
+    // scenes with a daughter grid get their own claim size
+    bool any_grid = false;
+    for (const auto& s : sample) any_grid = any_grid || !c->geoms[s.geom].gd.empty();
+    if (any_grid) knobs.push_back({&c->grid_chunk, {0, 64, 128, 256}});
 
     float cur = 0.f;
     rc = trial_ms(c, sample, batched, st, e0, e1, 2, &cur);

@@ -176,6 +176,11 @@ def test_tuning_validation(ctx):
     assert code_of(lambda: ctx.set_tuning(bin_cache_slots=1000)) == -1
     assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
     assert code_of(lambda: ctx.set_tuning(waves_per_simd=3)) == -1
+    assert code_of(lambda: ctx.set_tuning(grid_chunk=-1)) == -1
+    assert code_of(lambda: ctx.set_tuning(grid_chunk=(1 << 20) + 1)) == -1
+    ctx.set_tuning(grid_chunk=128)
+    assert ctx.get_tuning()["grid_chunk"] == 128
+    ctx.set_tuning(grid_chunk=0)
     ctx.set_tuning(refill_threshold=8, waves_per_simd=5)
     assert ctx.get_tuning()["refill_threshold"] == 8 and ctx.get_tuning()["waves_per_simd"] == 5
     ctx.set_tuning(waves_per_simd=0)

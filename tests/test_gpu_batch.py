@@ -138,7 +138,8 @@ def test_batch_tuning_and_validation(ctx):
     base = ctx.get_tuning()
     res = []
     try:
-        for t in (dict(), dict(chunk=64, refill_threshold=4, bin_cache_slots=0), dict(chunk=1024, bin_cache_slots=4096)):
+        for t in (dict(), dict(chunk=64, refill_threshold=4, bin_cache_slots=0), dict(chunk=1024, bin_cache_slots=4096),
+                  dict(chunk=512, grid_chunk=16), dict(chunk=3, grid_chunk=1000)):
             ctx.set_tuning(**{**base, **t})
             br = B.BatchRun(ctx, batch)
             br.run()
