@@ -107,6 +107,8 @@ TUNINGS = [
     dict(block=64, blocks_per_cu=0, refill_threshold=1, chunk=1, bin_cache_slots=0, lds_tally_bytes=32768),
     dict(block=256, blocks_per_cu=1, refill_threshold=64, chunk=4096, bin_cache_slots=2048, lds_tally_bytes=0),
     dict(block=128, blocks_per_cu=2, refill_threshold=17, chunk=100, bin_cache_slots=256, lds_tally_bytes=32768),
+    dict(block=256, blocks_per_cu=0, refill_threshold=32, chunk=1024, bin_cache_slots=256, lds_tally_bytes=32768,
+         grid_chunk=7),
 ]
 
 
