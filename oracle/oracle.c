@@ -451,11 +451,14 @@ static int tally_bin(const orc_tally* t, double value, int axis)
     return i;
 }
 
-static void score(const orc_problem* P, acc_t* acc, int term, int det_vol, const double p[3], const double u[3],
-                  double lam, double w, int nscat, double tof)
+/* first_coll = 1: the history's first collision just happened (only the
+ * first-collision tallies fire); first_coll = 0: the history ended with `term` */
+static void score(const orc_problem* P, acc_t* acc, int first_coll, int term, int det_vol, const double p[3],
+                  const double u[3], double lam, double w, int nscat, double tof)
 {
     for (int ti = 0; ti < P->n_tallies; ++ti) {
         const orc_tally* t = &P->tallies[ti];
+        if ((t->trigger == ORC_TRIG_FIRST_COLLISION) != (first_coll != 0)) continue;
         if (t->trigger == ORC_TRIG_ESCAPE && term != ORC_END_ESCAPE) continue;
         if (t->trigger == ORC_TRIG_ABSORB && term != ORC_END_ABSORB) continue;
         if (t->trigger == ORC_TRIG_DETECT) {
@@ -624,6 +627,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
                 w *= 1.0 / ga;
                 term = ORC_END_ABSORB;
                 hash_event(&hash, ORC_EV_ABS, 0);
+                if (nscat == 0) score(P, acc, 1, term, -1, p, u, lam, w, nscat, t);
                 break;
             }
             w *= 1.0 / gs;
@@ -662,6 +666,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
                 hash_event(&hash, ORC_EV_COH, fam);
             }
             nscat++;
+            if (nscat == 1) score(P, acc, 1, 0, -1, p, u, lam, w, nscat, t);
             continue;
         }
 
@@ -707,7 +712,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
     }
 
     if (term == ORC_END_ESCAPE || term == ORC_END_ABSORB || term == ORC_END_DETECT)
-        score(P, acc, term, det_vol, p, u, lam, w, nscat, t);
+        score(P, acc, 0, term, det_vol, p, u, lam, w, nscat, t);
 
     st->histories++;
     st->steps += (uint64_t)steps;

@@ -36,7 +36,11 @@ extern "C" {
 enum { ORC_BOX = 0, ORC_CYLINDER = 1, ORC_CYL_SHELL = 2, ORC_SPHERE = 3, ORC_SPH_SHELL = 4 };
 enum { ORC_PENCIL = 0, ORC_RECT = 1, ORC_RECT_DIVERGENT = 2, ORC_MODERATOR = 3 };
 enum { ORC_MONO = 0, ORC_UNIFORM = 1, ORC_MAXWELL = 2 };
-enum { ORC_TRIG_ESCAPE = 0, ORC_TRIG_ABSORB = 1, ORC_TRIG_DETECT = 2 };
+/* FIRST_COLLISION fires at a history's first absorption or scattering, with the
+ * state just after it (collision point, outgoing direction, weight including the
+ * 1/g factor of the chosen process, scattering count 1, or 0 for an absorption);
+ * the other triggers fire once, when the history ends */
+enum { ORC_TRIG_ESCAPE = 0, ORC_TRIG_ABSORB = 1, ORC_TRIG_DETECT = 2, ORC_TRIG_FIRST_COLLISION = 3 };
 enum { ORC_FILT_ALL = 0, ORC_FILT_UNSCATTERED = 1, ORC_FILT_SCATTERED = 2, ORC_FILT_NSCAT_EQ = 3 };
 enum { ORC_Q_THETA2 = 0, ORC_Q_LAMBDA = 1, ORC_Q_X = 2, ORC_Q_Y = 3, ORC_Q_Z = 4,
        ORC_Q_DIVX = 5, ORC_Q_DIVY = 6, ORC_Q_NSCAT = 7, ORC_Q_Q = 8, ORC_Q_TOF = 9 };

@@ -22,7 +22,7 @@ SRC_PATH = os.path.join(HERE, "oracle.c")
 SOLID = {"box": 0, "cylinder": 1, "cyl_shell": 2, "sphere": 3, "sph_shell": 4}
 SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
-TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
+TRIGGER = {"escape": 0, "absorb": 1, "detect": 2, "first_collision": 3}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
 QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8, "tof": 9}
 MIRROR = {"linear": 0, "tanh": 1}

@@ -32,7 +32,7 @@ RUN_SEED = 4096  # the launcher's default seed (program section, launcher option
 SOLIDS = ("box", "cylinder", "cyl_shell", "sphere", "sph_shell")
 SOURCES = ("pencil", "rect", "rect_divergent", "moderator")
 SPECTRA = ("mono", "uniform", "maxwell")
-TRIGGERS = ("escape", "absorb", "detect")
+TRIGGERS = ("escape", "absorb", "detect", "first_collision")
 FILTERS = ("all", "unscattered", "scattered", "nscat_eq")
 QUANTITIES = ("theta2", "lambda", "x", "y", "z", "div_x", "div_y", "nscat", "q", "tof")
 MIRROR_MODELS = ("linear", "tanh")
