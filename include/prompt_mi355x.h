@@ -21,11 +21,18 @@
  *     abort crosses the ABI.
  *   - create_* calls deep-copy caller arrays; the caller keeps its inputs.
  *     The context owns every object it creates (freed by pr_destroy),
- *     including the device storage of tallies.
+ *     including the device storage of tallies, except storage the caller
+ *     passes to pr_create_tally_in and workspaces passed to pr_run_histories,
+ *     which stay the caller's.
  *   - "stream" arguments are hipStream_t values passed as void* (NULL = the
  *     default stream).  Runs and resets are asynchronous on that stream;
  *     pr_read_* calls wait for the whole device, so results are complete
- *     whichever streams the runs were issued on.
+ *     whichever streams the runs were issued on.  Runs of one context may
+ *     overlap on different streams: each run has its own history-claim
+ *     counter (a caller workspace, or a slot of the context's ring whose reuse
+ *     waits for the run that last held it), tallies and statistics are summed
+ *     with atomics.  A reset that should not race a run must be ordered after
+ *     it by the caller (same stream, or an event).
  *   - One context per host thread.  A context is bound to one HIP device.
  *   - Random numbers: draw k of history h is taken from Philox4x32-10 with
  *     key = seed and counter = (k/2, h); even draws use words 0-1, odd draws
@@ -50,28 +57,42 @@ extern "C" {
 #define PR_EWORKSPACE (-4)  /* a caller buffer is too small */
 #define PR_EDEVICE (-5)     /* a HIP call failed; the message holds its error string */
 #define PR_ENOMEM (-6)      /* host or device allocation failed */
+#define PR_ECAPPED (-7)     /* pr_read_stats: the statistics are complete and filled in, but some history
+                               since the last pr_reset_stats reached PR_MAX_STEPS (terminated there,
+                               counted in pr_run_stats.capped, scored by no tally) */
 
 /* ---- enumerations ---- */
 enum { PR_BOX = 0, PR_CYLINDER = 1, PR_CYL_SHELL = 2, PR_SPHERE = 3, PR_SPH_SHELL = 4 };
 enum { PR_PENCIL = 0, PR_RECT = 1, PR_RECT_DIVERGENT = 2, PR_MODERATOR = 3 };
 enum { PR_MONO = 0, PR_UNIFORM = 1, PR_MAXWELL = 2 };
-enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2 };
+/* PR_TRIG_FIRST_COLLISION (a debugging trigger, FP64 policies of pr_run_histories
+ * only): fires at a history's first absorption or scattering, scoring the state
+ * just after it: the collision point, the outgoing direction (unchanged for an
+ * absorption), the weight including the 1/g factor of the chosen process, and
+ * the scattering count (1 after a scattering, 0 after an absorption).  Its
+ * expectation per source neutron is the first-collision probability of the free
+ * flight law (cross section section) whatever the bias factors. */
+enum { PR_TRIG_ESCAPE = 0, PR_TRIG_ABSORB = 1, PR_TRIG_DETECT = 2, PR_TRIG_FIRST_COLLISION = 3 };
 enum { PR_FILT_ALL = 0, PR_FILT_UNSCATTERED = 1, PR_FILT_SCATTERED = 2, PR_FILT_NSCAT_EQ = 3 };
 enum { PR_Q_THETA2 = 0, PR_Q_LAMBDA = 1, PR_Q_X = 2, PR_Q_Y = 3, PR_Q_Z = 4, PR_Q_DIVX = 5, PR_Q_DIVY = 6,
        PR_Q_NSCAT = 7, PR_Q_Q = 8, PR_Q_TOF = 9 };
 enum { PR_MIRROR_LINEAR = 0, PR_MIRROR_TANH = 1 };
+/* Tally accumulators: FP64 sums (gfx950 adds FP64 atomically in LDS and in global
+ * memory).  PR_ACC_KAHAN_FP32 is reserved and rejected with PR_EINVAL. */
 enum { PR_ACC_FP64 = 0, PR_ACC_KAHAN_FP32 = 1 };
 /* precision policies of pr_run_histories */
 enum {
     PR_FP64_PLAIN = 0,   /* one thread per history, everything in FP64, global tables and atomics */
     PR_FP32_MIXED = 1,   /* persistent lanes refilled from a wave-shared history counter; FP32
                             positions, directions, cross sections and sampling; FP64 weight
-                            product and tallies; LDS-staged tables, LDS-privatised small tallies.
-                            A daughter's piece shorter than 2^-20 (|x|+|y|+|z|) along the ray is
-                            passed by rather than entered (an FP32 position would not move
-                            across it), so volumes should be thicker than about 1e-6 of their
-                            distance from the origin (0.1 mm at 100 m); use PR_FP64_PLAIN for
-                            thinner foils far from the origin */
+                            product and tallies; LDS-staged tables, LDS-privatised small tallies
+                            (or, under a monochromatic source, the slice of a tally at the source
+                            wavelength's bin).  Every volume is entered whatever its thickness;
+                            a history that leaves a daughter by a move shorter than 2^-20
+                            (|x|+|y|+|z|) (an FP32 position may not change over it) does not
+                            re-enter that daughter in its next step through a piece that short,
+                            so rays grazing an edge make progress.  First-collision tallies are
+                            not accepted (PR_EINVAL) */
     PR_FP64_PERSISTENT = 2  /* the persistent lanes, LDS-privatised tallies and bin cache of
                             PR_FP32_MIXED around the FP64 step of PR_FP64_PLAIN: every
                             history's events, final weight and exit state equal
@@ -224,7 +245,7 @@ typedef struct {
     int32_t filter;           /* PR_FILT_* on the history's scattering count */
     int32_t filter_arg;       /* k of PR_FILT_NSCAT_EQ */
     int32_t naxes;            /* 0..4 */
-    int32_t accumulator;      /* PR_ACC_FP64 (PR_ACC_KAHAN_FP32 is accepted and stored in FP64) */
+    int32_t accumulator;      /* PR_ACC_FP64 */
     pr_tally_axis axes[4];
     double beam[3];           /* 2theta reference direction (need not be normalised) */
 } pr_tally_desc;
@@ -232,14 +253,17 @@ typedef struct {
 /* Per-history outcome (96 bytes, little endian), written when a record
  * buffer is given: FNV-1a hash of the event sequence, final weight, final
  * position and direction, wavelength, termination code, scatterings, steps,
- * random draws consumed and the final volume. */
+ * random draws consumed, the final volume and the time since emission in s
+ * (rounded to FP32; 0 unless the run tracks time, i.e. its scene holds a disk
+ * chopper or a tally bins the time of flight). */
 typedef struct {
     uint64_t hash;
     double w;
     double pos[3];
     double dir[3];
     double lambda;
-    int32_t term, n_scat, n_steps, n_draws, region, pad;
+    int32_t term, n_scat, n_steps, n_draws, region;
+    float tof;
 } pr_history_record;
 
 typedef struct {
@@ -261,19 +285,40 @@ int pr_create_geometry(pr_ctx* ctx, const pr_volume_desc* volumes, int32_t n, in
 int pr_create_source(pr_ctx* ctx, const pr_source_desc* desc, int32_t* id);
 /* allocates and zeroes the tally's device storage: 2 x nbins doubles, (sum w,
  * sum w^2) interleaved per bin so that the two atomics of a score update one
- * 16-byte pair; pr_read_tally returns them as separate arrays */
+ * 16-byte pair; pr_read_tally returns them as separate arrays.  Synchronises
+ * the device. */
 int pr_create_tally(pr_ctx* ctx, const pr_tally_desc* desc, int32_t* id);
+/* Bytes of device storage a tally of this description needs (2 x nbins doubles);
+ * validates the description as pr_create_tally does. */
+int pr_tally_storage_size(pr_ctx* ctx, const pr_tally_desc* desc, size_t* bytes);
+/* As pr_create_tally, with the tally's storage in the caller's device buffer
+ * dev_storage of storage_bytes bytes (16-byte aligned, at least
+ * pr_tally_storage_size bytes; PR_EWORKSPACE if smaller): the library zeroes it
+ * (synchronising the device), accumulates into it with the layout above and
+ * never frees it.  The buffer must stay valid until pr_destroy or until no run
+ * uses the tally any more. */
+int pr_create_tally_in(pr_ctx* ctx, const pr_tally_desc* desc, void* dev_storage, size_t storage_bytes,
+                       int32_t* id);
 int pr_tally_nbins(pr_ctx* ctx, int32_t tally, uint64_t* nbins);
 
 /* ---- running ---- */
+/* Bytes of device workspace a run of this precision uses when the caller
+ * provides it (its history-claim counter; 256). */
+int pr_workspace_size(pr_ctx* ctx, int32_t precision, size_t* bytes);
 /* Run histories [first_history, first_history + n) of source `src` through
- * geometry `geom`, scoring into the n_tallies tallies listed.  precision is
- * PR_FP64_PLAIN, PR_FP32_MIXED or PR_FP64_PERSISTENT.  records_dev is NULL or a device buffer of
- * n pr_history_record entries (record i is history first_history + i).
- * Asynchronous on `stream`; tallies and run statistics accumulate across runs
- * until reset. */
+ * geometry `geom`, scoring into the n_tallies tallies listed (the simulation
+ * flow section: source, transport, scoring).  precision is PR_FP64_PLAIN,
+ * PR_FP32_MIXED or PR_FP64_PERSISTENT.  records_dev is NULL or a device buffer
+ * of n pr_history_record entries (record i is history first_history + i).
+ * dev_workspace is NULL or a caller device buffer of ws_bytes >=
+ * pr_workspace_size bytes (8-byte aligned; PR_EWORKSPACE if smaller), owned by
+ * the caller, that the run uses as scratch until it completes on `stream`; with
+ * NULL the run takes a slot of the context's counter ring.  Asynchronous on
+ * `stream`; tallies and run statistics accumulate across runs until reset.
+ * n is at most 2^48 and first_history at most 2^62 (PR_EINVAL). */
 int pr_run_histories(pr_ctx* ctx, int32_t geom, int32_t src, const int32_t* tallies, int32_t n_tallies,
-                     uint64_t first_history, uint64_t n, int32_t precision, void* records_dev, void* stream);
+                     uint64_t first_history, uint64_t n, int32_t precision, void* records_dev, void* dev_workspace,
+                     size_t ws_bytes, void* stream);
 
 /* ---- batched runs ---- */
 /* One simulation of a batch: geometry, source, up to PR_MAX_TALLIES tallies and
@@ -293,7 +338,7 @@ typedef struct {
 /* Run nsims independent simulations of uneven size and geometry in one
  * persistent launch per class of simulations (scene staged in LDS or not,
  * daughter grid or not) of the PR_FP32_MIXED policy (the only policy
- * accepted).  Each block starts on the simulation under its share of the
+ * accepted; first-collision tallies are not).  Each block starts on the simulation under its share of the
  * concatenated history ranges, stages that simulation's scene and tallies in
  * LDS, and its waves claim chunks of that simulation's histories from the
  * simulation's own counter until none are left; the block then merges its
@@ -383,7 +428,8 @@ int pr_read_tally(pr_ctx* ctx, int32_t tally, double* sum_w, double* sum_w2, uin
 int pr_read_tally_range(pr_ctx* ctx, int32_t tally, uint64_t offset, uint64_t count, double* sum_w,
                         double* sum_w2, void* stream);
 int pr_reset_tally(pr_ctx* ctx, int32_t tally, void* stream);
-/* Run statistics accumulated since the last pr_reset_stats (waits for the device). */
+/* Run statistics accumulated since the last pr_reset_stats (waits for the device).
+ * Returns PR_ECAPPED, with *out filled in, when out->capped > 0. */
 int pr_read_stats(pr_ctx* ctx, pr_run_stats* out, void* stream);
 int pr_reset_stats(pr_ctx* ctx, void* stream);
 

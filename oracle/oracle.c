@@ -735,7 +735,7 @@ static void run_history(const orc_problem* P, uint64_t seed, uint64_t hid, acc_t
         rec->n_steps = steps;
         rec->n_draws = (int32_t)rng.k;
         rec->region = region;
-        rec->pad = 0;
+        rec->tof = (float)t;
     }
 }
 

@@ -110,14 +110,15 @@ typedef struct {
     const orc_tally* tallies;
 } orc_problem;
 
-/* per-history outcome (96 bytes) */
+/* per-history outcome (96 bytes); tof: time since emission in s, rounded to FP32 */
 typedef struct {
     uint64_t hash;
     double w;
     double pos[3];
     double dir[3];
     double lambda;
-    int32_t term, n_scat, n_steps, n_draws, region, pad;
+    int32_t term, n_scat, n_steps, n_draws, region;
+    float tof;
 } orc_record;
 
 typedef struct {

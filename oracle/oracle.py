@@ -32,7 +32,7 @@ END_ESCAPE, END_ABSORB, END_KILL, END_DETECT, END_CAPPED, END_OUTSIDE = 1, 2, 3,
 # per-history record as laid out by orc_record (96 bytes)
 RECORD_DTYPE = np.dtype([("hash", "<u8"), ("w", "<f8"), ("pos", "<f8", 3), ("dir", "<f8", 3),
                          ("lambda", "<f8"), ("term", "<i4"), ("n_scat", "<i4"), ("n_steps", "<i4"),
-                         ("n_draws", "<i4"), ("region", "<i4"), ("pad", "<i4")])
+                         ("n_draws", "<i4"), ("region", "<i4"), ("tof", "<f4")])
 assert RECORD_DTYPE.itemsize == 96
 
 

@@ -19,6 +19,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libprompt_mi355x.so")
 
 PR_OK = 0
+PR_EWORKSPACE = -4
+PR_ECAPPED = -7
 PR_FP64_PLAIN, PR_FP32_MIXED, PR_FP64_PERSISTENT = 0, 1, 2
 PRECISION = {"fp64": PR_FP64_PLAIN, "fp64_plain": PR_FP64_PLAIN, "fp32": PR_FP32_MIXED, "fp32_mixed": PR_FP32_MIXED,
              "fp64_persistent": PR_FP64_PERSISTENT}
@@ -26,7 +28,7 @@ PRECISION = {"fp64": PR_FP64_PLAIN, "fp64_plain": PR_FP64_PLAIN, "fp32": PR_FP32
 SOLID = {"box": 0, "cylinder": 1, "cyl_shell": 2, "sphere": 3, "sph_shell": 4}
 SOURCE = {"pencil": 0, "rect": 1, "rect_divergent": 2, "moderator": 3}
 SPECTRUM = {"mono": 0, "uniform": 1, "maxwell": 2}
-TRIGGER = {"escape": 0, "absorb": 1, "detect": 2}
+TRIGGER = {"escape": 0, "absorb": 1, "detect": 2, "first_collision": 3}
 FILTER = {"all": 0, "unscattered": 1, "scattered": 2, "nscat_eq": 3}
 QUANTITY = {"theta2": 0, "lambda": 1, "x": 2, "y": 3, "z": 4, "div_x": 5, "div_y": 6, "nscat": 7, "q": 8, "tof": 9}
 MIRROR = {"linear": 0, "tanh": 1}
@@ -37,14 +39,14 @@ END_ESCAPE, END_ABSORB, END_KILL, END_DETECT, END_CAPPED, END_OUTSIDE = 1, 2, 3,
 # pr_history_record (96 bytes)
 RECORD_DTYPE = np.dtype([("hash", "<u8"), ("w", "<f8"), ("pos", "<f8", 3), ("dir", "<f8", 3),
                          ("lambda", "<f8"), ("term", "<i4"), ("n_scat", "<i4"), ("n_steps", "<i4"),
-                         ("n_draws", "<i4"), ("region", "<i4"), ("pad", "<i4")])
+                         ("n_draws", "<i4"), ("region", "<i4"), ("tof", "<f4")])
 RECORD_BYTES = 96
 
 EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_material", "pr_create_geometry",
-           "pr_create_source", "pr_create_tally", "pr_tally_nbins", "pr_run_histories", "pr_read_tally",
-           "pr_read_tally_range", "pr_reset_tally", "pr_read_stats", "pr_reset_stats", "pr_set_tuning",
-           "pr_get_tuning", "pr_run_batch", "pr_autotune", "pr_prepare_batch", "pr_run_prepared",
-           "pr_release_batch"]
+           "pr_create_source", "pr_create_tally", "pr_tally_storage_size", "pr_create_tally_in", "pr_tally_nbins",
+           "pr_workspace_size", "pr_run_histories", "pr_read_tally", "pr_read_tally_range", "pr_reset_tally",
+           "pr_read_stats", "pr_reset_stats", "pr_set_tuning", "pr_get_tuning", "pr_run_batch", "pr_autotune",
+           "pr_prepare_batch", "pr_run_prepared", "pr_release_batch"]
 
 
 class pr_material_desc(C.Structure):
@@ -128,8 +130,11 @@ def load():
     L.pr_create_geometry.argtypes = [vp, C.POINTER(pr_volume_desc), i32, C.POINTER(i32)]
     L.pr_create_source.argtypes = [vp, C.POINTER(pr_source_desc), C.POINTER(i32)]
     L.pr_create_tally.argtypes = [vp, C.POINTER(pr_tally_desc), C.POINTER(i32)]
+    L.pr_tally_storage_size.argtypes = [vp, C.POINTER(pr_tally_desc), C.POINTER(C.c_size_t)]
+    L.pr_create_tally_in.argtypes = [vp, C.POINTER(pr_tally_desc), vp, C.c_size_t, C.POINTER(i32)]
     L.pr_tally_nbins.argtypes = [vp, i32, C.POINTER(u64)]
-    L.pr_run_histories.argtypes = [vp, i32, i32, C.POINTER(i32), i32, u64, u64, i32, vp, vp]
+    L.pr_workspace_size.argtypes = [vp, i32, C.POINTER(C.c_size_t)]
+    L.pr_run_histories.argtypes = [vp, i32, i32, C.POINTER(i32), i32, u64, u64, i32, vp, vp, C.c_size_t, vp]
     L.pr_read_tally.argtypes = [vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(u64), C.c_size_t, vp]
     L.pr_read_tally_range.argtypes = [vp, i32, u64, u64, C.POINTER(C.c_double), C.POINTER(C.c_double), vp]
     L.pr_reset_tally.argtypes = [vp, i32, vp]
@@ -280,11 +285,30 @@ class Context:
         self._check(self.lib.pr_create_source(self.h, C.byref(d), C.byref(i)))
         return i.value
 
-    def create_tally(self, t: W.Tally) -> int:
+    def create_tally(self, t: W.Tally, storage=None) -> int:
+        """storage: None (the library allocates), or a caller-owned CUDA tensor of at
+        least tally_storage_size(t) bytes that holds the tally's (sum w, sum w^2) pairs."""
         d = tally_desc(t)
         i = C.c_int32()
-        self._check(self.lib.pr_create_tally(self.h, C.byref(d), C.byref(i)))
+        if storage is None:
+            self._check(self.lib.pr_create_tally(self.h, C.byref(d), C.byref(i)))
+        else:
+            nbytes = storage.numel() * storage.element_size()
+            self._check(self.lib.pr_create_tally_in(self.h, C.byref(d), C.c_void_p(storage.data_ptr()), nbytes,
+                                                    C.byref(i)))
         return i.value
+
+    def tally_storage_size(self, t: W.Tally) -> int:
+        d = tally_desc(t)
+        n = C.c_size_t()
+        self._check(self.lib.pr_tally_storage_size(self.h, C.byref(d), C.byref(n)))
+        return n.value
+
+    def workspace_size(self, precision="fp32") -> int:
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        n = C.c_size_t()
+        self._check(self.lib.pr_workspace_size(self.h, prec, C.byref(n)))
+        return n.value
 
     def tally_nbins(self, t: int) -> int:
         n = C.c_uint64()
@@ -292,12 +316,17 @@ class Context:
         return n.value
 
     def run(self, geom: int, src: int, tallies: Sequence[int], first: int, n: int, precision="fp64",
-            records_ptr: Optional[int] = None, stream=None):
+            records_ptr: Optional[int] = None, stream=None, workspace=None):
+        """workspace: None (a slot of the context's counter ring) or a caller-owned
+        CUDA tensor of at least workspace_size() bytes."""
         ts = (C.c_int32 * max(1, len(tallies)))(*tallies)
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         st = _current_stream() if stream is None else C.c_void_p(stream)
+        ws, wsb = None, 0
+        if workspace is not None:
+            ws, wsb = C.c_void_p(workspace.data_ptr()), workspace.numel() * workspace.element_size()
         self._check(self.lib.pr_run_histories(self.h, geom, src, ts, len(tallies), first, n, prec,
-                                              C.c_void_p(records_ptr) if records_ptr else None, st))
+                                              C.c_void_p(records_ptr) if records_ptr else None, ws, wsb, st))
 
     def read_tally(self, t: int, stream=None):
         nb = self.tally_nbins(t)
@@ -322,9 +351,13 @@ class Context:
         self._check(self.lib.pr_reset_tally(self.h, t, st))
 
     def read_stats(self, stream=None) -> dict:
+        """Run statistics since the last reset (PR_ECAPPED, returned when some history
+        reached the step cap, is not an error here: out["capped"] says so)."""
         s = pr_run_stats()
         st = _current_stream() if stream is None else C.c_void_p(stream)
-        self._check(self.lib.pr_read_stats(self.h, C.byref(s), st))
+        rc = self.lib.pr_read_stats(self.h, C.byref(s), st)
+        if rc != PR_ECAPPED:
+            self._check(rc)
         return {name: getattr(s, name) for name, _ in pr_run_stats._fields_}
 
     @staticmethod
@@ -394,8 +427,10 @@ class Simulation:
         self.src = ctx.create_source(prob.source)
         self.tallies = [ctx.create_tally(t) for t in prob.tallies]
 
-    def run(self, first: int = 0, n: Optional[int] = None, precision="fp64", records=None, stream=None):
-        """records: None or a torch uint8 CUDA tensor of n * 96 bytes."""
+    def run(self, first: int = 0, n: Optional[int] = None, precision="fp64", records=None, stream=None,
+            workspace=None):
+        """records: None or a torch uint8 CUDA tensor of n * 96 bytes; workspace: None or
+        a caller-owned CUDA tensor of Context.workspace_size() bytes."""
         if n is None:
             n = self.prob.n_histories
         ptr = None
@@ -403,7 +438,7 @@ class Simulation:
             if records.numel() < n * RECORD_BYTES or not records.is_cuda:
                 raise ValueError("records must be a CUDA uint8 tensor of n * 96 bytes")
             ptr = records.data_ptr()
-        self.ctx.run(self.geom, self.src, self.tallies, first, n, precision, ptr, stream)
+        self.ctx.run(self.geom, self.src, self.tallies, first, n, precision, ptr, stream, workspace)
 
     def reset(self):
         for t in self.tallies:

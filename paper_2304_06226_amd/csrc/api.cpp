@@ -66,6 +66,7 @@ struct Tally {
     pr_tally_desc desc;
     uint64_t nbins = 0;
     double* dev = nullptr;   // (sum_w, sum_w2) interleaved per bin
+    bool owned = true;       // false: the caller's storage (pr_create_tally_in), never freed here
     uint64_t n_hist = 0;     // histories of host-issued runs
     unsigned long long* dev_nhist = nullptr;   // histories counted on the device (prepared batches)
 };
@@ -106,6 +107,13 @@ struct PreparedBatch {
     int nh = 0;
 };
 
+// History-claim counters of runs without a caller workspace: a ring of slots,
+// each reused only after the stream of its next run has waited for the event
+// recorded behind the last run that used it, so runs on different streams never
+// share a counter while they overlap.
+constexpr int kRunSlots = 64;
+constexpr size_t kRunSlotBytes = 256;   // one counter per slot, slots 256 bytes apart
+
 struct pr_ctx {
     int device = -1;
     uint64_t seed = 4096;
@@ -115,7 +123,10 @@ struct pr_ctx {
     std::vector<pr_source_desc> srcs;
     std::vector<Tally> tallies;
     unsigned long long* stats = nullptr;
-    unsigned long long* counter = nullptr;
+    char* run_slots = nullptr;              // kRunSlots x kRunSlotBytes of device memory
+    hipEvent_t run_done[kRunSlots] = {};
+    bool run_used[kRunSlots] = {};
+    int next_run_slot = 0;
     int num_cus = 256;
     // launch tuning of the mixed policy
     int mixed_block = 256;
@@ -431,10 +442,17 @@ extern "C" int pr_init(pr_ctx** out, int hip_device, uint64_t seed) {
             delete c;
             return PR_EDEVICE;
         }
-        if (hipSetDevice(hip_device) != hipSuccess ||
-            hipMalloc((void**)&c->stats, ST_N * sizeof(unsigned long long)) != hipSuccess ||
-            hipMalloc((void**)&c->counter, 64) != hipSuccess ||
-            hipMemset(c->stats, 0, ST_N * sizeof(unsigned long long)) != hipSuccess) {
+        bool ok = hipSetDevice(hip_device) == hipSuccess &&
+                  hipMalloc((void**)&c->stats, ST_N * sizeof(unsigned long long)) == hipSuccess &&
+                  hipMalloc((void**)&c->run_slots, kRunSlots * kRunSlotBytes) == hipSuccess &&
+                  hipMemset(c->stats, 0, ST_N * sizeof(unsigned long long)) == hipSuccess;
+        for (int i = 0; ok && i < kRunSlots; ++i)
+            ok = hipEventCreateWithFlags(&c->run_done[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            for (int i = 0; i < kRunSlots; ++i)
+                if (c->run_done[i]) (void)hipEventDestroy(c->run_done[i]);
+            if (c->stats) (void)hipFree(c->stats);
+            if (c->run_slots) (void)hipFree(c->run_slots);
             delete c;
             return PR_EDEVICE;
         }
@@ -453,12 +471,14 @@ extern "C" void pr_destroy(pr_ctx* c) {
         (void)hipDeviceSynchronize();
         for (auto& g : c->geoms) free_geometry(g);
         for (auto& t : c->tallies) {
-            if (t.dev) (void)hipFree(t.dev);
+            if (t.dev && t.owned) (void)hipFree(t.dev);
             if (t.dev_nhist) (void)hipFree(t.dev_nhist);
         }
         for (auto& pb : c->prepared) free_prepared(pb);
         if (c->stats) (void)hipFree(c->stats);
-        if (c->counter) (void)hipFree(c->counter);
+        if (c->run_slots) (void)hipFree(c->run_slots);
+        for (int i = 0; i < kRunSlots; ++i)
+            if (c->run_done[i]) (void)hipEventDestroy(c->run_done[i]);
         if (c->scratch) (void)hipFree(c->scratch);
         if (c->scratch_stats) (void)hipFree(c->scratch_stats);
         for (auto& sl : c->slots) {
@@ -840,13 +860,15 @@ extern "C" int pr_create_source(pr_ctx* c, const pr_source_desc* d, int32_t* id)
 // tallies
 // =========================================================================
 
-extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
-    if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
-    if (d->trigger < PR_TRIG_ESCAPE || d->trigger > PR_TRIG_DETECT) return fail(c, PR_EINVAL, "tally.trigger invalid");
+// validates a tally description; *nbins receives its bin count
+static int check_tally_desc(pr_ctx* c, const pr_tally_desc* d, uint64_t* nbins) {
+    if (d->trigger < PR_TRIG_ESCAPE || d->trigger > PR_TRIG_FIRST_COLLISION)
+        return fail(c, PR_EINVAL, "tally.trigger invalid");
     if (d->filter < PR_FILT_ALL || d->filter > PR_FILT_NSCAT_EQ) return fail(c, PR_EINVAL, "tally.filter invalid");
     if (d->naxes < 0 || d->naxes > 4) return fail(c, PR_EINVAL, "tally.naxes must be in [0, 4]");
-    if (d->accumulator != PR_ACC_FP64 && d->accumulator != PR_ACC_KAHAN_FP32)
-        return fail(c, PR_EINVAL, "tally.accumulator invalid");
+    if (d->accumulator == PR_ACC_KAHAN_FP32)
+        return fail(c, PR_EINVAL, "tally.accumulator: PR_ACC_KAHAN_FP32 is not supported (tallies accumulate in FP64)");
+    if (d->accumulator != PR_ACC_FP64) return fail(c, PR_EINVAL, "tally.accumulator invalid");
     uint64_t nb = 1;
     for (int a = 0; a < d->naxes; ++a) {
         const pr_tally_axis& x = d->axes[a];
@@ -861,24 +883,63 @@ extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
     for (int a = 0; a < d->naxes; ++a)
         if ((d->axes[a].quantity == PR_Q_THETA2 || d->axes[a].quantity == PR_Q_Q) && !(bn > 0))
             return fail(c, PR_EINVAL, "tally.beam must be non-zero");
+    *nbins = nb;
+    return PR_OK;
+}
+
+extern "C" int pr_tally_storage_size(pr_ctx* c, const pr_tally_desc* d, size_t* bytes) {
+    if (!c || !d || !bytes) return fail(c, PR_EINVAL, "null argument");
+    uint64_t nb = 0;
+    int rc = check_tally_desc(c, d, &nb);
+    if (rc) return rc;
+    *bytes = (size_t)(2 * nb * sizeof(double));
+    return PR_OK;
+}
+
+// storage: the caller's device buffer, or nullptr to allocate it
+static int create_tally(pr_ctx* c, const pr_tally_desc* d, void* storage, size_t storage_bytes, int32_t* id) {
+    if (!c || !d || !id) return fail(c, PR_EINVAL, "null argument");
+    uint64_t nb = 0;
+    int rc = check_tally_desc(c, d, &nb);
+    if (rc) return rc;
     Tally t;
     t.desc = *d;
     t.nbins = nb;
+    if (storage) {
+        if (storage_bytes < 2 * nb * sizeof(double))
+            return fail(c, PR_EWORKSPACE, "tally storage holds %zu bytes, %llu needed", storage_bytes,
+                        (unsigned long long)(2 * nb * sizeof(double)));
+        if ((uintptr_t)storage % 16 != 0) return fail(c, PR_EINVAL, "tally storage must be 16-byte aligned");
+        if (c->device < 0) return fail(c, PR_EDEVICE, "caller tally storage needs a device context");
+    }
     if (c->device >= 0) {
-        int rc = set_device(c);
-        if (rc) return rc;
-        if (hipMalloc((void**)&t.dev, 2 * nb * sizeof(double)) != hipSuccess)
+        if ((rc = set_device(c))) return rc;
+        if (storage) {
+            t.dev = (double*)storage;
+            t.owned = false;
+        } else if (hipMalloc((void**)&t.dev, 2 * nb * sizeof(double)) != hipSuccess) {
             return fail(c, PR_ENOMEM, "cannot allocate %llu tally bins on the device", (unsigned long long)nb);
+        }
         hipError_t e = zero_f64(t.dev, 2 * nb, nullptr);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
-            (void)hipFree(t.dev);
+            if (t.owned) (void)hipFree(t.dev);
             return hipfail(c, e, "zeroing tally");
         }
     }
     c->tallies.push_back(t);
     *id = (int32_t)c->tallies.size() - 1;
     return PR_OK;
+}
+
+extern "C" int pr_create_tally(pr_ctx* c, const pr_tally_desc* d, int32_t* id) {
+    return create_tally(c, d, nullptr, 0, id);
+}
+
+extern "C" int pr_create_tally_in(pr_ctx* c, const pr_tally_desc* d, void* dev_storage, size_t storage_bytes,
+                                  int32_t* id) {
+    if (!dev_storage) return fail(c, PR_EINVAL, "dev_storage is null");
+    return create_tally(c, d, dev_storage, storage_bytes, id);
 }
 
 extern "C" int pr_tally_nbins(pr_ctx* c, int32_t tally, uint64_t* nbins) {
@@ -921,8 +982,12 @@ static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
     memset(&o, 0, sizeof(o));
     const pr_tally_desc& td = T.desc;
     TallyHead& h = o.head;
-    h.term_mask = td.trigger == PR_TRIG_ESCAPE ? 1u << PR_END_ESCAPE
-                  : td.trigger == PR_TRIG_ABSORB ? 1u << PR_END_ABSORB : 1u << PR_END_DETECT;
+    h.term_mask = td.trigger == PR_TRIG_ESCAPE   ? 1u << PR_END_ESCAPE
+                  : td.trigger == PR_TRIG_ABSORB ? 1u << PR_END_ABSORB
+                  : td.trigger == PR_TRIG_DETECT ? 1u << PR_END_DETECT
+                                                 : 1u << kTermFirstCollision;
+    h.fix_axis = -1;
+    h.fix_bin = 0;
     h.volume = td.trigger == PR_TRIG_DETECT && td.trigger_volume >= 0 ? td.trigger_volume + vol_offset : -1;
     const int32_t big = std::numeric_limits<int32_t>::max();
     h.nscat_lo = td.filter == PR_FILT_SCATTERED ? 1 : td.filter == PR_FILT_NSCAT_EQ ? td.filter_arg : 0;
@@ -948,6 +1013,7 @@ static void make_tally_dev(const Tally& T, int vol_offset, TallyDev& o) {
     o.sw = T.dev;
     o.sw2 = T.dev ? T.dev + 1 : nullptr;
     o.total = (int64_t)T.nbins;
+    o.lds_bins = 0;
     o.lds_offset = -1;
     o.cache_base = -1;
     o.cache_bits = 0;
@@ -975,6 +1041,20 @@ static int grid_block(const pr_ctx* c, Occ occupancy) {
         if (w > best_waves) { best = b; best_waves = w; }
     }
     return best;
+}
+
+// Bin of value x on axis A computed as the device computes it in precision R
+// (the FP32 range and scale are the axis's FP32 copies); -1 outside the axis.
+template <class R>
+static int axis_bin(const TallyAxis& A, R x) {
+    const R lo = sizeof(R) == 4 ? (R)A.lo_f : (R)A.lo, hi = sizeof(R) == 4 ? (R)A.hi_f : (R)A.hi;
+    const R scale = sizeof(R) == 4 ? (R)A.scale_f : (R)A.scale;
+    if (!(x >= lo && x <= hi)) return -1;
+    const R prod = (x - lo) * scale;
+    int b = (int)std::floor((double)prod);
+    if (x == hi || b >= A.nbins) b = A.nbins - 1;
+    if (b < 0) b = 0;
+    return b;
 }
 
 static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
@@ -1018,6 +1098,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n_tallies = nt;
     int lds_doubles = 0;
     const int budget = precision != PR_FP64_PLAIN ? c->lds_tally_budget / 8 : 0;
+    const pr_source_desc& sdesc = c->srcs[src];
     for (int i = 0; i < nt; ++i) {
         int t = tallies[i];
         if (t < 0 || t >= (int)c->tallies.size()) return fail(c, PR_ENOTFOUND, "tally %d unknown", t);
@@ -1027,12 +1108,35 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         const pr_tally_desc& td = T.desc;
         if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= g.nv)
             return fail(c, PR_EINVAL, "tally %d: trigger_volume beyond the geometry", t);
+        if (td.trigger == PR_TRIG_FIRST_COLLISION) {
+            if (precision == PR_FP32_MIXED)
+                return fail(c, PR_EINVAL, "tally %d: first-collision tallies run with the FP64 policies only", t);
+            P.has_fc = 1;
+        }
         TallyDev& o = P.tallies[i];
         make_tally_dev(T, 0, o);
         P.qmask |= tally_qmask(td);
-        if ((int64_t)lds_doubles + 2 * (int64_t)T.nbins <= budget) {
+        // Privatise the whole tally when it fits the block's LDS budget; else, under
+        // a monochromatic source (elastic physics keeps lambda), the slice at the
+        // source wavelength's bin of a wavelength axis, when that fits.
+        int64_t bins = (int64_t)T.nbins;
+        if ((int64_t)lds_doubles + 2 * bins > budget && sdesc.spectrum == PR_MONO) {
+            for (int a = 0; a < td.naxes && o.head.fix_axis < 0; ++a) {
+                if (td.axes[a].quantity != PR_Q_LAMBDA) continue;
+                const int b = precision == PR_FP32_MIXED ? axis_bin<float>(o.ax[a], (float)sdesc.lam0)
+                                                         : axis_bin<double>(o.ax[a], sdesc.lam0);
+                const int64_t slice = bins / td.axes[a].nbins;
+                if (b >= 0 && (int64_t)lds_doubles + 2 * slice <= budget) {
+                    o.head.fix_axis = a;
+                    o.head.fix_bin = b;
+                    bins = slice;
+                }
+            }
+        }
+        if ((int64_t)lds_doubles + 2 * bins <= budget) {
             o.lds_offset = lds_doubles;
-            lds_doubles += 2 * (int)T.nbins;
+            o.lds_bins = (int32_t)bins;
+            lds_doubles += 2 * (int)bins;
         }
     }
     // tallies too large to privatise get an LDS bin cache (persistent policies)
@@ -1060,7 +1164,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.n = n;
     P.records = (pr_history_record*)records;
     P.stats = c->stats;
-    P.counter = c->counter;
+    P.counter = nullptr;   // set by the caller: a run slot or the caller's workspace
     P.refill_threshold = c->refill_threshold;
     P.chunk = P.has_grid && c->grid_chunk > 0 ? c->grid_chunk : c->chunk;
     P.waves = c->waves_per_simd;
@@ -1068,12 +1172,21 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
 }
 
 // Launch one history range.  trial: autotuner run scoring into scratch.
+// workspace: the caller's device workspace (pr_workspace_size bytes) holding
+// the run's history-claim counter, or nullptr to take a slot of the context's
+// ring (the stream then waits for the last run that used the slot).
 static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt, uint64_t first,
-                      uint64_t n, int32_t precision, void* records, hipStream_t st, bool trial) {
+                      uint64_t n, int32_t precision, void* records, void* workspace, size_t ws_bytes, hipStream_t st,
+                      bool trial) {
     Params P;
     int rc = build_params(c, geom, src, tallies, nt, first, n, precision, records, P);
     if (rc) return rc;
     if ((rc = set_device(c))) return rc;
+    if (workspace) {
+        if (ws_bytes < kRunSlotBytes)
+            return fail(c, PR_EWORKSPACE, "workspace holds %zu bytes, %zu needed", ws_bytes, kRunSlotBytes);
+        if ((uintptr_t)workspace % 8 != 0) return fail(c, PR_EINVAL, "workspace must be 8-byte aligned");
+    }
     if (trial) {
         for (int i = 0; i < nt; ++i) {
             P.tallies[i].sw = c->scratch;
@@ -1081,6 +1194,7 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
         }
         P.stats = c->scratch_stats;
     }
+    if (n == 0) return PR_OK;
     hipError_t e;
     if (precision == PR_FP64_PLAIN) {
         e = launch_plain(P, records != nullptr, st);
@@ -1094,16 +1208,39 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
         uint64_t want = (n + block - 1) / block;
         uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, want);
         if (grid < 1) grid = 1;
+        int slot = -1;
+        if (workspace) {
+            P.counter = (unsigned long long*)workspace;
+        } else {
+            slot = c->next_run_slot;
+            c->next_run_slot = (slot + 1) % kRunSlots;
+            if (c->run_used[slot]) HIPCHK(c, hipStreamWaitEvent(st, c->run_done[slot], 0));
+            P.counter = (unsigned long long*)(c->run_slots + slot * kRunSlotBytes);
+        }
         e = launch_mixed(P, records != nullptr, (int)grid, block, st);
+        if (e == hipSuccess && slot >= 0) {
+            e = hipEventRecord(c->run_done[slot], st);
+            if (e == hipSuccess) c->run_used[slot] = true;
+        }
     }
     if (e != hipSuccess) return hipfail(c, e, "kernel launch");
     return PR_OK;
 }
 
+extern "C" int pr_workspace_size(pr_ctx* c, int32_t precision, size_t* bytes) {
+    if (!c || !bytes) return fail(c, PR_EINVAL, "null argument");
+    if (precision != PR_FP64_PLAIN && precision != PR_FP32_MIXED && precision != PR_FP64_PERSISTENT)
+        return fail(c, PR_EINVAL, "precision invalid");
+    *bytes = kRunSlotBytes;
+    return PR_OK;
+}
+
 extern "C" int pr_run_histories(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tallies, int32_t nt,
-                                uint64_t first, uint64_t n, int32_t precision, void* records, void* stream) {
+                                uint64_t first, uint64_t n, int32_t precision, void* records, void* workspace,
+                                size_t ws_bytes, void* stream) {
     if (!c) return PR_EINVAL;
-    int rc = run_single(c, geom, src, tallies, nt, first, n, precision, records, (hipStream_t)stream, false);
+    int rc = run_single(c, geom, src, tallies, nt, first, n, precision, records, workspace, ws_bytes,
+                        (hipStream_t)stream, false);
     if (rc) return rc;
     for (int i = 0; i < nt; ++i) c->tallies[tallies[i]].n_hist += n;
     return PR_OK;
@@ -1193,6 +1330,9 @@ extern "C" int pr_read_stats(pr_ctx* c, pr_run_stats* out, void* stream) {
     out->steps = h[ST_STEPS];
     out->draws = h[ST_DRAWS];
     out->scatters = h[ST_SCAT];
+    if (out->capped > 0)
+        return fail(c, PR_ECAPPED, "%llu histories reached the step cap (%d); they are counted and scored as ended",
+                    (unsigned long long)out->capped, PR_MAX_STEPS);
     return PR_OK;
 }
 
@@ -1425,6 +1565,8 @@ static int validate_sims(pr_ctx* c, const pr_sim* sims, int32_t nsims) {
             const pr_tally_desc& td = c->tallies[tid].desc;
             if (td.trigger == PR_TRIG_DETECT && td.trigger_volume >= c->geoms[sm.geom].nv)
                 return fail(c, PR_EINVAL, "sims[%d]: tally %d trigger_volume beyond its geometry", i, tid);
+            if (td.trigger == PR_TRIG_FIRST_COLLISION)
+                return fail(c, PR_EINVAL, "sims[%d]: first-collision tallies run with the FP64 policies only", i);
         }
     }
     return PR_OK;
@@ -1597,7 +1739,7 @@ static int trial_ms(pr_ctx* c, const std::vector<pr_sim>& sample, bool batched, 
         } else {
             const pr_sim& s = sample[0];
             rc = run_single(c, s.geom, s.src, s.tallies, s.n_tallies, s.first_history, s.n, PR_FP32_MIXED, nullptr,
-                            st, true);
+                            nullptr, 0, st, true);
         }
         if (rc) return rc;
         HIPCHK(c, hipEventRecord(e1, st));

@@ -155,13 +155,20 @@ __device__ __forceinline__ void axis_range<float>(const TallyAxis& A, float& lo,
 // Which finished histories a tally takes, in a form one scalar load brings in:
 // its trigger as a set of termination codes (plus the detector volume for a
 // detection trigger) and its scattering-count filter as an inclusive range.
+// Termination code under which first-collision tallies fire (the history is
+// still alive then; codes 1..6 are the PR_END_* values).
+constexpr int kTermFirstCollision = 7;
+
 struct TallyHead {
-    uint32_t term_mask;           // bit per PR_END_* code that triggers the tally
+    uint32_t term_mask;           // bit per termination code that triggers the tally (kTermFirstCollision included)
     int32_t volume;               // detection trigger: required final region (-1: any)
     int32_t nscat_lo, nscat_hi;   // scattering-count filter
     int32_t naxes;
     uint32_t qmask;               // quantities its axes bin (bit per PR_Q_* value)
-    int32_t pad[2];
+    // The privatised copy may hold only the slice of bins whose axis fix_axis has
+    // bin fix_bin (a wavelength axis under a monochromatic source: every score
+    // lands there); scores outside the slice go to global memory.  -1: whole tally.
+    int32_t fix_axis, fix_bin;
 };
 
 struct TallyDev {
@@ -169,7 +176,7 @@ struct TallyDev {
     int32_t lds_offset;   // privatised copy in LDS (offset in doubles), -1 = none
     int32_t cache_base;   // first slot of this tally's LDS bin cache, -1 = none
     int32_t cache_bits;   // log2 of its slot count
-    int32_t pad;
+    int32_t lds_bins;     // bins of the privatised copy (the whole tally, or the slice)
     float beam_f[4];      // the beam direction rounded to FP32 (the FP32 policy's copy)
     TallyAxis ax[4];
     double beam[3];                  // unit vector
@@ -214,6 +221,7 @@ struct Params {
     int32_t refill_threshold;      // persistent policy: refill once this many lanes of a wave are idle
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
     int32_t waves;                 // FP32 persistent policy: waves per SIMD the launched variant is built for (4 or 5)
+    int32_t has_fc;                // some tally of the run fires at the first collision
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)
@@ -364,6 +372,9 @@ struct PState {
     int32_t xs_mat, nact;
     R sa, si, sc, sig, sig_g, ga, gs, cl;
     R t;   // time since emission, s
+    // FP32: the daughter just left by a move shorter than the sliver length (see
+    // sliver_tol), not to be re-entered through a piece that short; -1: none
+    int32_t skip;
 };
 
 // FP64 draws: the block of draw k is computed when k is even, its second word
@@ -566,13 +577,16 @@ __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int 
     P.n = (lo ? 1 : 0) + (hi ? 1 : 0);
 }
 
-// pieces of the ray q + t u (q relative to the centre) inside a box of half sides h
-// Shortest piece a history enters.  In FP32 a piece only a few ulps of the
-// position long (a ray grazing an edge or touching a curved surface) can be
-// crossed without the position changing at all; the next step would then find
-// the same piece ahead and re-enter it, for ever.  Pieces shorter than about
-// eight ulps of the largest coordinate are therefore passed by in FP32 (the
-// material skipped is under 1e-6 of the coordinate).  FP64 enters every piece.
+// Sliver length of the FP32 policy: about eight ulps of the largest coordinate.
+// A move shorter than this may leave an FP32 position unchanged.  A ray grazing
+// an edge or touching a curved surface can cut a daughter piece that short: the
+// history enters the daughter, finds its exit at distance ~0, returns to the
+// mother without having moved, and would find the same piece ahead again, for
+// ever.  So when a history leaves a daughter by a move shorter than the sliver
+// length, that daughter (PState::skip) is not re-entered in the next step through
+// a piece shorter than the sliver length.  Every other piece is entered as in
+// FP64, however thin (a 1 um chopper disk far from the origin included).  FP64
+// needs no such rule.
 template <class R>
 __device__ __forceinline__ R sliver_tol(const R p[3]) {
     if constexpr (sizeof(R) == 4)
@@ -581,12 +595,14 @@ __device__ __forceinline__ R sliver_tol(const R p[3]) {
         return (R)0;
 }
 
-// distance to where the ray enters a daughter's first piece ahead (rinf: none)
+// distance to where the ray enters a daughter's first piece ahead (rinf: none);
+// skipped: the daughter is the one just left without progress (FP32)
 template <class R>
-__device__ __forceinline__ R entry_distance(const Pieces<R>& P, R tol) {
+__device__ __forceinline__ R entry_distance(const Pieces<R>& P, R tol, bool skipped) {
     if constexpr (sizeof(R) == 4) {
-        if (P.n > 0 && P.a0 > (R)0 && P.b0 - P.a0 > tol) return P.a0;
-        if (P.n > 1 && P.a1 > (R)0 && P.b1 - P.a1 > tol) return P.a1;
+        const R min_len = skipped ? tol : (R)0;
+        if (P.n > 0 && P.a0 > (R)0 && P.b0 - P.a0 > min_len) return P.a0;
+        if (P.n > 1 && P.a1 > (R)0 && P.b1 - P.a1 > min_len) return P.a1;
         return rinf<R>();
     } else {
         if (P.n > 0 && P.a0 > (R)0) return P.a0;
@@ -824,6 +840,7 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     s.nscat = 0;
     s.steps = 0;
     s.term = 0;
+    s.skip = -1;
     s.hash = 14695981039346656037ull;
     R p[3] = {(R)src.o[0], (R)src.o[1], (R)src.o[2]};
     R u[3] = {(R)src.u[0], (R)src.u[1], (R)src.u[2]};
@@ -944,7 +961,7 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
 
 template <class R>
 __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>& G, const R p[3], const R u[3], R tmax,
-                                             R tol, R& d_child, int& child, int& child_det) {
+                                             R tol, int skip, R& d_child, int& child, int& child_det) {
     R t0 = (R)0, t1 = tmax;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -988,7 +1005,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
             const uint32_t item = (uint32_t)S.cell_items[j];
             Pieces<R> Q;
             item_pieces<R>(S, item, p, u, Q);
-            const R a = entry_distance<R>(Q, tol);
+            const R a = entry_distance<R>(Q, tol, (int)(item & kItemVol) == skip);
             if (a < d_child) {
                 d_child = a;
                 child = (int)(item & kItemVol);
@@ -1032,7 +1049,7 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
                 if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
                 if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
             } else {
-                const R a = entry_distance<R>(P, tol);
+                const R a = entry_distance<R>(P, tol, vid == s.skip);
                 if (a < d_child || (a == d_child && a != rinf<R>() && i < child_item)) {
                     d_child = a;
                     child = vid;
@@ -1045,12 +1062,14 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
 }
 
 
+// One step; returns true when the step was the history's first collision
+// (absorption or scattering), the event of first-collision tallies.
 template <class R, bool REC, bool GRID>
-__device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
+__device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
     if (s.steps >= kMaxSteps) {
         s.term = PR_END_CAPPED;
         hash_ev<REC>(s.hash, EV_CAPPED, 0);
-        return;
+        return false;
     }
     s.steps++;
     const VolT<R>& V = S.vols[s.region];
@@ -1069,7 +1088,8 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
     scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, tol, d_child, child, child_item, child_det);
     scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
-    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, tol, d_child, child, child_det);
+    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, tol, s.skip, d_child, child, child_det);
+    if constexpr (sizeof(R) == 4) s.skip = -1;
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
 
@@ -1101,7 +1121,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
             s.w *= S.mats[s.xs_mat].inv_ga;
             s.term = PR_END_ABSORB;
             hash_ev<REC>(s.hash, EV_ABS, 0);
-            return;
+            return s.nscat == 0;
         }
         s.w *= S.mats[s.xs_mat].inv_gs;
         bool inc = r < wa + wi || wc == (R)0 || s.nact == 0;
@@ -1150,7 +1170,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
         s.u[1] = nu[1];
         s.u[2] = nu[2];
         s.nscat++;
-        return;
+        return s.nscat == 1;
     }
 
     if (to_child) {
@@ -1168,7 +1188,7 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
                 hash_ev<REC>(s.hash, EV_KILL, 0);
             }
         }
-        return;
+        return false;
     }
     if (face >= 0 && ((V.mirror_mask >> face) & 1)) {
         R n[3];
@@ -1184,15 +1204,17 @@ __device__ __forceinline__ void step(PState<R>& s, const SceneT<R>& S, uint64_t 
             s.term = PR_END_KILL;
             hash_ev<REC>(s.hash, EV_KILL, 0);
         }
-        return;
+        return false;
     }
     if (V.parent < 0) {   // leaving a world volume
         s.term = PR_END_ESCAPE;
         hash_ev<REC>(s.hash, EV_ESCAPE, 0);
-        return;
+        return false;
     }
+    if constexpr (sizeof(R) == 4) s.skip = x < tol ? s.region : -1;
     s.region = V.parent;
     hash_ev<REC>(s.hash, EV_EXIT, s.region);
+    return false;
 }
 
 // -------------------------------------------------------------------------
@@ -1222,21 +1244,31 @@ __device__ __forceinline__ double beam_component<double>(const TallyDev& T, int 
 template <>
 __device__ __forceinline__ float beam_component<float>(const TallyDev& T, int k) { return T.beam_f[k]; }
 
-// q: the history's divergence angles, computed once for all tallies (PRE), or
-// left to each divergence axis to compute (fewer values live across the loop)
+// Bin of a score: flat index over all axes (-1: not scored) and the index in the
+// tally's privatised slice (-1: outside it; the flat index when the whole tally
+// is privatised).
+struct Bin {
+    int64_t flat, slice;
+};
+
+// term: the history's termination code, or kTermFirstCollision at its first
+// collision.  q: the history's divergence angles, computed once for all tallies
+// (PRE), or left to each divergence axis to compute (fewer values live across
+// the loop).
 template <class R, bool PRE = true>
-__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s, const HistAngles<R>& q) {
+__device__ __forceinline__ Bin tally_bin(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
     const TallyHead h = T.head;
-    if (!(((h.term_mask >> s.term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
+    if (!(((h.term_mask >> term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
           (h.volume < 0 || h.volume == s.region)))
-        return -1;
+        return Bin{-1, -1};
     // cosine of the angle to the beam, for the 2-theta and momentum-transfer axes
     R c = (R)0;
     if (h.qmask & ((1u << PR_Q_THETA2) | (1u << PR_Q_Q))) {
         c = s.u[0] * beam_component<R>(T, 0) + s.u[1] * beam_component<R>(T, 1) + s.u[2] * beam_component<R>(T, 2);
         c = c > (R)1 ? (R)1 : (c < (R)-1 ? (R)-1 : c);
     }
-    int64_t flat = 0;
+    int64_t flat = 0, slice = 0;
+    bool in_slice = true;
     for (int a = 0; a < h.naxes; ++a) {
         const TallyAxis& A = T.ax[a];
         const int32_t quantity = A.quantity, n = A.nbins;
@@ -1258,13 +1290,25 @@ __device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>&
             break;
         default: x = (R)s.nscat; break;
         }
-        if (!(x >= lo && x <= hi)) return -1;
+        if (!(x >= lo && x <= hi)) return Bin{-1, -1};
         int b = (int)__builtin_floor((double)((x - lo) * scale));
         if (x == hi || b >= n) b = n - 1;
         if (b < 0) b = 0;
         flat = flat * n + b;
+        if (a == h.fix_axis) in_slice = b == h.fix_bin;
+        else slice = slice * n + b;
     }
-    return flat;
+    return Bin{flat, in_slice ? slice : -1};
+}
+
+// flat index of bin i of a tally's slice (inverse of the slice index)
+__device__ __forceinline__ int64_t slice_to_flat(const TallyDev& T, int64_t i) {
+    const int k = T.head.fix_axis;
+    if (k < 0) return i;
+    int64_t stride = 1;   // bins of the axes after k
+    for (int a = k + 1; a < T.head.naxes; ++a) stride *= T.ax[a].nbins;
+    const int64_t hi = i / stride, lo = i - hi * stride;
+    return (hi * T.ax[k].nbins + T.head.fix_bin) * stride + lo;
 }
 
 template <class R>
@@ -1281,7 +1325,7 @@ __device__ __forceinline__ void write_record(pr_history_record* rec, const PStat
     rec->n_steps = s.steps;
     rec->n_draws = (int32_t)s.k;
     rec->region = s.region;
-    rec->pad = 0;
+    rec->tof = (float)s.t;
 }
 
 }  // namespace prk

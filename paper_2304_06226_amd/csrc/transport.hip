@@ -66,6 +66,34 @@ __device__ __forceinline__ void add_global(const TallyDev& T, int64_t b, double 
     atomicAdd(T.sw + 2 * b + 1, w2);
 }
 
+// Add the pair (v0, v1) to bin b of global pair storage sw for every lane with
+// `need` (SQUARE: v1 = v0^2, a score); called by a converged wave.  Lanes 2j and
+// 2j+1 of one atomic instruction carry the two words of lane j's pair (then of
+// lane 32 + j), so the two FP64 atomics of a pair leave the wave as one request
+// on one 16-byte pair instead of two requests from two instructions.  Halves of
+// the wave without a pair are skipped.
+template <bool SQUARE>
+__device__ __forceinline__ void add_pairs_wave(double* sw, int64_t b, double v0, double v1, bool need) {
+    const unsigned long long m = __ballot(need);
+    if (m == 0ull) return;
+    const int lane = lane_id();
+    const int odd = lane & 1;
+#pragma unroll 1
+    for (int r = 0; r < 2; ++r) {
+        if (((m >> (32 * r)) & 0xFFFFFFFFull) == 0ull) continue;
+        const int src = 32 * r + (lane >> 1);
+        const long long bs = __shfl((long long)b, src, kWave);
+        const double a = __shfl(v0, src, kWave);
+        const double c = SQUARE ? a * a : __shfl(v1, src, kWave);
+        if ((m >> src) & 1ull) atomicAdd(sw + 2 * bs + odd, odd ? c : a);
+    }
+}
+
+// a score w (adds w and w^2) from every lane with `need`, converged wave
+__device__ __forceinline__ void add_global_wave(double* sw, int64_t b, double w, bool need) {
+    add_pairs_wave<true>(sw, b, w, 0.0, need);
+}
+
 // ------------------------------------------------------------------------
 // FP64 plain
 // ------------------------------------------------------------------------
@@ -73,30 +101,50 @@ __device__ __forceinline__ void add_global(const TallyDev& T, int64_t b, double 
 // The grid variant is held to three waves per SIMD (168 VGPRs): its grid walk
 // is latency-bound, and the third wave hides more of it (1000-box imaging
 // 48.9 -> 38.3 ms); the other variants run two, as they would anyway.
+// One thread per history; the grid strides over history indices when the run
+// has more histories than the launch has threads.
 template <bool REC, bool GRID>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 2, 8))) void k_plain(Params P) {
     const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.boxes_d,
                            P.kinds};
     Counters cnt = {};
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < P.n) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < P.n; base += stride) {
+        const uint64_t i = base + threadIdx.x;
+        const bool live = i < P.n;
         PState<double> s;
         s.xs_mat = -2;
         s.lam = -1.0;
-        source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
-        while (s.term == 0) step<double, REC, GRID>(s, S, P.seed);
-        if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
-            const HistAngles<double> q = hist_angles<double>(s, P.qmask);
-            for (int t = 0; t < P.n_tallies; ++t) {
-                const TallyDev& T = P.tallies[t];
-                int64_t b = tally_bin<double>(T, s, q);
-                if (b >= 0) {
-                    add_global(T, b, s.w, s.w * s.w);
+        s.term = PR_END_OUTSIDE;
+        s.nscat = 0;
+        if (live) {
+            source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
+            while (s.term == 0) {
+                const bool first = step<double, REC, GRID>(s, S, P.seed);
+                if (P.has_fc && first) {
+                    // first-collision tallies score the state just after the collision
+                    const HistAngles<double> q = hist_angles<double>(s, P.qmask);
+                    for (int t = 0; t < P.n_tallies; ++t) {
+                        const Bin b = tally_bin<double>(P.tallies[t], s, kTermFirstCollision, q);
+                        if (b.flat >= 0) add_global(P.tallies[t], b.flat, s.w, s.w * s.w);
+                    }
                 }
             }
         }
-        if (REC) write_record<double>(P.records + i, s);
-        count_end<double>(cnt, s);
+        // scoring with the whole wave converged (paired-lane global atomics)
+        const bool scoring = live && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
+        if (__ballot(scoring) != 0ull) {
+            const HistAngles<double> q = hist_angles<double>(s, P.qmask);
+            for (int t = 0; t < P.n_tallies; ++t) {
+                const TallyDev& T = P.tallies[t];
+                const Bin b = scoring ? tally_bin<double>(T, s, s.term, q) : Bin{-1, -1};
+                add_global_wave(T.sw, b.flat, s.w, b.flat >= 0);
+            }
+        }
+        if (live) {
+            if (REC) write_record<double>(P.records + i, s);
+            count_end<double>(cnt, s);
+        }
     }
     flush_counters(cnt, P.stats);
 }
@@ -147,18 +195,21 @@ __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
 
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 
-// Score w into bin b of tally T from a mixed-policy lane: the block's
-// privatised copy if there is one, else the block's LDS bin cache (a slot is
-// claimed by the first bin that hashes to it; two probes), else global atomics.
-__device__ __forceinline__ void score_mixed(const TallyDev& T, int64_t b, double w, double* lds, double* cvals,
-                                            uint32_t* ckeys) {
+// Score w into tally T from every lane of a converged wave whose bin is valid:
+// the block's privatised copy when the bin lies in it (the whole tally, or its
+// slice), else the block's LDS bin cache (a slot is claimed by the first bin
+// that hashes to it; two probes), else global memory.
+__device__ __forceinline__ void score_wave(const TallyDev& T, const Bin& b, double w, double* lds, double* cvals,
+                                           uint32_t* ckeys) {
+    bool global = b.flat >= 0;
     if (T.lds_offset >= 0) {
-        atomicAdd(lds + T.lds_offset + b, w);
-        atomicAdd(lds + T.lds_offset + T.total + b, w * w);
-        return;
-    }
-    if (T.cache_base >= 0 && b < (int64_t)kEmptyKey) {
-        const uint32_t key = (uint32_t)b;
+        if (b.slice >= 0) {
+            atomicAdd(lds + T.lds_offset + b.slice, w);
+            atomicAdd(lds + T.lds_offset + T.lds_bins + b.slice, w * w);
+            global = false;
+        }
+    } else if (T.cache_base >= 0 && global && b.flat < (int64_t)kEmptyKey) {
+        const uint32_t key = (uint32_t)b.flat;
         const uint32_t h = (key * 2654435761u) >> (32 - T.cache_bits);
         const uint32_t mask = (1u << T.cache_bits) - 1u;
 #pragma unroll
@@ -172,11 +223,25 @@ __device__ __forceinline__ void score_mixed(const TallyDev& T, int64_t b, double
             if (k == key) {
                 atomicAdd(cvals + 2 * slot, w);
                 atomicAdd(cvals + 2 * slot + 1, w * w);
-                return;
+                global = false;
+                break;
             }
         }
     }
-    add_global(T, b, w, w * w);
+    add_global_wave(T.sw, b.flat, w, global);
+}
+
+// Merge n_pairs (value, square) LDS sums a[i], a[n + i] into global pairs at
+// flat(i): the block walks the interleaved words, so consecutive lanes write
+// consecutive words of the destination pairs; zero words are skipped.
+template <class Flat>
+__device__ __forceinline__ void merge_pairs(double* sw, const double* a, int64_t n, Flat flat) {
+    for (int64_t j = threadIdx.x; j < 2 * n; j += blockDim.x) {
+        const int64_t i = j >> 1;
+        const int odd = (int)(j & 1);
+        const double v = a[odd * n + i];
+        if (v != 0.0) atomicAdd(sw + 2 * flat(i) + odd, v);
+    }
 }
 
 __device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes) {
@@ -265,18 +330,20 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
         const int n_idle = __popcll(idle_mask);
         if (n_idle >= P.refill_threshold || n_idle == kWave) {
             // score the histories that ended since the last refill, all together
-            if (pending) {
-                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
-                    const HistAngles<R> q = hist_angles<R>(s, P.qmask);
-                    for (int t = 0; t < P.n_tallies; ++t) {
-                        const TallyDev& T = P.tallies[t];
-                        int64_t b = tally_bin<R>(T, s, q);
-                        if (b >= 0) score_mixed(T, b, s.w, lds, cvals, ckeys);
-                    }
+            if (__ballot(pending) != 0ull) {
+                const bool scoring =
+                    pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
+                const HistAngles<R> q = hist_angles<R>(s, P.qmask);
+                for (int t = 0; t < P.n_tallies; ++t) {
+                    const TallyDev& T = P.tallies[t];
+                    const Bin b = scoring ? tally_bin<R>(T, s, s.term, q) : Bin{-1, -1};
+                    score_wave(T, b, s.w, lds, cvals, ckeys);
                 }
-                if (REC) write_record<R>(P.records + (s.h - P.first), s);
-                count_end<R>(cnt, s);
-                pending = false;
+                if (pending) {
+                    if (REC) write_record<R>(P.records + (s.h - P.first), s);
+                    count_end<R>(cnt, s);
+                    pending = false;
+                }
             }
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
@@ -307,9 +374,20 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
             if (exhausted && __ballot(pending) == 0ull) break;
             continue;
         }
+        bool first = false;
         if (s.term == 0) {
-            step<R, REC, GRID>(s, S, P.seed);
+            first = step<R, REC, GRID>(s, S, P.seed);
             pending = s.term != 0;
+        }
+        // first-collision tallies (a debugging trigger of the FP64 policies) score
+        // the state just after the collision
+        if (sizeof(R) == 8 && P.has_fc && __ballot(first) != 0ull) {
+            const HistAngles<R> q = hist_angles<R>(s, P.qmask);
+            for (int t = 0; t < P.n_tallies; ++t) {
+                const TallyDev& T = P.tallies[t];
+                const Bin b = first ? tally_bin<R>(T, s, kTermFirstCollision, q) : Bin{-1, -1};
+                score_wave(T, b, s.w, lds, cvals, ckeys);
+            }
         }
     }
     flush_counters(cnt, P.stats);
@@ -319,22 +397,17 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
         const TallyDev& T = P.tallies[t];
         if (T.cache_base >= 0) {
             const int ns = 1 << T.cache_bits;
-            for (int i = threadIdx.x; i < ns; i += blockDim.x) {
+            for (int base = 0; base < ns; base += blockDim.x) {
+                const int i = base + (int)threadIdx.x;
                 const int slot = T.cache_base + i;
-                const uint32_t key = ckeys[slot];
-                if (key != kEmptyKey) {
-                    add_global(T, key, cvals[2 * slot], cvals[2 * slot + 1]);
-                }
+                const uint32_t key = i < ns ? ckeys[slot] : kEmptyKey;
+                const bool used = key != kEmptyKey;
+                add_pairs_wave<false>(T.sw, used ? (int64_t)key : 0, used ? cvals[2 * slot] : 0.0,
+                                      used ? cvals[2 * slot + 1] : 0.0, used);
             }
         }
         if (T.lds_offset < 0) continue;
-        for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
-            double a = lds[T.lds_offset + i];
-            double b = lds[T.lds_offset + T.total + i];
-            if (a != 0.0 || b != 0.0) {
-                add_global(T, i, a, b);
-            }
-        }
+        merge_pairs(T.sw, lds + T.lds_offset, T.lds_bins, [&](int64_t i) { return slice_to_flat(T, i); });
     }
 }
 
@@ -390,16 +463,22 @@ __device__ __forceinline__ int sim_of_position(const BatchParams& B, unsigned lo
     return lo;
 }
 
+// Score w into entry t of the staged simulation from every lane of a converged
+// wave with a valid bin: the privatised LDS copy, else the LDS bin cache, else
+// global memory (paired-lane atomics).
 __device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& sd, int t, int64_t b, double w,
                                             double* ltal, uint32_t* ckeys) {
     const TallyDev& T = B.tallies[t];
+    bool global = b >= 0;
     if (sd.privatised) {
-        atomicAdd(ltal + T.lds_offset + b, w);
-        atomicAdd(ltal + T.lds_offset + T.total + b, w * w);
+        if (b >= 0) {
+            atomicAdd(ltal + T.lds_offset + b, w);
+            atomicAdd(ltal + T.lds_offset + T.total + b, w * w);
+        }
         return;
     }
     const uint64_t key64 = B.tally_key_base[t] + (uint64_t)b;
-    if (B.cache_bits > 0 && key64 < (uint64_t)kEmptyKey) {
+    if (B.cache_bits > 0 && global && key64 < (uint64_t)kEmptyKey) {
         const uint32_t key = (uint32_t)key64;
         const uint32_t h = (key * 2654435761u) >> (32 - B.cache_bits);
         const uint32_t mask = (1u << B.cache_bits) - 1u;
@@ -414,11 +493,12 @@ __device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& 
             if (k == key) {
                 atomicAdd(ltal + 2 * slot, w);
                 atomicAdd(ltal + 2 * slot + 1, w * w);
-                return;
+                global = false;
+                break;
             }
         }
     }
-    add_global(T, b, w, w * w);
+    add_global_wave(T.sw, b, w, global);
 }
 
 // merge the staged simulation's LDS tallies into global memory (whole block)
@@ -427,23 +507,23 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
     if (sd.privatised) {
         for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
             const TallyDev& T = B.tallies[t];
-            for (int64_t i = threadIdx.x; i < T.total; i += blockDim.x) {
-                const double a = ltal[T.lds_offset + i], b = ltal[T.lds_offset + T.total + i];
-                if (a != 0.0 || b != 0.0) {
-                    add_global(T, i, a, b);
-                }
-            }
+            merge_pairs(T.sw, ltal + T.lds_offset, T.total, [](int64_t i) { return i; });
         }
     } else if (B.cache_bits > 0) {
         const int nslots = 1 << B.cache_bits;
-        for (int i = threadIdx.x; i < nslots; i += blockDim.x) {
-            const uint32_t key = ckeys[i];
-            if (key == kEmptyKey) continue;
+        for (int base = 0; base < nslots; base += blockDim.x) {
+            const int i = base + (int)threadIdx.x;
+            const uint32_t key = i < nslots ? ckeys[i] : kEmptyKey;
+            const bool used = key != kEmptyKey;
             int t = sd.tally_begin;
-            while (t + 1 < sd.tally_begin + sd.tally_count && B.tally_key_base[t + 1] <= key) ++t;
-            const TallyDev& T = B.tallies[t];
-            const uint64_t b = key - B.tally_key_base[t];
-            add_global(T, b, ltal[2 * i], ltal[2 * i + 1]);
+            while (used && t + 1 < sd.tally_begin + sd.tally_count && B.tally_key_base[t + 1] <= key) ++t;
+            // the entries of one simulation may differ from lane to lane: one pass per entry
+            for (int e = sd.tally_begin; e < sd.tally_begin + sd.tally_count; ++e) {
+                const bool mine = used && t == e;
+                const uint64_t b = mine ? key - B.tally_key_base[e] : 0;
+                add_pairs_wave<false>(B.tallies[e].sw, (int64_t)b, mine ? ltal[2 * i] : 0.0, mine ? ltal[2 * i + 1] : 0.0,
+                                      mine);
+            }
         }
     }
 }
@@ -487,16 +567,18 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
         const unsigned long long idle_mask = __ballot(idle);
         const int n_idle = __popcll(idle_mask);
         if (n_idle >= B.refill_threshold || n_idle == kWave) {
-            if (pending) {
-                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
-                    const HistAngles<float> q{0.f, 0.f};
-                    for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
-                        int64_t b = tally_bin<float, false>(B.tallies[t], s, q);
-                        if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
-                    }
+            if (__ballot(pending) != 0ull) {
+                const bool scoring =
+                    pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
+                const HistAngles<float> q{0.f, 0.f};
+                for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
+                    const int64_t b = scoring ? tally_bin<float, false>(B.tallies[t], s, s.term, q).flat : -1;
+                    score_block(B, sd, t, b, s.w, ltal, ckeys);
                 }
-                count_end<float>(cnt, s);
-                pending = false;
+                if (pending) {
+                    count_end<float>(cnt, s);
+                    pending = false;
+                }
             }
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
@@ -632,7 +714,9 @@ int mixed_lds_bytes(const Params& P) { return lds_layout(P).bytes; }
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     if (P.n == 0) return hipSuccess;
     const int block = 256;
-    const dim3 grid((unsigned)((P.n + block - 1) / block));
+    // one thread per history up to 2^20 blocks; larger runs stride over the grid
+    const uint64_t blocks = (P.n + block - 1) / block;
+    const dim3 grid((unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20)));
     if (P.has_grid) {
         if (rec) hipLaunchKernelGGL((k_plain<true, true>), grid, dim3(block), 0, st, P);
         else hipLaunchKernelGGL((k_plain<false, true>), grid, dim3(block), 0, st, P);

@@ -206,3 +206,27 @@ def test_prepared_batch_validation(ctx):
     assert code_of(lambda: ctx.prepare_batch([], stride=1000)) == -1
     assert code_of(lambda: ctx.run_prepared(0, stream=0)) == -2
     assert code_of(lambda: ctx.release_batch(3)) == -2
+
+
+def test_boundary_sizes_and_rejections(ctx):
+    """pr_workspace_size and pr_tally_storage_size answer without a device; the
+    Kahan accumulator is rejected; first-collision tallies are refused by the FP32
+    policy before any device work; caller tally storage is size-checked."""
+    for prec in ("fp64", "fp32", "fp64_persistent"):
+        assert ctx.workspace_size(prec) == 256
+    assert code_of(lambda: ctx.workspace_size(7)) == -1
+    t = W.Tally(axes=[W.Axis("theta2", 0, 180, 1800), W.Axis("lambda", 0.5, 5, 100)])
+    assert ctx.tally_storage_size(t) == 2 * 1800 * 100 * 8
+    assert code_of(lambda: ctx.create_tally(dataclasses.replace(t, accumulator="kahan_fp32"))) == -1
+    assert code_of(lambda: ctx.tally_storage_size(dataclasses.replace(t, accumulator="kahan_fp32"))) == -1
+    p = W.analog_sample()
+    p.tallies = [W.Tally(trigger="first_collision")]
+    sim = B.Simulation(ctx, p)
+    assert code_of(lambda: ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, "fp32", None, 0)) == -1
+    for prec in ("fp64", "fp64_persistent"):
+        assert code_of(lambda: ctx.run(sim.geom, sim.src, sim.tallies, 0, 10, prec, None, 0)) == -5
+    d = B.tally_desc(t)
+    i = C.c_int32()
+    assert ctx.lib.pr_create_tally_in(ctx.h, C.byref(d), C.c_void_p(4096), 1000, C.byref(i)) == B.PR_EWORKSPACE
+    assert ctx.lib.pr_create_tally_in(ctx.h, C.byref(d), C.c_void_p(4096), 1 << 22, C.byref(i)) == -5
+    assert ctx.lib.pr_create_tally_in(ctx.h, C.byref(d), None, 1 << 22, C.byref(i)) == -1

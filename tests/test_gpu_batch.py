@@ -13,7 +13,7 @@ from oracle import oracle as O
 from paper_2304_06226_amd import binding as B
 from paper_2304_06226_amd import workloads as W
 
-from parity import compare_records_fp64, compare_tallies_fp64, gpu_run, tally_stat_test
+from parity import ORACLE_FIRST, compare_records_fp64, compare_tallies_fp64, gpu_run, tally_stat_test
 
 pytestmark = pytest.mark.gpu
 
@@ -45,7 +45,7 @@ def test_imaging_fp32_tally_agreement(ctx, imaging):
     print("[case] imaging fp32 n=200000", flush=True)
     prob = W.imaging_problem(n=200_000)
     gres, grec, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
-    ores = O.run(prob, first=0, n=200_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=200_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         # coarse 32x32 pixels: sums of 16x16 detector pixels
         def coarse(a):
@@ -119,7 +119,7 @@ def test_batch_against_oracle(ctx):
     for i in list(range(0, 24, 5)) + [24]:
         s = br.sims[i]
         prob = batch.problems[i]
-        o = O.run(prob, first=br.offsets[i], n=prob.n_histories, threads=8)
+        o = O.run(prob, first=ORACLE_FIRST + br.offsets[i], n=prob.n_histories, threads=8)
         for t, (sw, sw2, nh) in enumerate(s.results()):
             if prob.name == "imaging":
                 def coarse(a):
@@ -230,7 +230,7 @@ def test_mixed_kind_grid_fp32_tally_agreement(ctx):
     print("[case] mixed-kind grid fp32 n=400000", flush=True)
     prob = _mixed_grid_problem(400_000)
     gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
-    ores = O.run(prob, first=0, n=400_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=400_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -275,7 +275,7 @@ def test_nested_grid_fp32_tally_agreement(ctx):
     prob = _nested_grid_problem(400_000)
     gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=0, n=400_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=400_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -327,7 +327,7 @@ def test_deep_scene_fp32_and_batched(ctx):
     prob = _deep_scene_problem(200_000)
     gres, _, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=0, n=200_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=200_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -398,7 +398,7 @@ def test_big_grid_fp32_and_batched(ctx):
     prob = _big_grid_problem(300_000)
     gres, _, gst = gpu_run(ctx, prob, first=0, n=300_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=0, n=300_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=300_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
