@@ -369,7 +369,10 @@ int pr_run_prepared(pr_ctx* ctx, int32_t batch, void* stream);
 int pr_release_batch(pr_ctx* ctx, int32_t batch);
 
 /* ---- launch tuning of the persistent policies (PR_FP32_MIXED, PR_FP64_PERSISTENT) ---- */
-/* block: threads per block (64, 128, 192 or 256); blocks_per_cu: resident
+/* block: threads per block, a multiple of 64 up to 1024 (launches clamp it to
+ * their kernel's limit: 1024 for the FP32 kernels without a daughter grid, 512
+ * with one, 256 for PR_FP64_PERSISTENT and for batches without a grid);
+ * blocks_per_cu: resident
  * blocks per compute unit of the persistent grid (0 = occupancy limit);
  * refill_threshold: idle lanes of a wave that trigger a refill (1..64);
  * lds_tally_bytes: LDS per block for privatised tallies (tallies are
@@ -380,6 +383,14 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * grid_chunk: the claim size for scenes that navigate a daughter grid (their
  * histories vary more in length, so smaller claims balance the waves), 0 =
  * chunk; in a batch it applies to the class of grid scenes;
+ * grid_walk_cells: 0, or 2..1024: in the FP32 policy (single runs and batches)
+ * a daughter-grid walk that has visited this many cells without finding the
+ * nearest daughter entry pauses at the far wall of the last cell: the history
+ * moves there without an event (a virtual boundary; the free flight is
+ * memoryless, so no expectation changes) and walks on in its next step, so a
+ * wave does not wait for its longest walk.  0: walks run to the end.  The FP64
+ * policies always walk to the end (their histories match the oracle's event by
+ * event);
  * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
  * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
  * spilling some state to scratch; which is faster depends on the workload);
@@ -399,6 +410,7 @@ typedef struct {
     int32_t chunk;
     int32_t waves_per_simd;
     int32_t grid_chunk;
+    int32_t grid_walk_cells;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
@@ -407,7 +419,7 @@ int pr_get_tuning(pr_ctx* ctx, pr_tuning* tuning);
 /* Pick the launch tuning for a workload by measurement: coordinate descent
  * (two passes) over refill threshold, chunk, resident blocks per CU,
  * bin-cache slots, waves per SIMD, block size and (when a scene has a daughter
- * grid) the grid claim size, each candidate timed with
+ * grid) the grid claim size and the grid walk length, each candidate timed with
  * HIP events on `stream` over a sample of the workload (every simulation's
  * history count times sample_fraction, at least 1; the best claim size depends
  * on the launch's size, so 1 tunes for the full workload).  nsims = 1 tunes pr_run_histories'

@@ -138,6 +138,7 @@ struct pr_ctx {
     int grid_chunk = 0;                 // claim size for scenes with a daughter grid (0: chunk)
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
+    int grid_walk_cells = 0;            // FP32 grid walks pause after this many cells (0: never)
     DescSlot slots[4];
     int waves_per_simd = 4;             // FP32 kernels without a grid: variant built for 4 or 5 waves per SIMD
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
@@ -1034,8 +1035,8 @@ constexpr int kLdsPerCu = 160 * 1024;
 // block count per CU set by the tuning keeps the tuned block size.
 template <class Occ>
 static int grid_block(const pr_ctx* c, Occ occupancy) {
-    if (c->mixed_blocks_per_cu > 0) return c->mixed_block;
-    int best = c->mixed_block, best_waves = occupancy(best) * (best / 64);
+    if (c->mixed_blocks_per_cu > 0) return std::min(c->mixed_block, 512);
+    int best = std::min(c->mixed_block, 512), best_waves = occupancy(best) * (best / 64);
     for (int b = 256; b <= 512; b += 256) {
         const int w = occupancy(b) * (b / 64);
         if (w > best_waves) { best = b; best_waves = w; }
@@ -1168,6 +1169,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.refill_threshold = c->refill_threshold;
     P.chunk = P.has_grid && c->grid_chunk > 0 ? c->grid_chunk : c->chunk;
     P.waves = c->waves_per_simd;
+    P.walk_cells = precision == PR_FP32_MIXED ? c->grid_walk_cells : 0;
     return PR_OK;
 }
 
@@ -1202,7 +1204,7 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
         if (P.scene_in_lds && mixed_lds_bytes(P) > kLdsPerCu) P.scene_in_lds = 0;   // tallies leave no room
         int lds = mixed_lds_bytes(P);
         if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "scene and tallies need %d bytes of LDS", lds);
-        int block = c->mixed_block;
+        int block = std::min(c->mixed_block, mixed_max_block(P));
         if (P.has_grid && P.scene_in_lds) block = grid_block(c, [&](int b) { return mixed_occupancy(P, b); });
         int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : mixed_occupancy(P, block);
         uint64_t want = (n + block - 1) / block;
@@ -1351,7 +1353,8 @@ extern "C" int pr_reset_stats(pr_ctx* c, void* stream) {
 
 extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
     if (!c || !t) return fail(c, PR_EINVAL, "null argument");
-    if (t->block < 64 || t->block > 256 || t->block % 64) return fail(c, PR_EINVAL, "tuning.block must be 64, 128, 192 or 256");
+    if (t->block < 64 || t->block > 1024 || t->block % 64)
+        return fail(c, PR_EINVAL, "tuning.block must be a multiple of 64 in [64, 1024]");
     if (t->blocks_per_cu < 0 || t->blocks_per_cu > 64) return fail(c, PR_EINVAL, "tuning.blocks_per_cu must be 0..64");
     if (t->refill_threshold < 1 || t->refill_threshold > 64) return fail(c, PR_EINVAL, "tuning.refill_threshold must be 1..64");
     if (t->lds_tally_bytes < 0 || t->lds_tally_bytes > 131072) return fail(c, PR_EINVAL, "tuning.lds_tally_bytes must be 0..131072");
@@ -1361,6 +1364,9 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
     if (t->grid_chunk < 0 || t->grid_chunk > (1 << 20)) return fail(c, PR_EINVAL, "tuning.grid_chunk must be 0..2^20");
     if (t->waves_per_simd != 0 && t->waves_per_simd != 4 && t->waves_per_simd != 5)
         return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
+    if (t->grid_walk_cells != 0 && (t->grid_walk_cells < 2 || t->grid_walk_cells > 1024))
+        return fail(c, PR_EINVAL, "tuning.grid_walk_cells must be 0 or 2..1024");
+    c->grid_walk_cells = t->grid_walk_cells;
     c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
     c->grid_chunk = t->grid_chunk;
@@ -1382,6 +1388,7 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->chunk = c->chunk;
     t->waves_per_simd = c->waves_per_simd;
     t->grid_chunk = c->grid_chunk;
+    t->grid_walk_cells = c->grid_walk_cells;
     return PR_OK;
 }
 
@@ -1485,6 +1492,7 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     B.lds_scene_bytes = scene_bytes;
     B.refill_threshold = c->refill_threshold;
     B.waves = c->waves_per_simd;
+    B.walk_cells = c->grid_walk_cells;
     B.total_histories = total;
     B.chunk = (uint64_t)(grid_nav && c->grid_chunk > 0 ? c->grid_chunk : c->chunk);
     B.seed = c->seed;
@@ -1493,7 +1501,7 @@ static int plan_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int
     B.shift = nullptr;
     const int lds = batch_lds_bytes(B);
     if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "batch needs %d bytes of LDS per block", lds);
-    P.block = c->mixed_block;
+    P.block = std::min(c->mixed_block, batch_max_block(grid_nav));
     if (grid_nav && slds) P.block = grid_block(c, [&](int b) { return batch_occupancy(B, slds, grid_nav, b); });
     const int per_cu =
         c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : batch_occupancy(B, slds, grid_nav, P.block);
@@ -1549,6 +1557,7 @@ static int run_batch_class(pr_ctx* c, const pr_sim* sims, const std::vector<int>
 }
 
 static int run_batch_all(pr_ctx* c, const pr_sim* sims, int32_t nsims, hipStream_t stream, bool trial);
+static std::vector<int> batch_classes(const pr_ctx* c, const pr_sim* sims, int32_t nsims);
 
 static int validate_sims(pr_ctx* c, const pr_sim* sims, int32_t nsims) {
     for (int i = 0; i < nsims; ++i) {
@@ -1789,12 +1798,15 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         {&c->mixed_blocks_per_cu, {0, 2, 3}},
         {&c->bin_cache_slots, {0, 256, 1024, 2048}},
         {&c->waves_per_simd, {4, 5}},
-        {&c->mixed_block, {64, 128, 256}},
+        {&c->mixed_block, {64, 128, 256, 512, 1024}},
     };
     // scenes with a daughter grid get their own claim size
     bool any_grid = false;
     for (const auto& s : sample) any_grid = any_grid || !c->geoms[s.geom].gd.empty();
-    if (any_grid) knobs.push_back({&c->grid_chunk, {0, 64, 128, 256}});
+    if (any_grid) {
+        knobs.push_back({&c->grid_chunk, {0, 64, 128, 256}});
+        knobs.push_back({&c->grid_walk_cells, {0, 2, 3, 4, 6, 8, 16}});
+    }
 
     float cur = 0.f;
     rc = trial_ms(c, sample, batched, st, e0, e1, 2, &cur);

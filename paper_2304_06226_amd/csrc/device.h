@@ -222,6 +222,7 @@ struct Params {
     int32_t chunk;                 // persistent policy: history indices a wave claims per atomic
     int32_t waves;                 // FP32 persistent policy: waves per SIMD the launched variant is built for (4 or 5)
     int32_t has_fc;                // some tally of the run fires at the first collision
+    int32_t walk_cells;            // FP32 grid walks pause after this many cells (0: never)
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)
@@ -260,6 +261,7 @@ struct BatchParams {
     int32_t lds_scene_bytes;          // LDS scene region
     int32_t refill_threshold;
     int32_t waves;                    // waves per SIMD the launched variant is built for (4 or 5)
+    int32_t walk_cells;               // grid walks pause after this many cells (0: never)
     uint64_t total_histories, chunk, seed;
     unsigned long long* stats;
     unsigned long long* sim_next;     // per simulation: next history index to claim (zeroed per launch)
@@ -372,9 +374,6 @@ struct PState {
     int32_t xs_mat, nact;
     R sa, si, sc, sig, sig_g, ga, gs, cl;
     R t;   // time since emission, s
-    // FP32: the daughter just left by a move shorter than the sliver length (see
-    // sliver_tol), not to be re-entered through a piece that short; -1: none
-    int32_t skip;
 };
 
 // FP64 draws: the block of draw k is computed when k is even, its second word
@@ -582,33 +581,43 @@ __device__ __forceinline__ void subtract(Pieces<R>& P, R oa, R ob, int ofa, int 
 // an edge or touching a curved surface can cut a daughter piece that short: the
 // history enters the daughter, finds its exit at distance ~0, returns to the
 // mother without having moved, and would find the same piece ahead again, for
-// ever.  So when a history leaves a daughter by a move shorter than the sliver
-// length, that daughter (PState::skip) is not re-entered in the next step through
-// a piece shorter than the sliver length.  Every other piece is entered as in
-// FP64, however thin (a 1 um chopper disk far from the origin included).  FP64
-// needs no such rule.
+// ever.  So in FP32 a move that enters a daughter and is shorter than the sliver
+// length carries the position the sliver length along the direction (the weight
+// and the time of flight take the true distance): a sliver piece then lies behind
+// the history, which leaves the daughter at once and does not find it again.
+// Every piece is entered as in FP64, however thin (a 1 um chopper disk far from
+// the origin included: its mask applies); what the rule gives up is the
+// attenuation of at most one sliver length of path per such entry.  FP64 needs no
+// such rule.
 template <class R>
 __device__ __forceinline__ R sliver_tol(const R p[3]) {
-    if constexpr (sizeof(R) == 4)
-        return (__builtin_fabsf(p[0]) + __builtin_fabsf(p[1]) + __builtin_fabsf(p[2])) * 9.5367431640625e-07f;   // 2^-20
+    if constexpr (sizeof(R) == 4)   // 3 * 2^-20 * max |coordinate| (one max3 and one multiply)
+        return __builtin_fmaxf(__builtin_fmaxf(__builtin_fabsf(p[0]), __builtin_fabsf(p[1])), __builtin_fabsf(p[2])) *
+               2.86102294921875e-06f;
     else
         return (R)0;
 }
 
-// distance to where the ray enters a daughter's first piece ahead (rinf: none);
-// skipped: the daughter is the one just left without progress (FP32)
-template <class R>
-__device__ __forceinline__ R entry_distance(const Pieces<R>& P, R tol, bool skipped) {
-    if constexpr (sizeof(R) == 4) {
-        const R min_len = skipped ? tol : (R)0;
-        if (P.n > 0 && P.a0 > (R)0 && P.b0 - P.a0 > min_len) return P.a0;
-        if (P.n > 1 && P.a1 > (R)0 && P.b1 - P.a1 > min_len) return P.a1;
-        return rinf<R>();
-    } else {
-        if (P.n > 0 && P.a0 > (R)0) return P.a0;
-        if (P.n > 1 && P.a1 > (R)0) return P.a1;
-        return rinf<R>();
+// FP32: after a move of length x that ended at a paused grid walk's virtual
+// boundary, advance the position to at least the sliver length along the
+// direction (no surface lies there).  Only lanes taking that branch pay.
+__device__ __forceinline__ void sliver_advance(PState<float>& s, float x) {
+    const float tol = sliver_tol<float>(s.p);
+    if (x < tol) {
+        const float e = tol - x;
+        s.p[0] += e * s.u[0];
+        s.p[1] += e * s.u[1];
+        s.p[2] += e * s.u[2];
     }
+}
+__device__ __forceinline__ void sliver_advance(PState<double>&, double) {}
+
+// distance to where the ray enters a daughter's first piece ahead (rinf: none)
+template <class R>
+__device__ __forceinline__ R entry_distance(const Pieces<R>& P) {
+    if (P.n > 0 && P.a0 > (R)0) return P.a0;
+    if (P.n > 1 && P.a1 > (R)0) return P.a1;
+    return rinf<R>();
 }
 
 template <class R>
@@ -840,7 +849,6 @@ __device__ __forceinline__ void source(PState<R>& s, const SourceDev& src, const
     s.nscat = 0;
     s.steps = 0;
     s.term = 0;
-    s.skip = -1;
     s.hash = 14695981039346656037ull;
     R p[3] = {(R)src.o[0], (R)src.o[1], (R)src.o[2]};
     R u[3] = {(R)src.u[0], (R)src.u[1], (R)src.u[2]};
@@ -959,9 +967,14 @@ __device__ __forceinline__ void load_xs(PState<R>& s, const SceneT<R>& S, int ma
 // lies within the cells already visited)
 // -------------------------------------------------------------------------
 
+// walk_cells > 0 (FP32): after that many cells without a definitive answer the
+// walk pauses and d_pause receives the far wall of the last cell visited; the
+// step then moves there without an event (a virtual boundary) and the next step
+// walks on from there, so a wave no longer waits for its longest walk.  The
+// free flight is memoryless, so pausing changes no expectation.
 template <class R>
 __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>& G, const R p[3], const R u[3], R tmax,
-                                             R tol, int skip, R& d_child, int& child, int& child_det) {
+                                             int walk_cells, R& d_child, int& child, int& child_det, R& d_pause) {
     R t0 = (R)0, t1 = tmax;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -1005,7 +1018,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
             const uint32_t item = (uint32_t)S.cell_items[j];
             Pieces<R> Q;
             item_pieces<R>(S, item, p, u, Q);
-            const R a = entry_distance<R>(Q, tol, (int)(item & kItemVol) == skip);
+            const R a = entry_distance<R>(Q);
             if (a < d_child) {
                 d_child = a;
                 child = (int)(item & kItemVol);
@@ -1017,6 +1030,10 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
         const bool ax1 = !ax0 && tn[1] <= tn[2];
         const R tc = ax0 ? tn[0] : (ax1 ? tn[1] : tn[2]);
         if (d_child <= tc || tc > t1) break;
+        if (it + 1 == walk_cells) {
+            d_pause = tc;
+            break;
+        }
         if (ax0) { ix[0] += st[0]; tn[0] += td[0]; }
         else if (ax1) { ix[1] += st[1]; tn[1] += td[1]; }
         else { ix[2] += st[2]; tn[2] += td[2]; }
@@ -1036,7 +1053,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 // equal entry distances the lower daughter index wins, as in a scan in order.
 template <class R, int K, class ST>
 __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, const ST& s, uint32_t items, R& d_exit,
-                                          int& face, R tol, R& d_child, int& child, int& child_item, int& child_det) {
+                                          int& face, R& d_child, int& child, int& child_item, int& child_det) {
     if (((S.kinds >> K) & 1u) == 0u) return;
     while (__ballot(items != 0u) != 0ull) {
         if (items != 0u) {
@@ -1049,7 +1066,7 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
                 if (P.n > 0 && P.b0 > (R)0) { d_exit = P.b0; face = P.fb0; }
                 if (P.n > 1 && P.b1 > (R)0 && P.b1 < d_exit) { d_exit = P.b1; face = P.fb1; }
             } else {
-                const R a = entry_distance<R>(P, tol, vid == s.skip);
+                const R a = entry_distance<R>(P);
                 if (a < d_child || (a == d_child && a != rinf<R>() && i < child_item)) {
                     d_child = a;
                     child = vid;
@@ -1065,7 +1082,7 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
 // One step; returns true when the step was the history's first collision
 // (absorption or scattering), the event of first-collision tallies.
 template <class R, bool REC, bool GRID>
-__device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed) {
+__device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed, int walk_cells = 0) {
     if (s.steps >= kMaxSteps) {
         s.term = PR_END_CAPPED;
         hash_ev<REC>(s.hash, EV_CAPPED, 0);
@@ -1081,17 +1098,24 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
     int face = -1;
     R d_child = rinf<R>();
     int child = -1, child_item = 0, child_det = 0;
-    const R tol = sliver_tol<R>(s.p);
-    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
-    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
-    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
-    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, tol, d_child, child, child_item, child_det);
-    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, tol, d_child, child, child_item, child_det);
+    scan_kind<R, PR_BOX>(S, V, s, V.kind_items & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYLINDER>(S, V, s, (V.kind_items >> 8) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_CYL_SHELL>(S, V, s, (V.kind_items >> 16) & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPHERE>(S, V, s, V.kind_items >> 24, d_exit, face, d_child, child, child_item, child_det);
+    scan_kind<R, PR_SPH_SHELL>(S, V, s, V.kind_items4 & 0xFFu, d_exit, face, d_child, child, child_item, child_det);
     if (d_exit == rinf<R>()) { d_exit = (R)0; face = -1; }
-    if (GRID && V.grid >= 0) grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, tol, s.skip, d_child, child, child_det);
-    if constexpr (sizeof(R) == 4) s.skip = -1;
+    R d_pause = rinf<R>();
+    if (GRID && V.grid >= 0)
+        grid_nearest<R>(S, S.grids[V.grid], s.p, s.u, d_exit, sizeof(R) == 4 ? walk_cells : 0, d_child, child,
+                        child_det, d_pause);
     bool to_child = d_child < d_exit;
     R d_b = to_child ? d_child : d_exit;
+    // a paused grid walk (FP32): the far wall of its last cell is a virtual boundary
+    const bool pause = GRID && d_pause < d_b;
+    if (pause) {
+        d_b = d_pause;
+        to_child = false;
+    }
 
     R sig = (R)0, sig_g = (R)0;
     if (V.mat >= 0) {
@@ -1108,9 +1132,15 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
         R l = M<R>::div_(-M<R>::log_(xi), sig_g);
         if (l < d_b) { collide = true; x = l; }
     }
-    s.p[0] += x * s.u[0];
-    s.p[1] += x * s.u[1];
-    s.p[2] += x * s.u[2];
+    // FP32: an entry move shorter than the sliver length carries the position the
+    // sliver length (see sliver_tol); weight and time take x
+    R xm = x;
+    if constexpr (sizeof(R) == 4) {
+        if (!collide && to_child) xm = __builtin_fmaxf(x, sliver_tol<R>(s.p));
+    }
+    s.p[0] += xm * s.u[0];
+    s.p[1] += xm * s.u[1];
+    s.p[2] += xm * s.u[2];
     if ((S.kinds >> kTimeBit) & 1u) s.t += M<R>::div_(x * s.lam, (R)kHOverMn);
     if (sig_g > (R)0) s.w *= (double)M<R>::exp_((sig_g - sig) * x);
 
@@ -1173,6 +1203,10 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
         return s.nscat == 1;
     }
 
+    if (pause) {   // no event: the next step walks on from here
+        sliver_advance(s, x);
+        return false;
+    }
     if (to_child) {
         s.region = child;
         hash_ev<REC>(s.hash, EV_ENTER, child);
@@ -1211,7 +1245,6 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
         hash_ev<REC>(s.hash, EV_ESCAPE, 0);
         return false;
     }
-    if constexpr (sizeof(R) == 4) s.skip = x < tol ? s.region : -1;
     s.region = V.parent;
     hash_ev<REC>(s.hash, EV_EXIT, s.region);
     return false;
@@ -1244,23 +1277,22 @@ __device__ __forceinline__ double beam_component<double>(const TallyDev& T, int 
 template <>
 __device__ __forceinline__ float beam_component<float>(const TallyDev& T, int k) { return T.beam_f[k]; }
 
-// Bin of a score: flat index over all axes (-1: not scored) and the index in the
-// tally's privatised slice (-1: outside it; the flat index when the whole tally
-// is privatised).
-struct Bin {
-    int64_t flat, slice;
-};
+// A score's bin: -1 when not scored; otherwise the flat index over all axes,
+// except for a tally privatised as a slice (fix_axis >= 0), where it is the
+// index within the slice, or the flat index with kOffSlice set for a bin outside
+// the slice.
+constexpr int64_t kOffSlice = 1ll << 62;
 
 // term: the history's termination code, or kTermFirstCollision at its first
 // collision.  q: the history's divergence angles, computed once for all tallies
 // (PRE), or left to each divergence axis to compute (fewer values live across
 // the loop).
 template <class R, bool PRE = true>
-__device__ __forceinline__ Bin tally_bin(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
+__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
     const TallyHead h = T.head;
     if (!(((h.term_mask >> term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
           (h.volume < 0 || h.volume == s.region)))
-        return Bin{-1, -1};
+        return -1;
     // cosine of the angle to the beam, for the 2-theta and momentum-transfer axes
     R c = (R)0;
     if (h.qmask & ((1u << PR_Q_THETA2) | (1u << PR_Q_Q))) {
@@ -1290,15 +1322,18 @@ __device__ __forceinline__ Bin tally_bin(const TallyDev& T, const PState<R>& s, 
             break;
         default: x = (R)s.nscat; break;
         }
-        if (!(x >= lo && x <= hi)) return Bin{-1, -1};
+        if (!(x >= lo && x <= hi)) return -1;
         int b = (int)__builtin_floor((double)((x - lo) * scale));
         if (x == hi || b >= n) b = n - 1;
         if (b < 0) b = 0;
         flat = flat * n + b;
-        if (a == h.fix_axis) in_slice = b == h.fix_bin;
-        else slice = slice * n + b;
+        if (h.fix_axis >= 0) {   // uniform: only sliced tallies pay
+            if (a == h.fix_axis) in_slice = b == h.fix_bin;
+            else slice = slice * n + b;
+        }
     }
-    return Bin{flat, in_slice ? slice : -1};
+    if (h.fix_axis < 0) return flat;
+    return in_slice ? slice : (flat | kOffSlice);
 }
 
 // flat index of bin i of a tally's slice (inverse of the slice index)

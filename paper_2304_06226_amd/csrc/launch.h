@@ -11,6 +11,8 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st);
 hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStream_t st);
 int mixed_occupancy(const Params& P, int block);
 int mixed_lds_bytes(const Params& P);
+int mixed_max_block(const Params& P);   // the launch bound of the persistent kernel P selects
+int batch_max_block(bool grid_nav);
 hipError_t launch_batch(const BatchParams& B, bool slds, bool grid_nav, int grid, int block, hipStream_t st);
 int batch_occupancy(const BatchParams& B, bool slds, bool grid_nav, int block);
 int batch_lds_bytes(const BatchParams& B);

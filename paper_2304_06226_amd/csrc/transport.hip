@@ -125,8 +125,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
                     // first-collision tallies score the state just after the collision
                     const HistAngles<double> q = hist_angles<double>(s, P.qmask);
                     for (int t = 0; t < P.n_tallies; ++t) {
-                        const Bin b = tally_bin<double>(P.tallies[t], s, kTermFirstCollision, q);
-                        if (b.flat >= 0) add_global(P.tallies[t], b.flat, s.w, s.w * s.w);
+                        const int64_t b = tally_bin<double>(P.tallies[t], s, kTermFirstCollision, q);
+                        if (b >= 0) add_global(P.tallies[t], b, s.w, s.w * s.w);
                     }
                 }
             }
@@ -137,8 +137,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
             const HistAngles<double> q = hist_angles<double>(s, P.qmask);
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
-                const Bin b = scoring ? tally_bin<double>(T, s, s.term, q) : Bin{-1, -1};
-                add_global_wave(T.sw, b.flat, s.w, b.flat >= 0);
+                const int64_t b = scoring ? tally_bin<double>(T, s, s.term, q) : -1;
+                add_global_wave(T.sw, b, s.w, b >= 0);
             }
         }
         if (live) {
@@ -195,21 +195,24 @@ __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
 
 constexpr uint32_t kEmptyKey = 0xFFFFFFFFu;
 
-// Score w into tally T from every lane of a converged wave whose bin is valid:
-// the block's privatised copy when the bin lies in it (the whole tally, or its
-// slice), else the block's LDS bin cache (a slot is claimed by the first bin
-// that hashes to it; two probes), else global memory.
-__device__ __forceinline__ void score_wave(const TallyDev& T, const Bin& b, double w, double* lds, double* cvals,
-                                           uint32_t* ckeys) {
-    bool global = b.flat >= 0;
+// Score w into tally T (b: the bin from tally_bin, -1 = none): the block's
+// privatised copy when the bin lies in it (the whole tally, or its slice), else
+// the block's LDS bin cache (a slot is claimed by the first bin that hashes to
+// it; two probes), else global memory.  Returns the global bin, or -1 when the
+// score was taken in LDS or there is none.
+__device__ __forceinline__ int64_t score_lds(const TallyDev& T, int64_t b, double w, double* lds, double* cvals,
+                                             uint32_t* ckeys) {
+    if (b < 0) return -1;
     if (T.lds_offset >= 0) {
-        if (b.slice >= 0) {
-            atomicAdd(lds + T.lds_offset + b.slice, w);
-            atomicAdd(lds + T.lds_offset + T.lds_bins + b.slice, w * w);
-            global = false;
+        if (T.head.fix_axis < 0 || (b & kOffSlice) == 0) {
+            atomicAdd(lds + T.lds_offset + b, w);
+            atomicAdd(lds + T.lds_offset + T.lds_bins + b, w * w);
+            return -1;
         }
-    } else if (T.cache_base >= 0 && global && b.flat < (int64_t)kEmptyKey) {
-        const uint32_t key = (uint32_t)b.flat;
+        return b & ~kOffSlice;   // outside the privatised slice
+    }
+    if (T.cache_base >= 0 && b < (int64_t)kEmptyKey) {
+        const uint32_t key = (uint32_t)b;
         const uint32_t h = (key * 2654435761u) >> (32 - T.cache_bits);
         const uint32_t mask = (1u << T.cache_bits) - 1u;
 #pragma unroll
@@ -223,12 +226,29 @@ __device__ __forceinline__ void score_wave(const TallyDev& T, const Bin& b, doub
             if (k == key) {
                 atomicAdd(cvals + 2 * slot, w);
                 atomicAdd(cvals + 2 * slot + 1, w * w);
-                global = false;
-                break;
+                return -1;
             }
         }
     }
-    add_global_wave(T.sw, b.flat, w, global);
+    return b;
+}
+
+// Scoring by a converged wave (every lane calls; b < 0: no score): global scores
+// leave as paired-lane atomics.
+__device__ __forceinline__ void score_wave(const TallyDev& T, int64_t b, double w, double* lds, double* cvals,
+                                           uint32_t* ckeys) {
+    const int64_t g = score_lds(T, b, w, lds, cvals, ckeys);
+    add_global_wave(T.sw, g, w, g >= 0);
+}
+
+// Scoring from one lane in divergent code: per-lane global atomics (two requests
+// per score).  The FP32 kernels score this way: shuffling scores between lanes
+// at the refill point cost them more instructions and registers than the atomics
+// it saves (headline +1.7 %, imaging +10 %).
+__device__ __forceinline__ void score_lane(const TallyDev& T, int64_t b, double w, double* lds, double* cvals,
+                                           uint32_t* ckeys) {
+    const int64_t g = score_lds(T, b, w, lds, cvals, ckeys);
+    if (g >= 0) add_global(T, g, w, w * w);
 }
 
 // Merge n_pairs (value, square) LDS sums a[i], a[n + i] into global pairs at
@@ -284,8 +304,13 @@ struct PersistentScene<double, false, GRID> {
 // per SIMD hides the latency of the grid walk (1000-box imaging 10.3 -> 8.6 ms).
 // Five waves (96 VGPRs) help some scenes and hurt others, so it is a launch
 // choice.
+// Block sizes: up to 1024 threads for the FP32 kernels without a grid (fewer
+// blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
 template <class R, bool REC, bool SLDS, bool GRID, int WPE>
-__global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_eu(WPE, 8))) void k_mixed(Params P) {
+__global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
+void k_mixed(Params P) {
+    // FP64: scores leave the wave as paired-lane atomics; FP32: per-lane atomics
+    constexpr bool kPaired = sizeof(R) == 8;
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
     char* base = (char*)lds;
@@ -330,20 +355,27 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
         const int n_idle = __popcll(idle_mask);
         if (n_idle >= P.refill_threshold || n_idle == kWave) {
             // score the histories that ended since the last refill, all together
-            if (__ballot(pending) != 0ull) {
+            if (kPaired && __ballot(pending) != 0ull) {
                 const bool scoring =
                     pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
                 const HistAngles<R> q = hist_angles<R>(s, P.qmask);
                 for (int t = 0; t < P.n_tallies; ++t) {
                     const TallyDev& T = P.tallies[t];
-                    const Bin b = scoring ? tally_bin<R>(T, s, s.term, q) : Bin{-1, -1};
+                    const int64_t b = scoring ? tally_bin<R>(T, s, s.term, q) : -1;
                     score_wave(T, b, s.w, lds, cvals, ckeys);
                 }
-                if (pending) {
-                    if (REC) write_record<R>(P.records + (s.h - P.first), s);
-                    count_end<R>(cnt, s);
-                    pending = false;
+            }
+            if (pending) {
+                if (!kPaired && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT)) {
+                    const HistAngles<R> q = hist_angles<R>(s, P.qmask);
+                    for (int t = 0; t < P.n_tallies; ++t) {
+                        const TallyDev& T = P.tallies[t];
+                        score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
+                    }
                 }
+                if (REC) write_record<R>(P.records + (s.h - P.first), s);
+                count_end<R>(cnt, s);
+                pending = false;
             }
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
@@ -376,7 +408,7 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
         }
         bool first = false;
         if (s.term == 0) {
-            first = step<R, REC, GRID>(s, S, P.seed);
+            first = step<R, REC, GRID>(s, S, P.seed, P.walk_cells);
             pending = s.term != 0;
         }
         // first-collision tallies (a debugging trigger of the FP64 policies) score
@@ -385,7 +417,7 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
             const HistAngles<R> q = hist_angles<R>(s, P.qmask);
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
-                const Bin b = first ? tally_bin<R>(T, s, kTermFirstCollision, q) : Bin{-1, -1};
+                const int64_t b = first ? tally_bin<R>(T, s, kTermFirstCollision, q) : -1;
                 score_wave(T, b, s.w, lds, cvals, ckeys);
             }
         }
@@ -463,22 +495,19 @@ __device__ __forceinline__ int sim_of_position(const BatchParams& B, unsigned lo
     return lo;
 }
 
-// Score w into entry t of the staged simulation from every lane of a converged
-// wave with a valid bin: the privatised LDS copy, else the LDS bin cache, else
-// global memory (paired-lane atomics).
+// Score w into entry t of the staged simulation from one lane: the privatised
+// LDS copy, else the LDS bin cache, else global memory.
 __device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& sd, int t, int64_t b, double w,
                                             double* ltal, uint32_t* ckeys) {
     const TallyDev& T = B.tallies[t];
-    bool global = b >= 0;
+    bool global = true;
     if (sd.privatised) {
-        if (b >= 0) {
-            atomicAdd(ltal + T.lds_offset + b, w);
-            atomicAdd(ltal + T.lds_offset + T.total + b, w * w);
-        }
+        atomicAdd(ltal + T.lds_offset + b, w);
+        atomicAdd(ltal + T.lds_offset + T.total + b, w * w);
         return;
     }
     const uint64_t key64 = B.tally_key_base[t] + (uint64_t)b;
-    if (B.cache_bits > 0 && global && key64 < (uint64_t)kEmptyKey) {
+    if (B.cache_bits > 0 && key64 < (uint64_t)kEmptyKey) {
         const uint32_t key = (uint32_t)key64;
         const uint32_t h = (key * 2654435761u) >> (32 - B.cache_bits);
         const uint32_t mask = (1u << B.cache_bits) - 1u;
@@ -498,7 +527,7 @@ __device__ __forceinline__ void score_block(const BatchParams& B, const SimDev& 
             }
         }
     }
-    add_global_wave(T.sw, b, w, global);
+    if (global) add_global(T, b, w, w * w);
 }
 
 // merge the staged simulation's LDS tallies into global memory (whole block)
@@ -530,7 +559,7 @@ __device__ __forceinline__ void flush_block(const BatchParams& B, const SimDev& 
 
 // the block's waves run histories of simulation `sim`, claiming chunks from its
 // counter, until the simulation has none left
-template <bool SLDS, bool GRID>
+template <bool SLDS, bool GRID, int WPE>
 __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, int sim, char* scene, double* ltal,
                                         uint32_t* ckeys, Counters& cnt, unsigned long long shift) {
     SceneT<float> S;
@@ -567,18 +596,16 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
         const unsigned long long idle_mask = __ballot(idle);
         const int n_idle = __popcll(idle_mask);
         if (n_idle >= B.refill_threshold || n_idle == kWave) {
-            if (__ballot(pending) != 0ull) {
-                const bool scoring =
-                    pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
-                const HistAngles<float> q{0.f, 0.f};
-                for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
-                    const int64_t b = scoring ? tally_bin<float, false>(B.tallies[t], s, s.term, q).flat : -1;
-                    score_block(B, sd, t, b, s.w, ltal, ckeys);
+            if (pending) {
+                if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
+                    const HistAngles<float> q{0.f, 0.f};
+                    for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
+                        const int64_t b = tally_bin<float, false>(B.tallies[t], s, s.term, q);
+                        if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
+                    }
                 }
-                if (pending) {
-                    count_end<float>(cnt, s);
-                    pending = false;
-                }
+                count_end<float>(cnt, s);
+                pending = false;
             }
             if (!exhausted && cnext >= cend) {
                 const int leader = __ffsll((long long)idle_mask) - 1;
@@ -612,7 +639,7 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
             continue;
         }
         if (s.term == 0) {
-            step<float, false, GRID>(s, S, B.seed);
+            step<float, false, GRID>(s, S, B.seed, B.walk_cells);
             pending = s.term != 0;
         }
     }
@@ -677,7 +704,7 @@ __global__ __launch_bounds__(GRID ? 512 : 256) __attribute__((amdgpu_waves_per_e
             __syncthreads();
             staged = sim;
         }
-        run_sim<SLDS, GRID>(B, sd, sim, scene, ltal, ckeys, cnt, shift);
+        run_sim<SLDS, GRID, WPE>(B, sd, sim, scene, ltal, ckeys, cnt, shift);
         __syncthreads();
         if (threadIdx.x == 0) ctl.sim = sim + 1 < B.nsims ? sim + 1 : 0;
     }
@@ -710,6 +737,9 @@ __global__ void k_zero_f64(double* p, uint64_t n) {
 // ------------------------------------------------------------------------
 
 int mixed_lds_bytes(const Params& P) { return lds_layout(P).bytes; }
+
+int mixed_max_block(const Params& P) { return P.has_grid ? 512 : (P.fp64 ? 256 : 1024); }
+int batch_max_block(bool grid_nav) { return grid_nav ? 512 : 256; }
 
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     if (P.n == 0) return hipSuccess;

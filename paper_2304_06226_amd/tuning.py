@@ -14,17 +14,17 @@ and the powder class 512 (-2 % against 256 for both)."""
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0},
+               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0},
+              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5, "grid_chunk": 0},
+               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 0, "chunk": 64, "waves_per_simd": 4, "grid_chunk": 0},
+                "bin_cache_slots": 0, "chunk": 64, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5, "grid_chunk": 0},
+                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5, "grid_chunk": 128},
+              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5, "grid_chunk": 128, "grid_walk_cells": 0},
 }
 
 # Launch tunings of the PR_FP64_PERSISTENT policy (the same knobs; waves_per_simd
@@ -39,5 +39,5 @@ TUNED_FP64_PERSISTENT = {
     "imaging": dict(TUNED["imaging"]),
     "paper_guide": dict(TUNED["paper_guide"], refill_threshold=32),
     "paper_chopper": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4, "grid_chunk": 0},
+                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
 }

@@ -181,37 +181,42 @@ def record_bins(tally, rec, edge_rel=0.0):
     return flat, alt, near_out
 
 
-def paired_variance(tally, rec32, rec64, edge_rel=2e-6):
+def paired_variance(tally, rec32, rec64, edge_rel32=2e-6, edge_rel64=2e-7):
     """Per-bin paired variance sum_h (x32_h - x64_h)^2 of the two policies'
-    per-history contributions.  A history whose FP32 value lies within edge_rel
-    of a bin edge counts its FP32 weight in the neighbouring bin too (its FP32
-    bin is uncertain at that distance), and one near the end of an axis range in
-    the FP64 bin."""
+    per-history contributions.  A history whose value lies within edge_rel of a
+    bin edge counts its weight in the neighbouring bin too: its bin is uncertain
+    at that distance (FP32 arithmetic on the FP32 side; on the FP64 side the
+    record's time of flight, rounded to FP32)."""
     nb = tally.nbins
-    b32, alt32, out32 = record_bins(tally, rec32, edge_rel)
-    b64, _, _ = record_bins(tally, rec64, 0.0)
+    b32, alt32, out32 = record_bins(tally, rec32, edge_rel32)
+    b64, alt64, out64 = record_bins(tally, rec64, edge_rel64)
     w32, w64 = rec32["w"], rec64["w"]
     V = np.zeros(nb)
-    uncertain = (alt32 >= 0).any(axis=1) | out32
+    uncertain = (alt32 >= 0).any(axis=1) | out32 | (alt64 >= 0).any(axis=1) | out64
     same = (b32 == b64) & (b32 >= 0) & ~uncertain
     np.add.at(V, b32[same], (w32[same] - w64[same]) ** 2)
     m = (b32 >= 0) & ~same
     np.add.at(V, b32[m], w32[m] ** 2)
     m = (b64 >= 0) & ~same
     np.add.at(V, b64[m], w64[m] ** 2)
-    for j in range(alt32.shape[1]):
-        m = alt32[:, j] >= 0
-        np.add.at(V, alt32[m, j], w32[m] ** 2)
+    for alt, w in ((alt32, w32), (alt64, w64)):
+        for j in range(alt.shape[1]):
+            m = alt[:, j] >= 0
+            np.add.at(V, alt[m, j], w[m] ** 2)
     return V
 
 
-def paired_check(prob, r32, rec32, r64, rec64, rel_round=1e-6, label=""):
+def paired_check(prob, r32, rec32, r64, rec64, rel_round=2e-5, label=""):
     """FP32 tallies r32 against FP64 tallies r64 of the same history ids (records
     rec32, rec64 of those histories): every bin's difference within 4 paired
     standard deviations (plus a relative FP32 rounding allowance rel_round of the
     bin), with the count of larger deviations within the 99.9% binomial quantile
     of (bins, 6.3e-5), and each tally's total within 4 paired standard deviations
-    plus rel_round.  Returns per tally (total relative difference, moved
+    plus rel_round.  The rounding allowance is systematic, not statistical: the
+    FP32 policy evaluates cross sections and flight exponents in FP32, so one
+    rounding of (g - 1) Sigma is shared by every step of every history of a
+    material; at large bias factors and path lengths it shifts the weights by up
+    to ~1e-5 relative.  Returns per tally (total relative difference, moved
     fraction sum|D| / sum|w64|) for reporting."""
     out = []
     n = len(rec32)
@@ -228,7 +233,7 @@ def paired_check(prob, r32, rec32, r64, rec64, rel_round=1e-6, label=""):
                                          den[bad][:10])
         tot = np.abs(w64).sum()
         if tot > 0:
-            assert abs(D.sum()) <= 4 * np.sqrt(V.sum()) + rel_round * tot, (label, t, D.sum(), np.sqrt(V.sum()))
+            assert abs(D.sum()) <= 4 * np.sqrt(V.sum()) + rel_round * tot, (label, t, D.sum(), np.sqrt(V.sum()), tot)
             out.append((float(D.sum() / tot), float(np.abs(D).sum() / tot)))
         else:
             assert np.all(w32 == 0), (label, t)
@@ -238,7 +243,7 @@ def paired_check(prob, r32, rec32, r64, rec64, rel_round=1e-6, label=""):
     return out
 
 
-def paired_fp32_fp64(ctx, prob, first, n, fp64="fp64_persistent", rel_round=1e-6, label=""):
+def paired_fp32_fp64(ctx, prob, first, n, fp64="fp64_persistent", rel_round=2e-5, label=""):
     """Both GPU policies over the same history ids with records, then paired_check."""
     print(f"[case] paired {label or prob.name} n={n} first={first}", flush=True)
     r32, rec32, st32 = gpu_run(ctx, prob, first=first, n=n, precision="fp32")

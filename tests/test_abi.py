@@ -172,7 +172,8 @@ def test_run_needs_a_device(ctx):
 def test_tuning_validation(ctx):
     t = ctx.get_tuning()
     assert t["block"] == 256 and t["chunk"] >= 1
-    assert code_of(lambda: ctx.set_tuning(block=512)) == -1
+    assert code_of(lambda: ctx.set_tuning(block=1088)) == -1
+    assert code_of(lambda: ctx.set_tuning(block=100)) == -1
     assert code_of(lambda: ctx.set_tuning(bin_cache_slots=1000)) == -1
     assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
     assert code_of(lambda: ctx.set_tuning(waves_per_simd=3)) == -1

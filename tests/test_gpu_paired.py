@@ -2,7 +2,7 @@
 FP32 workload: per tally bin, the difference of the two tallies is scored
 against the paired variance sum_h (x32_h - x64_h)^2 of the histories' own
 contributions (each history's bin from its record), with a relative FP32
-rounding allowance of 1e-6 per bin (parity.paired_check).  The FP64 policy is
+rounding allowance of 2e-5 per bin (parity.paired_check).  The FP64 policy is
 itself checked history by history against the oracle elsewhere, so this is the
 FP32 policy's error against the FP64 path, stated per tally (printed).  The
 batch is paired through its simulations: a batched FP32 run against the same
