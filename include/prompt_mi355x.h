@@ -348,6 +348,20 @@ typedef struct {
  * be reused as soon as the call returns. */
 int pr_run_batch(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): pr_run_batch without
+ * any device or pinned-host allocation.  The batch's descriptors and
+ * per-simulation claim counters go to a fixed 2 MiB device array compiled into
+ * the library (one per GPU, held until the process ends) instead of the
+ * context's descriptor ring; they are copied there from a context-owned host
+ * image with hipMemcpyAsync on `stream`, and the counters are cleared by a kernel
+ * on `stream`.  Results are those of pr_run_batch over the same simulations.
+ * Batches whose descriptors exceed the array (about 3000 simulations with one
+ * tally each) return PR_EWORKSPACE.  Every call on a GPU uses the same array:
+ * calls ordered on one stream are safe, calls that overlap in time on one GPU
+ * (other streams, other contexts) race and must not be issued. */
+int pr_run_batch_static(pr_ctx* ctx, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream);
+
 /* ---- prepared batches (repeated steps, HIP graph capture) ----
  * pr_prepare_batch validates sims as pr_run_batch does, uploads their
  * descriptors once into device memory owned by the context and freezes the

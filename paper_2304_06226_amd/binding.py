@@ -46,7 +46,7 @@ EXPORTS = ["pr_init", "pr_destroy", "pr_last_error", "pr_set_seed", "pr_create_m
            "pr_create_source", "pr_create_tally", "pr_tally_storage_size", "pr_create_tally_in", "pr_tally_nbins",
            "pr_workspace_size", "pr_run_histories", "pr_read_tally", "pr_read_tally_range", "pr_reset_tally",
            "pr_read_stats", "pr_reset_stats", "pr_set_tuning", "pr_get_tuning", "pr_run_batch", "pr_autotune",
-           "pr_prepare_batch", "pr_run_prepared", "pr_release_batch"]
+           "pr_prepare_batch", "pr_run_prepared", "pr_release_batch", "pr_run_batch_static"]
 
 
 class pr_material_desc(C.Structure):
@@ -142,6 +142,7 @@ def load():
     L.pr_reset_stats.argtypes = [vp, vp]
     L.pr_set_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     L.pr_run_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, vp]
+    L.pr_run_batch_static.argtypes = [vp, C.POINTER(pr_sim), i32, i32, vp]
     L.pr_autotune.argtypes = [vp, C.POINTER(pr_sim), i32, C.c_double, C.POINTER(pr_tuning), vp]
     L.pr_get_tuning.argtypes = [vp, C.POINTER(pr_tuning)]
     L.pr_prepare_batch.argtypes = [vp, C.POINTER(pr_sim), i32, i32, u64, C.POINTER(i32)]
@@ -384,6 +385,14 @@ class Context:
         prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
         st = _current_stream() if stream is None else C.c_void_p(stream)
         self._check(self.lib.pr_run_batch(self.h, arr, len(sims), prec, st))
+
+    def run_batch_static(self, sims, precision="fp32", stream=None):
+        """As run_batch, with descriptors and counters in the library's fixed device
+        scratch (no device allocation; overlapping calls on one GPU race)."""
+        arr = self._sims(sims)
+        prec = PRECISION[precision] if isinstance(precision, str) else int(precision)
+        st = _current_stream() if stream is None else C.c_void_p(stream)
+        self._check(self.lib.pr_run_batch_static(self.h, arr, len(sims), prec, st))
 
     def prepare_batch(self, sims, stride, precision="fp32") -> int:
         """Upload a batch once (sims as for run_batch); each run_prepared advances its ids by stride."""

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <limits>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -107,6 +108,18 @@ struct PreparedBatch {
     int nh = 0;
 };
 
+// Device scratch of pr_run_batch_static: the staged descriptors of a batch
+// (simulations, tally entries, bin-cache key bases) and its per-simulation
+// claim counters.  Each GPU the library runs on holds its own copy until the
+// process ends.  Host code never uses the array's name as an address: at
+// pr_init the device copy's address is looked up once per device
+// (hipGetSymbolAddress) and kept in g_scratch_dev.
+constexpr size_t kStaticScratchBytes = 2u << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+static void* g_scratch_dev[kMaxDevices] = {};
+static std::mutex g_scratch_mutex;
+
 // History-claim counters of runs without a caller workspace: a ring of slots,
 // each reused only after the stream of its next run has waited for the event
 // recorded behind the last run that used it, so runs on different streams never
@@ -146,6 +159,8 @@ struct pr_ctx {
     unsigned long long* scratch_stats = nullptr;
     int next_slot = 0;
     std::vector<PreparedBatch> prepared;
+    void* static_scratch = nullptr;     // this device's copy of `scratch` (pr_run_batch_static)
+    std::vector<char> static_host;      // host image of the descriptors staged there
 };
 
 namespace {
@@ -460,6 +475,15 @@ extern "C" int pr_init(pr_ctx** out, int hip_device, uint64_t seed) {
         int cus = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, hip_device) == hipSuccess && cus > 0)
             c->num_cus = cus;
+        // this device's copy of the static scratch, looked up once per device
+        if (hip_device < kMaxDevices) {
+            std::lock_guard<std::mutex> lock(g_scratch_mutex);
+            if (!g_scratch_dev[hip_device]) {
+                void* ptr = nullptr;
+                if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr) g_scratch_dev[hip_device] = ptr;
+            }
+            c->static_scratch = g_scratch_dev[hip_device];
+        }
     }
     *out = c;
     return PR_OK;
@@ -1589,6 +1613,51 @@ extern "C" int pr_run_batch(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_
     if (rc) return rc;
     if ((rc = validate_sims(c, sims, nsims))) return rc;
     if ((rc = run_batch_all(c, sims, nsims, (hipStream_t)stream, false))) return rc;
+    for (int i = 0; i < nsims; ++i)
+        for (int t = 0; t < sims[i].n_tallies; ++t) c->tallies[sims[i].tallies[t]].n_hist += sims[i].n;
+    return PR_OK;
+}
+
+extern "C" int pr_run_batch_static(pr_ctx* c, const pr_sim* sims, int32_t nsims, int32_t precision, void* stream) {
+    if (!c || !sims) return fail(c, PR_EINVAL, "null argument");
+    if (nsims < 1 || nsims > (1 << 20)) return fail(c, PR_EINVAL, "nsims must be in [1, 2^20]");
+    if (precision != PR_FP32_MIXED) return fail(c, PR_EINVAL, "batched runs use the PR_FP32_MIXED policy");
+    int rc = set_device(c);
+    if (rc) return rc;
+    if (!c->static_scratch) return fail(c, PR_EDEVICE, "the static scratch of device %d is not available", c->device);
+    if ((rc = validate_sims(c, sims, nsims))) return rc;
+    // plan every class, then place their descriptors side by side in the scratch
+    const std::vector<int> cls = batch_classes(c, sims, nsims);
+    ClassPlan plans[4];
+    size_t offs[4] = {0, 0, 0, 0}, total = 0;
+    bool used[4] = {false, false, false, false};
+    for (int k = 0; k < 4; ++k) {
+        std::vector<int> idx;
+        for (int i = 0; i < nsims; ++i)
+            if (cls[i] == k) idx.push_back(i);
+        if (idx.empty()) continue;
+        if ((rc = plan_batch_class(c, sims, idx, (k & 1) != 0, (k & 2) != 0, false, plans[k]))) return rc;
+        if (plans[k].B.total_histories == 0) continue;
+        offs[k] = total;
+        total += (plans[k].total + 255) & ~(size_t)255;
+        used[k] = true;
+    }
+    if (total > kStaticScratchBytes)
+        return fail(c, PR_EWORKSPACE, "batch descriptors need %zu bytes; the static scratch holds %zu", total,
+                    kStaticScratchBytes);
+    if (total == 0) return PR_OK;
+    if (c->static_host.size() < total) c->static_host.resize(total);
+    for (int k = 0; k < 4; ++k)
+        if (used[k]) pack_plan(plans[k], c->static_host.data() + offs[k]);
+    const hipStream_t st = (hipStream_t)stream;
+    // pageable source: the copy has consumed it when the call returns
+    HIPCHK(c, hipMemcpyAsync(c->static_scratch, c->static_host.data(), total, hipMemcpyHostToDevice, st));
+    for (int k = 0; k < 4; ++k) {
+        if (!used[k]) continue;
+        bind_plan(plans[k], (char*)c->static_scratch + offs[k]);
+        hipError_t e = launch_batch(plans[k].B, plans[k].slds, plans[k].grid_nav, plans[k].grid, plans[k].block, st);
+        if (e != hipSuccess) return hipfail(c, e, "batch kernel launch");
+    }
     for (int i = 0; i < nsims; ++i)
         for (int t = 0; t < sims[i].n_tallies; ++t) c->tallies[sims[i].tallies[t]].n_hist += sims[i].n;
     return PR_OK;
