@@ -79,12 +79,14 @@ def algorithmic_ops(stats: dict) -> float:
             + OPS_MODEL["scatter"][0] * stats["scatters"] + OPS_MODEL["history"][0] * stats["histories"])
 
 
-def alu_roofline(stats: dict, n: int, ms: float, kernel: str) -> dict:
+def alu_roofline(stats: dict, n: int, ms: float, kernel: str, workload: str) -> dict:
+    """The ALU roofline of one launch of `kernel` on `workload` (the key of its
+    measured traffic)."""
     per_launch = algorithmic_ops(stats) / max(1, stats["histories"]) * n
     achieved = per_launch / (ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
-            "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kernel), "traffic_unit": "bytes per launch",
-            "kernel": kernel, "ops_per_history": per_launch / n}
+            "frac": achieved / VALU_PEAK_TOPS, "traffic": measured_traffic(kernel + ":" + workload),
+            "traffic_unit": "bytes per launch", "kernel": kernel, "ops_per_history": per_launch / n}
 
 
 def cpu_info() -> dict:
@@ -183,7 +185,7 @@ def config_leg(torch, B, ctx, prob, tuning, steps, fp64_steps, plain_steps, kern
     leg = {"histories_per_step": n, "value": n / med * 1e3, "unit": "histories/s", "ms_per_step": med,
            "mean_ms_per_step": mean, "steps": steps, "tuning": ctx.get_tuning(),
            "steps_per_history": st["steps"] / max(1, st["histories"]),
-           "roofline": alu_roofline(st, n, med, kernel)}
+           "roofline": alu_roofline(st, n, med, kernel, tuning)}
     if hbm_bytes_per_score is not None:
         # tally traffic: one (sum w, sum w^2) pair per scored history into a tally far
         # larger than the caches, the bytes the algorithm must move at least
@@ -286,7 +288,7 @@ def main():
     out["ms_per_step"] = head_ms
     out["mean_ms_per_step"] = head_mean
     out["dtype"] = "f32" if fp32 else "f64"
-    out["roofline"] = alu_roofline(head_st, n, head_ms, "k_mixed<float>" if fp32 else "k_plain")
+    out["roofline"] = alu_roofline(head_st, n, head_ms, "k_mixed<float>" if fp32 else "k_plain", "sample")
     out["ops_model"] = {k: {"ops": v[0], "derivation": v[1]} for k, v in OPS_MODEL.items()}
     if fp32 and fp64:
         out["fp64_plain"] = {"value": n / fp64[0] * 1e3, "ms_per_step": fp64[0], "steps": args.fp64_steps}
