@@ -152,7 +152,6 @@ struct pr_ctx {
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     int grid_walk_cells = 0;            // FP32 grid walks pause after this many cells (0: never)
-    int regroup_steps = 0;              // FP32 single runs without a grid: regroup lanes every this many steps (0: never)
     DescSlot slots[4];
     int waves_per_simd = 4;             // FP32 kernels without a grid: variant built for 4 or 5 waves per SIMD
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
@@ -1179,6 +1178,12 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
         }
     }
     P.cache_slots = slots;
+    // FP32 runs with a tally scoring straight into global memory (neither
+    // privatised nor cached) score as a wave, with paired-lane atomics
+    P.paired = 0;
+    if (precision == PR_FP32_MIXED)
+        for (int i = 0; i < nt; ++i)
+            if (P.tallies[i].lds_offset < 0 && P.tallies[i].cache_base < 0) P.paired = 1;
     // the time of flight is tracked only when a chopper or a TOF axis needs it
     bool need_time = (g.kinds >> kChopperBit) & 1u;
     for (int i = 0; i < nt; ++i)
@@ -1195,8 +1200,6 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.chunk = P.has_grid && c->grid_chunk > 0 ? c->grid_chunk : c->chunk;
     P.waves = c->waves_per_simd;
     P.walk_cells = precision == PR_FP32_MIXED ? c->grid_walk_cells : 0;
-    P.regroup_steps = precision == PR_FP32_MIXED && !P.has_grid ? c->regroup_steps : 0;
-    P.block = 256;   // set by the launch
     return PR_OK;
 }
 
@@ -1228,18 +1231,11 @@ static int run_single(pr_ctx* c, int32_t geom, int32_t src, const int32_t* talli
     if (precision == PR_FP64_PLAIN) {
         e = launch_plain(P, records != nullptr, st);
     } else {
-        int block = std::min(c->mixed_block, mixed_max_block(P));
-        P.block = block;
         if (P.scene_in_lds && mixed_lds_bytes(P) > kLdsPerCu) P.scene_in_lds = 0;   // tallies leave no room
-        // regrouping needs room for its exchange buffer beside the tallies; else the
-        // run goes without it
-        if (P.regroup_steps > 0 && mixed_lds_bytes(P) > kLdsPerCu) P.regroup_steps = 0;
         int lds = mixed_lds_bytes(P);
         if (lds > kLdsPerCu) return fail(c, PR_EINVAL, "scene and tallies need %d bytes of LDS", lds);
-        if (P.has_grid && P.scene_in_lds) {
-            block = grid_block(c, [&](int b) { return mixed_occupancy(P, b); });
-            P.block = block;
-        }
+        int block = std::min(c->mixed_block, mixed_max_block(P));
+        if (P.has_grid && P.scene_in_lds) block = grid_block(c, [&](int b) { return mixed_occupancy(P, b); });
         int per_cu = c->mixed_blocks_per_cu > 0 ? c->mixed_blocks_per_cu : mixed_occupancy(P, block);
         uint64_t want = (n + block - 1) / block;
         uint64_t grid = std::min<uint64_t>((uint64_t)per_cu * (uint64_t)c->num_cus, want);
@@ -1400,9 +1396,7 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
         return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
     if (t->grid_walk_cells != 0 && (t->grid_walk_cells < 2 || t->grid_walk_cells > 1024))
         return fail(c, PR_EINVAL, "tuning.grid_walk_cells must be 0 or 2..1024");
-    if (t->regroup_steps < 0 || t->regroup_steps > 256) return fail(c, PR_EINVAL, "tuning.regroup_steps must be 0..256");
     c->grid_walk_cells = t->grid_walk_cells;
-    c->regroup_steps = t->regroup_steps;
     c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
     c->grid_chunk = t->grid_chunk;
@@ -1425,7 +1419,6 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->waves_per_simd = c->waves_per_simd;
     t->grid_chunk = c->grid_chunk;
     t->grid_walk_cells = c->grid_walk_cells;
-    t->regroup_steps = c->regroup_steps;
     return PR_OK;
 }
 

@@ -223,8 +223,8 @@ struct Params {
     int32_t waves;                 // FP32 persistent policy: waves per SIMD the launched variant is built for (4 or 5)
     int32_t has_fc;                // some tally of the run fires at the first collision
     int32_t walk_cells;            // FP32 grid walks pause after this many cells (0: never)
-    int32_t regroup_steps;         // FP32 without a grid: regroup the block's lanes every this many steps (0: never)
-    int32_t block;                 // threads per block of the launch
+    int32_t paired;                // FP32 without a grid: a tally scores straight into global memory, so the
+                                   // wave's scores leave as paired-lane atomics (the FP64 kernels always do)
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)

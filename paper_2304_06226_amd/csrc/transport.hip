@@ -156,18 +156,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
 // LDS of a mixed-policy block: [privatised tallies (doubles)] [bin-cache values
 // (2 doubles per slot)] [bin-cache keys (u32 per slot)] [scene, when staged:
 // volumes, materials, Bragg tables, daughter lists, grids, grid cells]
-// [regroup exchange buffer, when regrouping]
 struct LdsLayout {
-    int cache_vals, cache_keys, vols, mats, fams, children, grids, cell_start, cell_items, boxes, xchg,
-        bytes;   // byte offsets
+    int cache_vals, cache_keys, vols, mats, fams, children, grids, cell_start, cell_items, boxes, bytes;   // byte offsets
 };
 
 __host__ __device__ inline int align16(int x) { return (x + 15) & ~15; }
-
-// 32-bit words of a particle state that move with it when a block regroups its
-// lanes (k_regroup): 21, and 2 more for the event hash of recorded runs
-__host__ __device__ inline int xchg_words(const Params& P) { return P.records ? 23 : 21; }
-static_assert(kMaxSteps < (1 << 14) && PR_END_OUTSIDE < 16, "exchanged steps, scatterings and end codes are packed");
 
 __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
     LdsLayout L;
@@ -196,9 +189,6 @@ __host__ __device__ inline LdsLayout lds_layout(const Params& P) {
     off = align16(off + st * P.n_cell_items * 4);
     L.boxes = off;
     off = align16(off + sb * P.n_vols * (int)sizeof(BoxT<float>));
-    // regrouping: the exchange buffer (xchg_words per thread) and one word per wave
-    L.xchg = off;
-    if (P.regroup_steps > 0) off = align16(off + (xchg_words(P) * P.block + P.block / kWave) * 4);
     L.bytes = off;
     return L;
 }
@@ -368,12 +358,15 @@ __device__ __forceinline__ int start_region_of(const Params& P, const SceneT<R>&
 // all are), the histories that ended since the last refill are scored together,
 // and the idle lanes start the next histories of the wave's chunk (claiming a new
 // chunk when it is used up).
-template <class R, bool REC, bool GRID>
+template <class R, bool REC, bool GRID, bool PAIR>
 __device__ __forceinline__ void wave_refill(const Params& P, const SceneT<R>& S, PState<R>& s, bool& pending,
                                             WaveClaim& wc, Counters& cnt, double* lds, double* cvals, uint32_t* ckeys,
                                             int start_region) {
-    // FP64: scores leave the wave as paired-lane atomics; FP32: per-lane atomics
-    constexpr bool kPaired = sizeof(R) == 8;
+    // FP64, and FP32 runs whose tallies score straight into global memory: the
+    // wave scores together and the global scores leave as paired-lane atomics
+    // (one 16-byte request per score instead of two 8-byte ones: half the memory
+    // transactions); other FP32 runs: per-lane scoring, which holds fewer registers
+    constexpr bool kPaired = sizeof(R) == 8 || PAIR;
     const bool idle = s.term != 0;
     const unsigned long long idle_mask = __ballot(idle);
     const int n_idle = __popcll(idle_mask);
@@ -436,7 +429,9 @@ __device__ __forceinline__ void wave_refill(const Params& P, const SceneT<R>& S,
 // choice.
 // Block sizes: up to 1024 threads for the FP32 kernels without a grid (fewer
 // blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
-template <class R, bool REC, bool SLDS, bool GRID, int WPE>
+// PAIR (FP32 without a grid): paired-lane global scores, for runs with a tally
+// that scores straight into global memory.
+template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
     extern __shared__ double lds[];
@@ -456,7 +451,7 @@ void k_mixed(Params P) {
     WaveClaim wc = {0, 0, false};
     const int start_region = start_region_of<R, GRID>(P, S);
     for (;;) {
-        wave_refill<R, REC, GRID>(P, S, s, pending, wc, cnt, lds, cvals, ckeys, start_region);
+        wave_refill<R, REC, GRID, PAIR>(P, S, s, pending, wc, cnt, lds, cvals, ckeys, start_region);
         if (__ballot(s.term == 0) == 0ull) {
             if (wc.exhausted && __ballot(pending) == 0ull) break;
             continue;
@@ -476,183 +471,6 @@ void k_mixed(Params P) {
                 score_wave(T, b, s.w, lds, cvals, ckeys);
             }
         }
-    }
-    flush_counters(cnt, P.stats);
-    __syncthreads();
-    block_merge(P, lds, cvals, ckeys);
-}
-
-// ------------------------------------------------------------------------
-// FP32 mixed policy with block-wide regrouping of the lanes
-// ------------------------------------------------------------------------
-// The event loop of the paper's GPU flow (Section 3.1) separates the particles
-// by what happens to them next; in a persistent kernel the lanes of one wave
-// instead hold histories at different stages, and a wave runs every branch that
-// any of its lanes takes.  Here the waves of a block run regroup_steps steps on
-// their own (refilling as k_mixed does), then the block sorts its lanes through
-// LDS by class, so that each wave holds histories of one class for the next
-// steps and the idle lanes gather into whole waves that refill together.  A
-// history's draws depend only on its id and draw index, so where it runs changes
-// nothing in it: the records equal k_mixed's, and the tallies up to summation
-// order.
-
-// Class of a lane: 0 a live history in a volume with a material (its next step
-// samples a flight and may collide), 1 a live history in a vacuum volume (its
-// next step flies to a boundary), 2 an idle lane or an ended history (it waits
-// for its wave's next refill).
-__device__ __forceinline__ int regroup_class(const PState<float>& s, const SceneT<float>& S) {
-    if (s.term != 0) return 2;
-    return S.vols[s.region].mat >= 0 ? 0 : 1;
-}
-
-// Word f of the state in slot x of the exchange buffer is x[f * nb]: position,
-// direction, wavelength, time, weight, id, draw index with the buffered draw
-// count, the buffered draws, region, steps with scatterings and end code, cached
-// material with the pending flag, and (records) the event hash.  Idle lanes (no
-// history, nothing to score) write only the last two of these.
-template <bool REC>
-__device__ __forceinline__ void xchg_put(uint32_t* x, int nb, const PState<float>& s, bool pending) {
-    if (s.term == 0 || pending) {
-        x[0 * nb] = __float_as_uint(s.p[0]);
-        x[1 * nb] = __float_as_uint(s.p[1]);
-        x[2 * nb] = __float_as_uint(s.p[2]);
-        x[3 * nb] = __float_as_uint(s.u[0]);
-        x[4 * nb] = __float_as_uint(s.u[1]);
-        x[5 * nb] = __float_as_uint(s.u[2]);
-        x[6 * nb] = __float_as_uint(s.lam);
-        x[7 * nb] = __float_as_uint(s.t);
-        const unsigned long long w = (unsigned long long)__double_as_longlong(s.w);
-        x[8 * nb] = (uint32_t)w;
-        x[9 * nb] = (uint32_t)(w >> 32);
-        x[10 * nb] = (uint32_t)s.h;
-        x[11 * nb] = (uint32_t)(s.h >> 32);
-        // draw index (below 2^29: at most a few draws per step, PR_MAX_STEPS steps) and buffered count (<= 5)
-        x[12 * nb] = s.k | ((uint32_t)s.nbuf << 29);
-        x[13 * nb] = __float_as_uint(s.ub0);
-        x[14 * nb] = __float_as_uint(s.ub1);
-        x[15 * nb] = __float_as_uint(s.ub2);
-        x[16 * nb] = __float_as_uint(s.ub3);
-        x[17 * nb] = __float_as_uint(s.ub4);
-        x[18 * nb] = (uint32_t)s.region;
-        if (REC) {
-            x[21 * nb] = (uint32_t)s.hash;
-            x[22 * nb] = (uint32_t)(s.hash >> 32);
-        }
-    }
-    // steps and scatterings (each <= PR_MAX_STEPS < 2^14) and the end code (< 16)
-    x[19 * nb] = (uint32_t)s.steps | ((uint32_t)s.nscat << 14) | ((uint32_t)s.term << 28);
-    x[20 * nb] = (uint32_t)(s.xs_mat + 2) | (pending ? 0x80000000u : 0u);
-}
-
-// Read the state in slot x.  The lane's cached cross sections stay valid when
-// the arriving history has the same material and wavelength as the lane's last
-// one (always, for a monochromatic source in one material); otherwise they are
-// reloaded at its next step in a material.
-template <bool REC>
-__device__ __forceinline__ void xchg_get(const uint32_t* x, int nb, PState<float>& s, bool& pending) {
-    const int old_mat = s.xs_mat;
-    const float old_lam = s.lam;
-    s.p[0] = __uint_as_float(x[0 * nb]);
-    s.p[1] = __uint_as_float(x[1 * nb]);
-    s.p[2] = __uint_as_float(x[2 * nb]);
-    s.u[0] = __uint_as_float(x[3 * nb]);
-    s.u[1] = __uint_as_float(x[4 * nb]);
-    s.u[2] = __uint_as_float(x[5 * nb]);
-    s.lam = __uint_as_float(x[6 * nb]);
-    s.t = __uint_as_float(x[7 * nb]);
-    s.w = __longlong_as_double((long long)(((unsigned long long)x[9 * nb] << 32) | x[8 * nb]));
-    s.h = ((uint64_t)x[11 * nb] << 32) | x[10 * nb];
-    const uint32_t kb = x[12 * nb];
-    s.k = kb & 0x1FFFFFFFu;
-    s.nbuf = (int32_t)(kb >> 29);
-    s.ub0 = __uint_as_float(x[13 * nb]);
-    s.ub1 = __uint_as_float(x[14 * nb]);
-    s.ub2 = __uint_as_float(x[15 * nb]);
-    s.ub3 = __uint_as_float(x[16 * nb]);
-    s.ub4 = __uint_as_float(x[17 * nb]);
-    s.region = (int32_t)x[18 * nb];
-    const uint32_t sn = x[19 * nb];
-    s.steps = (int32_t)(sn & 0x3FFFu);
-    s.nscat = (int32_t)((sn >> 14) & 0x3FFFu);
-    s.term = (int32_t)(sn >> 28);
-    if (REC) s.hash = ((uint64_t)x[22 * nb] << 32) | x[21 * nb];
-    const uint32_t f = x[20 * nb];
-    pending = (f >> 31) != 0u;
-    const int in_mat = (int)(f & 0x7FFFFFFFu) - 2;
-    s.xs_mat = in_mat >= 0 && in_mat == old_mat && s.lam == old_lam ? in_mat : -2;
-}
-
-// Regroup the block's lanes (every thread of the block calls it): each state
-// moves through LDS to the slot of its class, classes in order (class 0 from
-// slot 0, then class 1, then class 2), waves in order within a class.  wword
-// holds one word per wave: its class-0 and class-1 counts and whether the wave
-// has finished (all its histories claimed, run and scored).  Returns true, with
-// nothing moved, when every wave of the block has finished.
-template <bool REC>
-__device__ __forceinline__ bool regroup(PState<float>& s, bool& pending, bool wave_done, const SceneT<float>& S,
-                                        uint32_t* xb, uint32_t* wword) {
-    const int nb = (int)blockDim.x, tid = (int)threadIdx.x, w = tid / kWave, nw = nb / kWave;
-    const int cls = regroup_class(s, S);
-    const unsigned long long m0 = __ballot(cls == 0), m1 = __ballot(cls == 1);
-    if (lane_id() == 0)
-        wword[w] = (uint32_t)__popcll(m0) | ((uint32_t)__popcll(m1) << 8) | (wave_done ? 1u << 16 : 0u);
-    __syncthreads();
-    int t0 = 0, t1 = 0, b0 = 0, b1 = 0, b2 = 0;
-    bool all_done = true;
-    for (int i = 0; i < nw; ++i) {
-        const uint32_t v = wword[i];
-        const int c0 = (int)(v & 0xFFu), c1 = (int)((v >> 8) & 0xFFu);
-        t0 += c0;
-        t1 += c1;
-        if (i < w) {
-            b0 += c0;
-            b1 += c1;
-            b2 += kWave - c0 - c1;
-        }
-        all_done = all_done && ((v >> 16) & 1u) != 0u;
-    }
-    if (all_done) return true;
-    const unsigned long long mine = cls == 0 ? m0 : (cls == 1 ? m1 : ~(m0 | m1));
-    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mine >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mine, 0u));
-    const int dst = cls == 0 ? b0 + rank : (cls == 1 ? t0 + b1 + rank : t0 + t1 + b2 + rank);
-    xchg_put<REC>(xb + dst, nb, s, pending);
-    __syncthreads();
-    xchg_get<REC>(xb + tid, nb, s, pending);
-    return false;
-}
-
-// FP32, no daughter grid, four waves per SIMD; P.regroup_steps > 0 and the
-// exchange buffer in LDS (xchg_words per thread).
-template <bool REC, bool SLDS>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_regroup(Params P) {
-    extern __shared__ double lds[];
-    const LdsLayout L = lds_layout(P);
-    char* base = (char*)lds;
-    double* cvals = (double*)(base + L.cache_vals);
-    uint32_t* ckeys = (uint32_t*)(base + L.cache_keys);
-    uint32_t* xb = (uint32_t*)(base + L.xchg);
-    uint32_t* wword = xb + xchg_words(P) * (int)blockDim.x;
-    block_stage<SLDS, false>(P, base, L);
-    const SceneT<float> S = PersistentScene<float, SLDS, false>::get(P, base, L);
-
-    Counters cnt = {};
-    PState<float> s;
-    s.term = 1;
-    s.xs_mat = -2;
-    s.lam = -1.0f;
-    bool pending = false;
-    WaveClaim wc = {0, 0, false};
-    const int start_region = start_region_of<float, false>(P, S);
-    for (;;) {
-        for (int it = 0; it < P.regroup_steps; ++it) {
-            wave_refill<float, REC, false>(P, S, s, pending, wc, cnt, lds, cvals, ckeys, start_region);
-            if (s.term == 0) {
-                step<float, REC, false>(s, S, P.seed, 0);
-                pending = s.term != 0;
-            }
-        }
-        const bool wave_done = wc.exhausted && __ballot(s.term == 0 || pending) == 0ull;
-        if (regroup<REC>(s, pending, wave_done, S, xb, wword)) break;
     }
     flush_counters(cnt, P.stats);
     __syncthreads();
@@ -974,27 +792,30 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
 }
 
 // variant index: FP32: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five
-// waves per SIMD (no grid only); FP64 (scene in global memory): 6, grid 7;
-// FP32 regrouping (no grid): 8, scene in LDS 9
+// waves per SIMD (no grid only), bit 3 paired global scores (no grid only);
+// FP64 (scene in global memory): 6, grid 7
 static int mixed_variant(const Params& P) {
     if (P.fp64) return P.has_grid ? 7 : 6;
-    if (P.regroup_steps > 0) return P.scene_in_lds ? 9 : 8;
-    return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0);
+    return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
+           (P.paired && !P.has_grid ? 8 : 0);
 }
 
+// the kernel of a variant index
 template <bool REC>
-static void launch_mixed_t(const Params& P, int grid, int block, int lds, hipStream_t st) {
-    switch (mixed_variant(P)) {
-    case 0: hipLaunchKernelGGL((k_mixed<float, REC, false, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 1: hipLaunchKernelGGL((k_mixed<float, REC, true, false, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 2: hipLaunchKernelGGL((k_mixed<float, REC, false, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 3: hipLaunchKernelGGL((k_mixed<float, REC, true, true, 4>), dim3(grid), dim3(block), lds, st, P); break;
-    case 4: hipLaunchKernelGGL((k_mixed<float, REC, false, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
-    case 5: hipLaunchKernelGGL((k_mixed<float, REC, true, false, 5>), dim3(grid), dim3(block), lds, st, P); break;
-    case 6: hipLaunchKernelGGL((k_mixed<double, REC, false, false, 2>), dim3(grid), dim3(block), lds, st, P); break;
-    case 7: hipLaunchKernelGGL((k_mixed<double, REC, false, true, 3>), dim3(grid), dim3(block), lds, st, P); break;
-    case 8: hipLaunchKernelGGL((k_regroup<REC, false>), dim3(grid), dim3(block), lds, st, P); break;
-    default: hipLaunchKernelGGL((k_regroup<REC, true>), dim3(grid), dim3(block), lds, st, P); break;
+static const void* mixed_kernel(int v) {
+    switch (v) {
+    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false>;
+    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false>;
+    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false>;
+    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false>;
+    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false>;
+    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false>;
+    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false>;
+    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false>;
+    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true>;
+    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true>;
+    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true>;
+    default: return (const void*)k_mixed<float, REC, true, false, 5, true>;   // 13
     }
 }
 
@@ -1002,27 +823,16 @@ hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStrea
     if (P.n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.counter, 1);
     const int lds = mixed_lds_bytes(P);
-    if (rec) launch_mixed_t<true>(P, grid, block, lds, st);
-    else launch_mixed_t<false>(P, grid, block, lds, st);
-    return hipGetLastError();
+    const int v = mixed_variant(P);
+    void* args[] = {(void*)&P};
+    return hipLaunchKernel(rec ? mixed_kernel<true>(v) : mixed_kernel<false>(v), dim3(grid), dim3(block), args,
+                           (size_t)lds, st);
 }
 
 int mixed_occupancy(const Params& P, int block) {
     int nb = 0;
     const int lds = mixed_lds_bytes(P);
-    hipError_t e;
-    switch (mixed_variant(P)) {
-    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, false, 4>, block, lds); break;
-    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, false, 4>, block, lds); break;
-    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, true, 4>, block, lds); break;
-    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, true, 4>, block, lds); break;
-    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, false, false, 5>, block, lds); break;
-    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<float, false, true, false, 5>, block, lds); break;
-    case 6: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<double, false, false, false, 2>, block, lds); break;
-    case 7: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_mixed<double, false, false, true, 3>, block, lds); break;
-    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_regroup<false, false>, block, lds); break;
-    default: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_regroup<false, true>, block, lds); break;
-    }
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mixed_kernel<false>(mixed_variant(P)), block, lds);
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }

@@ -18,17 +18,17 @@ per step: a wave no longer waits for its lanes' longest walk."""
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0, "regroup_steps": 0},
+               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "guide": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0, "regroup_steps": 0},
+              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0, "regroup_steps": 0},
+               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 0, "chunk": 64, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 3, "regroup_steps": 0},
+                "bin_cache_slots": 0, "chunk": 64, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 3},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0, "regroup_steps": 0},
+                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5, "grid_chunk": 128, "grid_walk_cells": 3, "regroup_steps": 0},
+              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5, "grid_chunk": 128, "grid_walk_cells": 3},
 }
 
 # Launch tunings of the PR_FP64_PERSISTENT policy (the same knobs; waves_per_simd
@@ -43,5 +43,5 @@ TUNED_FP64_PERSISTENT = {
     "imaging": dict(TUNED["imaging"], grid_walk_cells=0),
     "paper_guide": dict(TUNED["paper_guide"], refill_threshold=32),
     "paper_chopper": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0, "regroup_steps": 0},
+                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
 }
