@@ -1288,9 +1288,10 @@ constexpr int64_t kOffSlice = 1ll << 62;
 // term: the history's termination code, or kTermFirstCollision at its first
 // collision.  q: the history's divergence angles, computed once for all tallies
 // (PRE), or left to each divergence axis to compute (fewer values live across
-// the loop).
-template <class R, bool PRE = true>
-__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
+// the loop).  SLICED: the tally is privatised as a slice (a separate instance,
+// so that the bins of other tallies carry none of the slice arithmetic).
+template <class R, bool PRE, bool SLICED>
+__device__ __forceinline__ int64_t tally_bin_t(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
     const TallyHead h = T.head;
     if (!(((h.term_mask >> term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
           (h.volume < 0 || h.volume == s.region)))
@@ -1303,6 +1304,8 @@ __device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>&
     }
     int64_t flat = 0, slice = 0;
     bool in_slice = true;
+    (void)slice;
+    (void)in_slice;
     for (int a = 0; a < h.naxes; ++a) {
         const TallyAxis& A = T.ax[a];
         const int32_t quantity = A.quantity, n = A.nbins;
@@ -1329,13 +1332,18 @@ __device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>&
         if (x == hi || b >= n) b = n - 1;
         if (b < 0) b = 0;
         flat = flat * n + b;
-        if (h.fix_axis >= 0) {   // uniform: only sliced tallies pay
+        if constexpr (SLICED) {
             if (a == h.fix_axis) in_slice = b == h.fix_bin;
             else slice = slice * n + b;
         }
     }
-    if (h.fix_axis < 0) return flat;
+    if constexpr (!SLICED) return flat;
     return in_slice ? slice : (flat | kOffSlice);
+}
+
+template <class R, bool PRE = true>
+__device__ __forceinline__ int64_t tally_bin(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
+    return T.head.fix_axis >= 0 ? tally_bin_t<R, PRE, true>(T, s, term, q) : tally_bin_t<R, PRE, false>(T, s, term, q);
 }
 
 // flat index of bin i of a tally's slice (inverse of the slice index)

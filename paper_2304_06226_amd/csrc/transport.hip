@@ -296,129 +296,6 @@ struct PersistentScene<double, false, GRID> {
     }
 };
 
-// Block prologue of a persistent launch: stage the FP32 scene tables into LDS
-// (SLDS) and clear the privatised tallies and the bin cache.
-template <bool SLDS, bool GRID>
-__device__ __forceinline__ void block_stage(const Params& P, char* base, const LdsLayout& L) {
-    double* lds = (double*)base;
-    uint32_t* ckeys = (uint32_t*)(base + L.cache_keys);
-    if (SLDS) {
-        if (!GRID) copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
-        if (GRID) copy_words(base + L.boxes, P.boxes_f, P.n_vols * (int)sizeof(BoxT<float>));
-        copy_words(base + L.mats, P.mats_f, P.n_mats * (int)sizeof(MatT<float>));
-        copy_words(base + L.fams, P.fams_f, P.n_fams * (int)sizeof(FamT<float>));
-        copy_words(base + L.children, P.children, P.n_children * 4);
-        copy_words(base + L.grids, P.grids_f, P.n_grids * (int)sizeof(GridT<float>));
-        copy_words(base + L.cell_start, P.cell_start, P.n_cell_start * 4);
-        copy_words(base + L.cell_items, P.cell_items, P.n_cell_items * 4);
-    }
-    for (int i = threadIdx.x; i < P.lds_tally_doubles + 2 * P.cache_slots; i += blockDim.x) lds[i] = 0.0;
-    for (int i = threadIdx.x; i < P.cache_slots; i += blockDim.x) ckeys[i] = kEmptyKey;
-    __syncthreads();
-}
-
-// Block epilogue: merge the block's privatised tallies and cached bins into the
-// global tallies (non-zero bins only).
-__device__ __forceinline__ void block_merge(const Params& P, double* lds, const double* cvals, const uint32_t* ckeys) {
-    for (int t = 0; t < P.n_tallies; ++t) {
-        const TallyDev& T = P.tallies[t];
-        if (T.cache_base >= 0) {
-            const int ns = 1 << T.cache_bits;
-            for (int base = 0; base < ns; base += blockDim.x) {
-                const int i = base + (int)threadIdx.x;
-                const int slot = T.cache_base + i;
-                const uint32_t key = i < ns ? ckeys[slot] : kEmptyKey;
-                const bool used = key != kEmptyKey;
-                add_pairs_wave<false>(T.sw, used ? (int64_t)key : 0, used ? cvals[2 * slot] : 0.0,
-                                      used ? cvals[2 * slot + 1] : 0.0, used);
-            }
-        }
-        if (T.lds_offset < 0) continue;
-        merge_pairs(T.sw, lds + T.lds_offset, T.lds_bins, [&](int64_t i) { return slice_to_flat(T, i); });
-    }
-}
-
-// The wave's current chunk of history indices [cnext, cend), claimed with one
-// atomic per chunk; all values are wave-uniform.
-struct WaveClaim {
-    unsigned long long cnext, cend;
-    bool exhausted;   // the run's histories are all claimed and this chunk is used up
-};
-
-// region of a pencil source's start point (every history starts there: located
-// once per wave), else -2
-template <class R, bool GRID>
-__device__ __forceinline__ int start_region_of(const Params& P, const SceneT<R>& S) {
-    if (P.src.kind != PR_PENCIL) return -2;
-    const R o[3] = {(R)P.src.o[0], (R)P.src.o[1], (R)P.src.o[2]};
-    return locate<R, GRID>(S, o, 0);
-}
-
-// Refill of a persistent wave.  Once refill_threshold of its lanes are idle (or
-// all are), the histories that ended since the last refill are scored together,
-// and the idle lanes start the next histories of the wave's chunk (claiming a new
-// chunk when it is used up).
-template <class R, bool REC, bool GRID, bool PAIR>
-__device__ __forceinline__ void wave_refill(const Params& P, const SceneT<R>& S, PState<R>& s, bool& pending,
-                                            WaveClaim& wc, Counters& cnt, double* lds, double* cvals, uint32_t* ckeys,
-                                            int start_region) {
-    // FP64, and FP32 runs whose tallies score straight into global memory: the
-    // wave scores together and the global scores leave as paired-lane atomics
-    // (one 16-byte request per score instead of two 8-byte ones: half the memory
-    // transactions); other FP32 runs: per-lane scoring, which holds fewer registers
-    constexpr bool kPaired = sizeof(R) == 8 || PAIR;
-    const bool idle = s.term != 0;
-    const unsigned long long idle_mask = __ballot(idle);
-    const int n_idle = __popcll(idle_mask);
-    if (n_idle < P.refill_threshold && n_idle != kWave) return;
-    if (kPaired && __ballot(pending) != 0ull) {
-        const bool scoring = pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
-        const HistAngles<R> q = hist_angles<R>(s, P.qmask);
-        for (int t = 0; t < P.n_tallies; ++t) {
-            const TallyDev& T = P.tallies[t];
-            const int64_t b = scoring ? tally_bin<R>(T, s, s.term, q) : -1;
-            score_wave(T, b, s.w, lds, cvals, ckeys);
-        }
-    }
-    if (pending) {
-        if (!kPaired && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT)) {
-            const HistAngles<R> q = hist_angles<R>(s, P.qmask);
-            for (int t = 0; t < P.n_tallies; ++t) {
-                const TallyDev& T = P.tallies[t];
-                score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
-            }
-        }
-        if (REC) write_record<R>(P.records + (s.h - P.first), s);
-        count_end<R>(cnt, s);
-        pending = false;
-    }
-    const unsigned long long chunk = (unsigned long long)P.chunk;
-    if (!wc.exhausted && wc.cnext >= wc.cend) {
-        const int leader = __ffsll((long long)idle_mask) - 1;
-        unsigned long long got = 0;
-        if (lane_id() == leader) got = atomicAdd(P.counter, chunk);
-        got = __shfl(got, leader, kWave);
-        wc.cnext = got;
-        wc.cend = got + chunk < P.n ? got + chunk : P.n;
-        if (got >= P.n) wc.exhausted = true;
-    }
-    if (!wc.exhausted) {
-        const unsigned long long avail = wc.cend - wc.cnext;
-        const unsigned long long take = (unsigned long long)n_idle < avail ? (unsigned long long)n_idle : avail;
-        if (idle) {
-            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
-            if ((unsigned long long)rank < take) {
-                source<R, REC, GRID>(s, P.src, S, P.seed, P.first + wc.cnext + (unsigned long long)rank, 0,
-                                     start_region);
-                pending = s.term != 0;   // born outside the world: counted at the next refill
-            }
-        }
-        wc.cnext += take;
-        if (wc.cnext >= wc.cend && wc.cend >= P.n) wc.exhausted = true;
-    }
-}
-
 // R = float: the FP32 mixed policy; R = double: the persistent FP64 policy, whose
 // histories take exactly the arithmetic of the plain kernel.
 // WPE resident waves per SIMD (FP32: 4 or 5, grid variants 4; FP64: 2, grid 3,
@@ -434,12 +311,29 @@ __device__ __forceinline__ void wave_refill(const Params& P, const SceneT<R>& S,
 template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
+    // FP64, and FP32 runs whose tallies score straight into global memory: the
+    // wave scores together and the global scores leave as paired-lane atomics
+    // (one 16-byte request per score instead of two 8-byte ones: half the memory
+    // transactions); other FP32 runs: per-lane scoring, which holds fewer registers
+    constexpr bool kPaired = sizeof(R) == 8 || PAIR;
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
     char* base = (char*)lds;
     double* cvals = (double*)(base + L.cache_vals);
     uint32_t* ckeys = (uint32_t*)(base + L.cache_keys);
-    block_stage<SLDS, GRID>(P, base, L);
+    if (SLDS) {
+        if (!GRID) copy_words(base + L.vols, P.vols_f, P.n_vols * (int)sizeof(VolT<float>));
+        if (GRID) copy_words(base + L.boxes, P.boxes_f, P.n_vols * (int)sizeof(BoxT<float>));
+        copy_words(base + L.mats, P.mats_f, P.n_mats * (int)sizeof(MatT<float>));
+        copy_words(base + L.fams, P.fams_f, P.n_fams * (int)sizeof(FamT<float>));
+        copy_words(base + L.children, P.children, P.n_children * 4);
+        copy_words(base + L.grids, P.grids_f, P.n_grids * (int)sizeof(GridT<float>));
+        copy_words(base + L.cell_start, P.cell_start, P.n_cell_start * 4);
+        copy_words(base + L.cell_items, P.cell_items, P.n_cell_items * 4);
+    }
+    for (int i = threadIdx.x; i < P.lds_tally_doubles + 2 * P.cache_slots; i += blockDim.x) lds[i] = 0.0;
+    for (int i = threadIdx.x; i < P.cache_slots; i += blockDim.x) ckeys[i] = kEmptyKey;
+    __syncthreads();
     const SceneT<R> S = PersistentScene<R, SLDS, GRID>::get(P, base, L);
 
     Counters cnt = {};
@@ -448,12 +342,73 @@ void k_mixed(Params P) {
     s.xs_mat = -2;         // no cached cross sections
     s.lam = (R)-1;
     bool pending = false;  // finished history not yet scored
-    WaveClaim wc = {0, 0, false};
-    const int start_region = start_region_of<R, GRID>(P, S);
+    bool exhausted = false;
+    // the wave's current chunk of history indices [cnext, cend), claimed with one
+    // atomic per chunk; values are wave-uniform
+    unsigned long long cnext = 0, cend = 0;
+    const unsigned long long chunk = (unsigned long long)P.chunk;
+    const int lane = lane_id();
+    // a pencil starts every history at the same point: locate it once
+    int start_region = -2;
+    if (P.src.kind == PR_PENCIL) {
+        const R o[3] = {(R)P.src.o[0], (R)P.src.o[1], (R)P.src.o[2]};
+        start_region = locate<R, GRID>(S, o, 0);
+    }
     for (;;) {
-        wave_refill<R, REC, GRID, PAIR>(P, S, s, pending, wc, cnt, lds, cvals, ckeys, start_region);
+        const bool idle = s.term != 0;
+        const unsigned long long idle_mask = __ballot(idle);
+        const int n_idle = __popcll(idle_mask);
+        if (n_idle >= P.refill_threshold || n_idle == kWave) {
+            // score the histories that ended since the last refill, all together
+            if (kPaired && __ballot(pending) != 0ull) {
+                const bool scoring =
+                    pending && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
+                const HistAngles<R> q = hist_angles<R>(s, P.qmask);
+                for (int t = 0; t < P.n_tallies; ++t) {
+                    const TallyDev& T = P.tallies[t];
+                    const int64_t b = scoring ? tally_bin<R>(T, s, s.term, q) : -1;
+                    score_wave(T, b, s.w, lds, cvals, ckeys);
+                }
+            }
+            if (pending) {
+                if (!kPaired && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT)) {
+                    const HistAngles<R> q = hist_angles<R>(s, P.qmask);
+                    for (int t = 0; t < P.n_tallies; ++t) {
+                        const TallyDev& T = P.tallies[t];
+                        score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
+                    }
+                }
+                if (REC) write_record<R>(P.records + (s.h - P.first), s);
+                count_end<R>(cnt, s);
+                pending = false;
+            }
+            if (!exhausted && cnext >= cend) {
+                const int leader = __ffsll((long long)idle_mask) - 1;
+                unsigned long long got = 0;
+                if (lane == leader) got = atomicAdd(P.counter, chunk);
+                got = __shfl(got, leader, kWave);
+                cnext = got;
+                cend = got + chunk < P.n ? got + chunk : P.n;
+                if (got >= P.n) exhausted = true;
+            }
+            if (!exhausted) {
+                const unsigned long long avail = cend - cnext;
+                const unsigned long long take = (unsigned long long)n_idle < avail ? (unsigned long long)n_idle : avail;
+                if (idle) {
+                    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
+                    if ((unsigned long long)rank < take) {
+                        source<R, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
+                                             start_region);
+                        pending = s.term != 0;   // born outside the world: counted at the next refill
+                    }
+                }
+                cnext += take;
+                if (cnext >= cend && cend >= P.n) exhausted = true;
+            }
+        }
         if (__ballot(s.term == 0) == 0ull) {
-            if (wc.exhausted && __ballot(pending) == 0ull) break;
+            if (exhausted && __ballot(pending) == 0ull) break;
             continue;
         }
         bool first = false;
@@ -474,7 +429,23 @@ void k_mixed(Params P) {
     }
     flush_counters(cnt, P.stats);
     __syncthreads();
-    block_merge(P, lds, cvals, ckeys);
+    // merge the block's privatised tallies and cached bins (non-zero bins only)
+    for (int t = 0; t < P.n_tallies; ++t) {
+        const TallyDev& T = P.tallies[t];
+        if (T.cache_base >= 0) {
+            const int ns = 1 << T.cache_bits;
+            for (int base = 0; base < ns; base += blockDim.x) {
+                const int i = base + (int)threadIdx.x;
+                const int slot = T.cache_base + i;
+                const uint32_t key = i < ns ? ckeys[slot] : kEmptyKey;
+                const bool used = key != kEmptyKey;
+                add_pairs_wave<false>(T.sw, used ? (int64_t)key : 0, used ? cvals[2 * slot] : 0.0,
+                                      used ? cvals[2 * slot + 1] : 0.0, used);
+            }
+        }
+        if (T.lds_offset < 0) continue;
+        merge_pairs(T.sw, lds + T.lds_offset, T.lds_bins, [&](int64_t i) { return slice_to_flat(T, i); });
+    }
 }
 
 // ------------------------------------------------------------------------
@@ -634,7 +605,7 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
                     const HistAngles<float> q{0.f, 0.f};
                     for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
-                        const int64_t b = tally_bin<float, false>(B.tallies[t], s, s.term, q);
+                        const int64_t b = tally_bin_t<float, false, false>(B.tallies[t], s, s.term, q);   // batches privatise whole tallies only
                         if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
                     }
                 }
