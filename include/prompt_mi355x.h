@@ -405,15 +405,6 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * wave does not wait for its longest walk.  0: walks run to the end.  The FP64
  * policies always walk to the end (their histories match the oracle's event by
  * event);
- * regroup_steps: 0, or 1..256: FP32 single runs of scenes without a
- * daughter grid run a kernel whose blocks, every this many steps, sort their
- * lanes through LDS by what the histories do next (live in a material, live in
- * vacuum, idle or ended), so each wave holds histories taking the same branches
- * and idle lanes refill as whole waves (the event split of the paper's GPU
- * flow, Section 3.1, inside a block; no queues in global memory).  It needs 21
- * words of LDS per thread (23 with records) beside the tallies; a run where that
- * does not fit goes without it.  Records are those of the run without regrouping, tallies equal
- * up to summation order.  0: no regrouping;
  * waves_per_simd: 4 or 5 (0 means 4): resident waves per SIMD the FP32
  * kernels without a daughter grid are compiled for (5 holds them to 96 VGPRs,
  * spilling some state to scratch; which is faster depends on the workload);
@@ -434,7 +425,6 @@ typedef struct {
     int32_t waves_per_simd;
     int32_t grid_chunk;
     int32_t grid_walk_cells;
-    int32_t regroup_steps;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);
