@@ -53,7 +53,13 @@ HBM_PEAK_GBS = 8000.0
 # WRITE_SIZE passes (scaled by a 256 MiB copy: fetch x2.000, write x1.000), valid
 # only for the kernel build they were taken on (hash of transport.hip, device.h and
 # the compiler flags); the profiles/ summaries hold them.
-MEASURED_TRAFFIC = {"source_hash": "unprofiled"}
+MEASURED_TRAFFIC = {
+    "source_hash": "59354aff6eed79dd",
+    # profiles/k_mixed_biased_sample_1e7.txt, k_mixed_vessel_1e8.txt, k_mixed_guide_1e8_4e8bins.txt
+    "k_mixed<float>:sample": 1.61294e7,
+    "k_mixed<float>:vessel": 2.26719e9,
+    "k_mixed<float>:guide": 2.75812e9,
+}
 
 
 def kernel_source_hash() -> str:
