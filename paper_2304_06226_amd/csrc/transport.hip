@@ -101,16 +101,18 @@ __device__ __forceinline__ void add_global_wave(double* sw, int64_t b, double w,
 // The grid variant is held to three waves per SIMD (168 VGPRs): its grid walk
 // is latency-bound, and the third wave hides more of it (1000-box imaging
 // 48.9 -> 38.3 ms); the other variants run two, as they would anyway.
-// One thread per history; the grid strides over history indices when the run
-// has more histories than the launch has threads.
-template <bool REC, bool GRID>
+// One thread per history (a loop over several histories per thread costs the grid
+// variant registers: imaging 38 -> 43 ms; the host splits very large runs into
+// several launches instead).  FC: the run has
+// first-collision tallies (a separate instance: their scoring inside the step
+// loop costs the other runs registers, imaging 43 -> 53 ms).
+template <bool REC, bool GRID, bool FC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 2, 8))) void k_plain(Params P) {
     const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.boxes_d,
                            P.kinds};
     Counters cnt = {};
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t base = (uint64_t)blockIdx.x * blockDim.x; base < P.n; base += stride) {
-        const uint64_t i = base + threadIdx.x;
+    {
+        const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
         const bool live = i < P.n;
         PState<double> s;
         s.xs_mat = -2;
@@ -121,7 +123,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
             source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
             while (s.term == 0) {
                 const bool first = step<double, REC, GRID>(s, S, P.seed);
-                if (P.has_fc && first) {
+                if (FC && first) {
                     // first-collision tallies score the state just after the collision
                     const HistAngles<double> q = hist_angles<double>(s, P.qmask);
                     for (int t = 0; t < P.n_tallies; ++t) {
@@ -131,9 +133,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
                 }
             }
         }
-        // scoring with the whole wave converged (paired-lane global atomics)
+        // scoring with the whole wave converged (paired-lane global atomics); the
+        // grid variant scores per lane (the wave-level form costs it registers it
+        // does not have: imaging 38 -> 49 ms)
         const bool scoring = live && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT);
-        if (__ballot(scoring) != 0ull) {
+        if constexpr (GRID) {
+            if (scoring) {
+                const HistAngles<double> q = hist_angles<double>(s, P.qmask);
+                for (int t = 0; t < P.n_tallies; ++t) {
+                    const int64_t b = tally_bin<double>(P.tallies[t], s, s.term, q);
+                    if (b >= 0) add_global(P.tallies[t], b, s.w, s.w * s.w);
+                }
+            }
+        } else if (__ballot(scoring) != 0ull) {
             const HistAngles<double> q = hist_angles<double>(s, P.qmask);
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
@@ -307,15 +319,16 @@ struct PersistentScene<double, false, GRID> {
 // Block sizes: up to 1024 threads for the FP32 kernels without a grid (fewer
 // blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
 // PAIR (FP32 without a grid): paired-lane global scores, for runs with a tally
-// that scores straight into global memory.
-template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR>
+// that scores straight into global memory.  FC (FP64): the run has
+// first-collision tallies.
+template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
-    // FP64, and FP32 runs whose tallies score straight into global memory: the
-    // wave scores together and the global scores leave as paired-lane atomics
-    // (one 16-byte request per score instead of two 8-byte ones: half the memory
-    // transactions); other FP32 runs: per-lane scoring, which holds fewer registers
-    constexpr bool kPaired = sizeof(R) == 8 || PAIR;
+    // FP64 without a grid, and FP32 runs whose tallies score straight into global
+    // memory: the wave scores together and the global scores leave as paired-lane
+    // atomics (one 16-byte request per score instead of two 8-byte ones: half the
+    // memory transactions); the rest score per lane, which holds fewer registers
+    constexpr bool kPaired = (sizeof(R) == 8 && !GRID) || PAIR;
     extern __shared__ double lds[];
     const LdsLayout L = lds_layout(P);
     char* base = (char*)lds;
@@ -418,12 +431,13 @@ void k_mixed(Params P) {
         }
         // first-collision tallies (a debugging trigger of the FP64 policies) score
         // the state just after the collision
-        if (sizeof(R) == 8 && P.has_fc && __ballot(first) != 0ull) {
+        if (FC && __ballot(first) != 0ull) {
             const HistAngles<R> q = hist_angles<R>(s, P.qmask);
             for (int t = 0; t < P.n_tallies; ++t) {
                 const TallyDev& T = P.tallies[t];
                 const int64_t b = first ? tally_bin<R>(T, s, kTermFirstCollision, q) : -1;
-                score_wave(T, b, s.w, lds, cvals, ckeys);
+                if constexpr (kPaired) score_wave(T, b, s.w, lds, cvals, ckeys);
+                else score_lane(T, b, s.w, lds, cvals, ckeys);
             }
         }
     }
@@ -747,26 +761,33 @@ int mixed_max_block(const Params& P) { return P.has_grid ? 512 : (P.fp64 ? 256 :
 int batch_max_block(bool grid_nav) { return grid_nav ? 512 : 256; }
 
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
-    if (P.n == 0) return hipSuccess;
     const int block = 256;
-    // one thread per history up to 2^20 blocks; larger runs stride over the grid
-    const uint64_t blocks = (P.n + block - 1) / block;
-    const dim3 grid((unsigned)(blocks < (1ull << 20) ? blocks : (1ull << 20)));
-    if (P.has_grid) {
-        if (rec) hipLaunchKernelGGL((k_plain<true, true>), grid, dim3(block), 0, st, P);
-        else hipLaunchKernelGGL((k_plain<false, true>), grid, dim3(block), 0, st, P);
-    } else {
-        if (rec) hipLaunchKernelGGL((k_plain<true, false>), grid, dim3(block), 0, st, P);
-        else hipLaunchKernelGGL((k_plain<false, false>), grid, dim3(block), 0, st, P);
+    static const void* const kernels[8] = {
+        (const void*)k_plain<false, false, false>, (const void*)k_plain<true, false, false>,
+        (const void*)k_plain<false, true, false>,  (const void*)k_plain<true, true, false>,
+        (const void*)k_plain<false, false, true>,  (const void*)k_plain<true, false, true>,
+        (const void*)k_plain<false, true, true>,   (const void*)k_plain<true, true, true>};
+    const int v = (rec ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.has_fc ? 4 : 0);
+    // one thread per history, at most 2^30 histories (2^22 blocks) per launch
+    const uint64_t per_launch = 1ull << 30;
+    for (uint64_t off = 0; off < P.n; off += per_launch) {
+        Params Q = P;
+        Q.first = P.first + off;
+        Q.n = P.n - off < per_launch ? P.n - off : per_launch;
+        Q.records = P.records ? P.records + off : nullptr;
+        void* args[] = {(void*)&Q};
+        const hipError_t e =
+            hipLaunchKernel(kernels[v], dim3((unsigned)((Q.n + block - 1) / block)), dim3(block), args, 0, st);
+        if (e != hipSuccess) return e;
     }
-    return hipGetLastError();
+    return hipSuccess;
 }
 
 // variant index: FP32: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five
 // waves per SIMD (no grid only), bit 3 paired global scores (no grid only);
-// FP64 (scene in global memory): 6, grid 7
+// FP64 (scene in global memory): 6, grid 7, with first-collision tallies 16, 17
 static int mixed_variant(const Params& P) {
-    if (P.fp64) return P.has_grid ? 7 : 6;
+    if (P.fp64) return (P.has_grid ? 7 : 6) + (P.has_fc ? 10 : 0);
     return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
            (P.paired && !P.has_grid ? 8 : 0);
 }
@@ -775,18 +796,20 @@ static int mixed_variant(const Params& P) {
 template <bool REC>
 static const void* mixed_kernel(int v) {
     switch (v) {
-    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false>;
-    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false>;
-    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false>;
-    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false>;
-    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false>;
-    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false>;
-    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false>;
-    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false>;
-    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true>;
-    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true>;
-    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true>;
-    default: return (const void*)k_mixed<float, REC, true, false, 5, true>;   // 13
+    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false, false>;
+    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false, false>;
+    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false, false>;
+    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false, false>;
+    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false, false>;
+    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false, false>;
+    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false, false>;
+    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false, false>;
+    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true, false>;
+    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true, false>;
+    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false>;
+    case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false>;
+    case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true>;
+    default: return (const void*)k_mixed<double, REC, false, true, 3, false, true>;   // 17
     }
 }
 

@@ -42,10 +42,10 @@ def test_imaging_grid_fp64_elementwise(ctx, imaging):
 
 
 def test_imaging_fp32_tally_agreement(ctx, imaging):
-    print("[case] imaging fp32 n=200000", flush=True)
-    prob = W.imaging_problem(n=200_000)
-    gres, grec, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
-    ores = O.run(prob, first=ORACLE_FIRST, n=200_000, threads=8)
+    print("[case] imaging fp32 n=1000000", flush=True)
+    prob = W.imaging_problem(n=1_000_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=1_000_000, precision="fp32", records=False)
+    ores = O.run(prob, first=ORACLE_FIRST, n=1_000_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         # coarse 32x32 pixels: sums of 16x16 detector pixels
         def coarse(a):
@@ -227,10 +227,10 @@ def test_mixed_kind_grid_fp64_elementwise(ctx):
 
 
 def test_mixed_kind_grid_fp32_tally_agreement(ctx):
-    print("[case] mixed-kind grid fp32 n=400000", flush=True)
-    prob = _mixed_grid_problem(400_000)
-    gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
-    ores = O.run(prob, first=ORACLE_FIRST, n=400_000, threads=8)
+    print("[case] mixed-kind grid fp32 n=1000000", flush=True)
+    prob = _mixed_grid_problem(1_000_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=1_000_000, precision="fp32", records=False)
+    ores = O.run(prob, first=ORACLE_FIRST, n=1_000_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -271,11 +271,11 @@ def test_nested_grid_fp64_elementwise(ctx):
 
 
 def test_nested_grid_fp32_tally_agreement(ctx):
-    print("[case] nested grids fp32 n=400000", flush=True)
-    prob = _nested_grid_problem(400_000)
-    gres, grec, gst = gpu_run(ctx, prob, first=0, n=400_000, precision="fp32", records=False)
+    print("[case] nested grids fp32 n=1000000", flush=True)
+    prob = _nested_grid_problem(1_000_000)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=1_000_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=ORACLE_FIRST, n=400_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=1_000_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -323,11 +323,11 @@ def test_deep_scene_fp32_and_batched(ctx):
     oracle, and a batch mixing the deep scene with an LDS-staged simulation
     equals the two run one by one, with the four- and the five-wave builds."""
     import torch
-    print("[case] deep scene fp32 n=200000 + batch", flush=True)
-    prob = _deep_scene_problem(200_000)
-    gres, _, gst = gpu_run(ctx, prob, first=0, n=200_000, precision="fp32", records=False)
+    print("[case] deep scene fp32 n=1000000 + batch", flush=True)
+    prob = _deep_scene_problem(1_000_000)
+    gres, _, gst = gpu_run(ctx, prob, first=0, n=1_000_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=ORACLE_FIRST, n=200_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=1_000_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)
@@ -394,11 +394,11 @@ def test_big_grid_fp32_and_batched(ctx):
     the oracle, and batched beside an LDS-staged simulation, equal to the two run
     one by one."""
     import torch
-    print("[case] big grid fp32 n=300000 + batch", flush=True)
-    prob = _big_grid_problem(300_000)
-    gres, _, gst = gpu_run(ctx, prob, first=0, n=300_000, precision="fp32", records=False)
+    print("[case] big grid fp32 n=1000000 + batch", flush=True)
+    prob = _big_grid_problem(1_000_000)
+    gres, _, gst = gpu_run(ctx, prob, first=0, n=1_000_000, precision="fp32", records=False)
     assert gst["capped"] == 0
-    ores = O.run(prob, first=ORACLE_FIRST, n=300_000, threads=8)
+    ores = O.run(prob, first=ORACLE_FIRST, n=1_000_000, threads=8)
     for t, (sw, sw2, nh) in enumerate(gres):
         p, z = tally_stat_test(sw, sw2, nh, ores.sumw[t], ores.sumw2[t], ores.n)
         assert p > 1e-3, (t, p)

@@ -17,7 +17,7 @@ from paper_2304_06226_amd import workloads as W
 
 from parity import gpu_run, paired_check, paired_fp32_fp64
 from test_gpu_batch import _big_grid_problem, _deep_scene_problem, _mixed_grid_problem, _nested_grid_problem, _small_batch
-from test_gpu_parity import _largest_material_problem, _q_orders_problem, _tabulated_problem
+from test_gpu_parity import _fp32_case, _largest_material_problem, _q_orders_problem, _tabulated_problem
 
 pytestmark = pytest.mark.gpu
 
@@ -47,25 +47,25 @@ def far_chopper(n):
 
 
 CASES = {
-    "analog_sample": (lambda: W.analog_sample(), 100_000),
+    "analog_sample": (lambda: W.analog_sample(1_000_000), 1_000_000),
     "biased_sample": (lambda: W.biased_sample(), 1_000_000),
     "vessel": (lambda: W.vessel_sample(), 1_000_000),
     "m3_guide": (lambda: W.m3_guide(nbins_xy=50, nbins_div=20), 1_000_000),
-    "imaging": (lambda: W.imaging_problem(n=500_000), 500_000),
+    "imaging": (lambda: W.imaging_problem(n=1_000_000), 1_000_000),
     "paper_guide": (lambda: W.paper_guide(), 1_000_000),
-    "paper_chopper": (lambda: W.paper_chopper(), 500_000),
-    "paper_chopper_open": (lambda: W.paper_chopper(chopper=False), 400_000),
-    "far_chopper": (lambda: far_chopper(400_000), 400_000),
+    "paper_chopper": (lambda: W.paper_chopper(), 1_000_000),
+    "paper_chopper_open": (lambda: W.paper_chopper(chopper=False), 1_000_000),
+    "far_chopper": (lambda: far_chopper(1_000_000), 1_000_000),
     "tabulated": (lambda: _tabulated_problem(1_000_000), 1_000_000),
-    "largest_material": (lambda: _largest_material_problem(200_000), 200_000),
-    "q_orders_4_0.5": (lambda: _q_orders_problem(W.sample_material().biased(scatter_bias=4.0, abs_bias=0.5), 400_000),
-                       400_000),
-    "q_orders_1_0": (lambda: _q_orders_problem(W.sample_material().biased(scatter_bias=1.0, abs_bias=0.0), 400_000),
-                     400_000),
-    "mixed_kind_grid": (lambda: _mixed_grid_problem(200_000), 200_000),
-    "nested_grid": (lambda: _nested_grid_problem(200_000), 200_000),
-    "deep_scene": (lambda: _deep_scene_problem(200_000), 200_000),
-    "big_grid": (lambda: _big_grid_problem(200_000), 200_000),
+    "largest_material": (lambda: _largest_material_problem(1_000_000), 1_000_000),
+    "q_orders_4_0.5": (lambda: _q_orders_problem(W.sample_material().biased(scatter_bias=4.0, abs_bias=0.5),
+                                                 1_000_000), 1_000_000),
+    "q_orders_1_0": (lambda: _q_orders_problem(W.sample_material().biased(scatter_bias=1.0, abs_bias=0.0), 1_000_000),
+                     1_000_000),
+    "mixed_kind_grid": (lambda: _mixed_grid_problem(1_000_000), 1_000_000),
+    "nested_grid": (lambda: _nested_grid_problem(1_000_000), 1_000_000),
+    "deep_scene": (lambda: _deep_scene_problem(1_000_000), 1_000_000),
+    "big_grid": (lambda: _big_grid_problem(1_000_000), 1_000_000),
 }
 
 
@@ -86,6 +86,12 @@ def test_far_chopper_is_applied_in_fp32(ctx):
     det64 = (rec64["term"] == B.END_DETECT).mean()
     killed32 = (rec32["term"] == B.END_KILL).mean()
     assert killed32 > 0.5 and abs(det32 - det64) < 1e-3, (det32, det64, killed32)
+
+
+def test_far_chopper_fp32_against_oracle(ctx):
+    """The far chopper in FP32 against the oracle on disjoint history ids (the
+    tally agreement test on the TOF histogram and the detected counter)."""
+    _fp32_case(ctx, far_chopper(1_000_000), 1_000_000)
 
 
 def test_batch_paired_with_fp64_one_by_one(ctx):

@@ -207,7 +207,7 @@ def _fp32_case(ctx, prob, n, n_oracle=None, threads=8):
 
 
 def test_analog_sample_fp32_tally_agreement(ctx):
-    _fp32_case(ctx, W.analog_sample(), 100_000)
+    _fp32_case(ctx, W.analog_sample(1_000_000), 1_000_000)
 
 
 def test_biased_sample_fp32_tally_agreement(ctx):
@@ -229,11 +229,11 @@ def test_ragged_sizes_fp32(ctx, n):
 
 
 def test_vessel_sample_fp32_tally_agreement(ctx):
-    _fp32_case(ctx, W.vessel_sample(), 300_000)
+    _fp32_case(ctx, W.vessel_sample(), 1_000_000)
 
 
 def test_m3_guide_fp32_tally_agreement(ctx):
-    _fp32_case(ctx, W.m3_guide(nbins_xy=50, nbins_div=20), 300_000)
+    _fp32_case(ctx, W.m3_guide(nbins_xy=50, nbins_div=20), 1_000_000)
 
 
 def test_fp32_results_independent_of_launch_tuning(ctx):
@@ -297,7 +297,7 @@ def test_q_orders_and_bias_factors_fp64_elementwise(ctx, gs, ga):
 @pytest.mark.parametrize("gs,ga", [(4.0, 0.5), (1.0, 0.0)])
 def test_q_orders_and_bias_factors_fp32(ctx, gs, ga):
     mat = W.sample_material().biased(scatter_bias=gs, abs_bias=ga)
-    _fp32_case(ctx, _q_orders_problem(mat, 400_000), 400_000)
+    _fp32_case(ctx, _q_orders_problem(mat, 1_000_000), 1_000_000)
 
 
 def test_biasing_validations_on_gpu(ctx):
@@ -368,7 +368,7 @@ def test_paper_chopper_mono_fp64_elementwise(ctx):
 
 def test_paper_chopper_fp32_tally_agreement(ctx):
     _fp32_case(ctx, W.paper_chopper(1_000_000), 1_000_000)
-    _fp32_case(ctx, W.paper_chopper(400_000, chopper=False), 400_000)
+    _fp32_case(ctx, W.paper_chopper(1_000_000, chopper=False), 1_000_000)
 
 
 # ---------------------------------------------------------------------------
@@ -429,7 +429,7 @@ def test_largest_material_fp64_elementwise(ctx):
 
 
 def test_largest_material_fp32(ctx):
-    _fp32_case(ctx, _largest_material_problem(200_000), 200_000)
+    _fp32_case(ctx, _largest_material_problem(1_000_000), 1_000_000)
 
 
 def test_empty_runs_change_nothing(ctx):
