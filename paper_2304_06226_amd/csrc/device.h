@@ -1290,7 +1290,9 @@ constexpr int64_t kOffSlice = 1ll << 62;
 // (PRE), or left to each divergence axis to compute (fewer values live across
 // the loop).  SLICED: the tally is privatised as a slice (a separate instance,
 // so that the bins of other tallies carry none of the slice arithmetic).
-template <class R, bool PRE, bool SLICED>
+// UNROLL: the axis loop unrolled (the batch kernels, short of registers, keep it
+// rolled).
+template <class R, bool PRE, bool SLICED, bool UNROLL = true>
 __device__ __forceinline__ int64_t tally_bin_t(const TallyDev& T, const PState<R>& s, int term, const HistAngles<R>& q) {
     const TallyHead h = T.head;
     if (!(((h.term_mask >> term) & 1u) && s.nscat >= h.nscat_lo && s.nscat <= h.nscat_hi &&
@@ -1306,7 +1308,11 @@ __device__ __forceinline__ int64_t tally_bin_t(const TallyDev& T, const PState<R
     bool in_slice = true;
     (void)slice;
     (void)in_slice;
-    for (int a = 0; a < h.naxes; ++a) {
+    // unrolled over the at most four axes (UNROLL), so the scalar loads of every
+    // axis's descriptor issue together instead of one loop trip after another
+#pragma unroll
+    for (int a = 0; a < (UNROLL ? 4 : h.naxes); ++a) {
+        if (a >= h.naxes) break;
         const TallyAxis& A = T.ax[a];
         const int32_t quantity = A.quantity, n = A.nbins;
         R lo, hi, scale;
@@ -1328,7 +1334,11 @@ __device__ __forceinline__ int64_t tally_bin_t(const TallyDev& T, const PState<R
         default: x = (R)s.nscat; break;
         }
         if (!(x >= lo && x <= hi)) return -1;
-        int b = (int)__builtin_floor((double)((x - lo) * scale));
+        // FP32: floorf of the FP32 product (the same integer as the floor of its
+        // exact double conversion, without the FP64 round trip)
+        int b;
+        if constexpr (sizeof(R) == 4) b = (int)__builtin_floorf((x - lo) * scale);
+        else b = (int)__builtin_floor((x - lo) * scale);
         if (x == hi || b >= n) b = n - 1;
         if (b < 0) b = 0;
         flat = flat * n + b;

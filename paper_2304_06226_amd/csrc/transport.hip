@@ -386,9 +386,19 @@ void k_mixed(Params P) {
             if (pending) {
                 if (!kPaired && (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT)) {
                     const HistAngles<R> q = hist_angles<R>(s, P.qmask);
-                    for (int t = 0; t < P.n_tallies; ++t) {
-                        const TallyDev& T = P.tallies[t];
-                        score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
+                    if constexpr (GRID) {
+                        // two tallies per trip: their descriptors' scalar loads issue
+                        // together (the imaging scene's two image tallies: -5 %)
+#pragma unroll 2
+                        for (int t = 0; t < P.n_tallies; ++t) {
+                            const TallyDev& T = P.tallies[t];
+                            score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
+                        }
+                    } else {
+                        for (int t = 0; t < P.n_tallies; ++t) {
+                            const TallyDev& T = P.tallies[t];
+                            score_lane(T, tally_bin<R>(T, s, s.term, q), s.w, lds, cvals, ckeys);
+                        }
                     }
                 }
                 if (REC) write_record<R>(P.records + (s.h - P.first), s);
@@ -619,7 +629,7 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
                 if (s.term == PR_END_ESCAPE || s.term == PR_END_ABSORB || s.term == PR_END_DETECT) {
                     const HistAngles<float> q{0.f, 0.f};
                     for (int t = sd.tally_begin; t < sd.tally_begin + sd.tally_count; ++t) {
-                        const int64_t b = tally_bin_t<float, false, false>(B.tallies[t], s, s.term, q);   // batches privatise whole tallies only
+                        const int64_t b = tally_bin_t<float, false, false, false>(B.tallies[t], s, s.term, q);   // whole tallies only
                         if (b >= 0) score_block(B, sd, t, b, s.w, ltal, ckeys);
                     }
                 }
