@@ -819,7 +819,8 @@ static const void* mixed_kernel(int v) {
     case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false>;
     case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false>;
     case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true>;
-    default: return (const void*)k_mixed<double, REC, false, true, 3, false, true>;   // 17
+    case 17: return (const void*)k_mixed<double, REC, false, true, 3, false, true>;
+    default: return nullptr;   // no such variant: the launch reports an error
     }
 }
 
@@ -828,15 +829,18 @@ hipError_t launch_mixed(const Params& P, bool rec, int grid, int block, hipStrea
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, P.counter, 1);
     const int lds = mixed_lds_bytes(P);
     const int v = mixed_variant(P);
+    const void* k = rec ? mixed_kernel<true>(v) : mixed_kernel<false>(v);
+    if (!k) return hipErrorInvalidDeviceFunction;
     void* args[] = {(void*)&P};
-    return hipLaunchKernel(rec ? mixed_kernel<true>(v) : mixed_kernel<false>(v), dim3(grid), dim3(block), args,
-                           (size_t)lds, st);
+    return hipLaunchKernel(k, dim3(grid), dim3(block), args, (size_t)lds, st);
 }
 
 int mixed_occupancy(const Params& P, int block) {
     int nb = 0;
     const int lds = mixed_lds_bytes(P);
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mixed_kernel<false>(mixed_variant(P)), block, lds);
+    const void* k = mixed_kernel<false>(mixed_variant(P));
+    if (!k) return 1;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, block, lds);
     if (e != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
 }
