@@ -16,12 +16,14 @@ scene from 8.65 to 6.55 ms per 1e7 histories and the batch from 18.3 to 16.4 ms
 per step: a wave no longer waits for its lanes' longest walk.  Runs whose
 tallies score straight into global memory (guide, vessel, paper's guide) score
 as a wave with paired-lane atomics; for the guide that moved the best refill
-threshold from 16 to 48 idle lanes (7.56 -> 6.22 ms per 1e8 histories)."""
+threshold from 16 to 48 idle lanes (7.56 -> 6.22 ms per 1e8 histories).  Cheaper
+tally binning moved the biased sample's from 32 to 16 (512-id claims: 1.237 ->
+1.221 ms)."""
 
 # workload name -> pr_tuning fields
 TUNED = {
-    "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 32, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
+    "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
+               "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "guide": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
               "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
@@ -43,7 +45,7 @@ TUNED = {
 # slots, starting from the FP32 entries.  Its lanes run longer steps, so more of
 # them may wait before a refill (guide: 16 -> 48 idle lanes, -17 %).
 TUNED_FP64_PERSISTENT = {
-    "sample": dict(TUNED["sample"], block=256, chunk=256),
+    "sample": dict(TUNED["sample"], block=256, chunk=256, refill_threshold=32),
     "guide": dict(TUNED["guide"], block=256, refill_threshold=48),
     "vessel": dict(TUNED["vessel"], chunk=1024),
     "imaging": dict(TUNED["imaging"], chunk=64, grid_walk_cells=0),
