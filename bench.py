@@ -56,7 +56,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "source_hash": "418d1c08e4d4175b",
     # profiles/k_mixed_biased_sample_1e7.txt, k_mixed_vessel_1e8.txt, k_mixed_guide_1e8_4e8bins.txt
-    "k_mixed<float>:sample": 1.61625e7,
+    "k_mixed<float>:sample": 1.64759e7,
     "k_mixed<float>:vessel": 2.2071e9,
     "k_mixed<float>:guide": 2.75814e9,
 }
