@@ -196,3 +196,27 @@ def test_tally_slices_equal_plain_fp64(ctx, order):
         ctx.set_tuning(**base)
     _close(r32, g32)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("name", ["guide", "vessel", "sample"])
+def test_paired_global_scores_equal_cached_scores(ctx, name):
+    """FP32 runs whose large tally scores straight into global memory (no bin
+    cache: the wave scores together, paired-lane atomics) equal the same runs
+    with an LDS bin cache (per-lane scoring) up to summation order."""
+    import torch
+    prob = {"guide": lambda: W.m3_guide(nbins_xy=50, nbins_div=20), "vessel": W.vessel_sample,
+            "sample": W.biased_sample}[name]()
+    n = 400_000
+    base = ctx.get_tuning()
+    try:
+        # sample: a 4 KB LDS budget leaves its 2theta x lambda tally in global memory
+        lds = 4096 if name == "sample" else base["lds_tally_bytes"]
+        ctx.set_tuning(**{**base, "lds_tally_bytes": lds, "bin_cache_slots": 1024})
+        cached, _, _ = gpu_run(ctx, prob, first=99, n=n, precision="fp32", records=False)
+        ctx.set_tuning(**{**base, "lds_tally_bytes": lds, "bin_cache_slots": 0})
+        paired, _, _ = gpu_run(ctx, prob, first=99, n=n, precision="fp32", records=False)
+    finally:
+        ctx.set_tuning(**base)
+    _close(paired, cached)
+    assert paired[0][0].sum() > 0
+    torch.cuda.synchronize()
