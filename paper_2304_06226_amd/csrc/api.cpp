@@ -32,6 +32,7 @@ struct Material {
 
 struct Geometry {
     std::vector<pr_volume_desc> vols;
+    bool esc = false;   // some volume is marked exit_escapes
     // host copies of the device scene (batched runs concatenate them)
     std::vector<VolT<double>> vd;
     std::vector<VolT<float>> vf;
@@ -800,6 +801,22 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
         g.vd[i].kind_items4 = g.vf[i].kind_items4 = (uint32_t)(m >> 32);
         g.vd[i].det_items = g.vf[i].det_items = det;
     }
+    // the only, convex daughter of a vacuum world without mirrors: leaving it ends in
+    // the world's boundary (the step that leaves it takes the world crossing too)
+    for (int i = 1; i < n; ++i) {
+        const int w = g.vd[i].parent;
+        const int k = g.vd[i].kind, wk = g.vd[w].kind;
+        const bool convex = k == PR_BOX || k == PR_CYLINDER || k == PR_SPHERE;
+        const bool plain_world = g.vd[w].parent < 0 && g.vd[w].mat < 0 && g.vd[w].mirror_mask == 0 &&
+                                 g.vd[w].chop_n == 0 && g.vd[w].grid < 0 && kids[w].size() == 1 &&
+                                 (wk == PR_BOX || wk == PR_CYLINDER || wk == PR_SPHERE);
+        if (convex && plain_world) {
+            const uint32_t mark = (uint32_t)(1 + wk) << 24;   // byte 3 of kind_items4: exit_escapes
+            g.vd[i].kind_items4 |= mark;
+            g.vf[i].kind_items4 |= mark;
+            g.esc = true;
+        }
+    }
     g.kinds = 0;
     for (int i = 0; i < n; ++i) {
         g.kinds |= 1u << g.vd[i].kind;
@@ -1119,6 +1136,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
                      g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget);
     P.fp64 = precision == PR_FP64_PERSISTENT ? 1 : 0;
     P.kinds = g.kinds;
+    P.esc = g.esc ? 1 : 0;
     make_source_dev(c->srcs[src], P.src);
     P.n_tallies = nt;
     int lds_doubles = 0;

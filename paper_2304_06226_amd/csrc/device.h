@@ -44,6 +44,11 @@ struct VolT {
     // Byte k of kind_items (k = PR_BOX .. PR_SPHERE) and byte 0 of kind_items4
     // (PR_SPH_SHELL) hold the bit set of the items of that solid kind;
     // det_items the items that are detector volumes.
+    // Byte 3 of kind_items4 (exit_escapes): 1 + the world's solid kind when this
+    // volume is the only daughter of a vacuum, mirrorless world and is itself
+    // convex (box, cylinder, sphere): a history leaving it can only fly on to the
+    // world's boundary (no draws, nothing to meet), a step the leaving step takes
+    // at once; 0 otherwise.
     uint32_t kind_items, kind_items4, det_items;
     R R0, Qc, alpha, mQc, W;
     // disk chopper carried by a cylinder (chop_n = 0: none); angles in radians,
@@ -225,6 +230,7 @@ struct Params {
     int32_t walk_cells;            // FP32 grid walks pause after this many cells (0: never)
     int32_t paired;                // FP32 without a grid: a tally scores straight into global memory, so the
                                    // wave's scores leave as paired-lane atomics (the FP64 kernels always do)
+    int32_t esc;                   // some volume is marked exit_escapes (the world-crossing kernels apply)
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)
@@ -1081,9 +1087,28 @@ __device__ __forceinline__ void scan_kind(const SceneT<R>& S, const VolT<R>& V, 
 }
 
 
+// Distance to where the ray leaves volume W from inside it (the end of its first
+// piece ahead; 0 when none), exactly as a step's boundary scan finds it for the
+// volume itself.  kind: W's solid kind (box, cylinder or sphere).
+template <class R>
+__device__ __forceinline__ R own_exit(const VolT<R>& W, int kind, const R p[3], const R u[3]) {
+    Pieces<R> P;
+    P.n = 0;
+    if (kind == PR_BOX) pieces_kind<R, PR_BOX>(W, p, u, P);
+    else if (kind == PR_CYLINDER) pieces_kind<R, PR_CYLINDER>(W, p, u, P);
+    else pieces_kind<R, PR_SPHERE>(W, p, u, P);
+    R d = rinf<R>();
+    if (P.n > 0 && P.b0 > (R)0) d = P.b0;
+    if (P.n > 1 && P.b1 > (R)0 && P.b1 < d) d = P.b1;
+    return d == rinf<R>() ? (R)0 : d;
+}
+
 // One step; returns true when the step was the history's first collision
-// (absorption or scattering), the event of first-collision tallies.
-template <class R, bool REC, bool GRID>
+// (absorption or scattering), the event of first-collision tallies.  ESC: a
+// history leaving a volume marked exit_escapes takes the world crossing that
+// follows in the same step (kernels built without it leave that to the next
+// step; the history is the same either way).
+template <class R, bool REC, bool GRID, bool ESC = false>
 __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed, int walk_cells = 0) {
     if (s.steps >= kMaxSteps) {
         s.term = PR_END_CAPPED;
@@ -1249,6 +1274,20 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
     }
     s.region = V.parent;
     hash_ev<REC>(s.hash, EV_EXIT, s.region);
+    const int exit_escapes = (int)(V.kind_items4 >> 24);
+    if (ESC && exit_escapes && s.steps < kMaxSteps) {
+        // the next step can only cross the vacuum world to its boundary: take it
+        // now, as that step would (same distance, move and time; the step cap is
+        // left to the next step)
+        s.steps++;
+        const R xw = own_exit<R>(S.vols[s.region], exit_escapes - 1, s.p, s.u);
+        s.p[0] += xw * s.u[0];
+        s.p[1] += xw * s.u[1];
+        s.p[2] += xw * s.u[2];
+        if ((S.kinds >> kTimeBit) & 1u) s.t += M<R>::div_(xw * s.lam, (R)kHOverMn);
+        s.term = PR_END_ESCAPE;
+        hash_ev<REC>(s.hash, EV_ESCAPE, 0);
+    }
     return false;
 }
 

@@ -106,7 +106,9 @@ __device__ __forceinline__ void add_global_wave(double* sw, int64_t b, double w,
 // several launches instead).  FC: the run has
 // first-collision tallies (a separate instance: their scoring inside the step
 // loop costs the other runs registers, imaging 43 -> 53 ms).
-template <bool REC, bool GRID, bool FC>
+// ESC: the world crossing after leaving an exit_escapes volume is taken in the
+// leaving step (scenes without a grid; not with first-collision tallies).
+template <bool REC, bool GRID, bool FC, bool ESC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 2, 8))) void k_plain(Params P) {
     const SceneT<double> S{P.vols_d, P.mats_d, P.fams_d, P.children, P.grids_d, P.cell_start, P.cell_items, P.boxes_d,
                            P.kinds};
@@ -122,7 +124,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRID ? 3 : 
         if (live) {
             source<double, REC, GRID>(s, P.src, S, P.seed, P.first + i, 0);
             while (s.term == 0) {
-                const bool first = step<double, REC, GRID>(s, S, P.seed);
+                const bool first = step<double, REC, GRID, ESC>(s, S, P.seed);
                 if (FC && first) {
                     // first-collision tallies score the state just after the collision
                     const HistAngles<double> q = hist_angles<double>(s, P.qmask);
@@ -320,8 +322,13 @@ struct PersistentScene<double, false, GRID> {
 // blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
 // PAIR (FP32 without a grid): paired-lane global scores, for runs with a tally
 // that scores straight into global memory.  FC (FP64): the run has
-// first-collision tallies.
-template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC>
+// first-collision tallies.  ESC (no grid; FP32 with four waves and per-lane
+// scoring, and FP64): the world crossing after leaving an exit_escapes volume is
+// taken in the leaving step, and a history born in a vacuum volume takes its
+// first step in the refill pass, with the wave's other new histories (both draw
+// nothing and change no history; built only where the registers allow: the
+// other FP32 variants and the batch kernels slow down with the extra code).
+template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC, bool ESC>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
     // FP64 without a grid, and FP32 runs whose tallies score straight into global
@@ -423,7 +430,11 @@ void k_mixed(Params P) {
                     if ((unsigned long long)rank < take) {
                         source<R, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
                                              start_region);
-                        pending = s.term != 0;   // born outside the world: counted at the next refill
+                        // born in a vacuum volume: the first step draws nothing and is
+                        // taken here, with the wave's other new histories
+                        if (ESC && s.term == 0 && S.vols[s.region].mat < 0)
+                            step<R, REC, GRID, ESC>(s, S, P.seed, P.walk_cells);
+                        pending = s.term != 0;   // born outside the world, or ended: counted at the next refill
                     }
                 }
                 cnext += take;
@@ -436,7 +447,7 @@ void k_mixed(Params P) {
         }
         bool first = false;
         if (s.term == 0) {
-            first = step<R, REC, GRID>(s, S, P.seed, P.walk_cells);
+            first = step<R, REC, GRID, ESC>(s, S, P.seed, P.walk_cells);
             pending = s.term != 0;
         }
         // first-collision tallies (a debugging trigger of the FP64 policies) score
@@ -772,12 +783,14 @@ int batch_max_block(bool grid_nav) { return grid_nav ? 512 : 256; }
 
 hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
     const int block = 256;
-    static const void* const kernels[8] = {
-        (const void*)k_plain<false, false, false>, (const void*)k_plain<true, false, false>,
-        (const void*)k_plain<false, true, false>,  (const void*)k_plain<true, true, false>,
-        (const void*)k_plain<false, false, true>,  (const void*)k_plain<true, false, true>,
-        (const void*)k_plain<false, true, true>,   (const void*)k_plain<true, true, true>};
-    const int v = (rec ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.has_fc ? 4 : 0);
+    static const void* const kernels[10] = {
+        (const void*)k_plain<false, false, false, false>, (const void*)k_plain<true, false, false, false>,
+        (const void*)k_plain<false, true, false, false>,  (const void*)k_plain<true, true, false, false>,
+        (const void*)k_plain<false, false, true, false>,  (const void*)k_plain<true, false, true, false>,
+        (const void*)k_plain<false, true, true, false>,   (const void*)k_plain<true, true, true, false>,
+        (const void*)k_plain<false, false, false, true>,  (const void*)k_plain<true, false, false, true>};
+    const bool esc = P.esc && !P.has_grid && !P.has_fc;
+    const int v = esc ? 8 + (rec ? 1 : 0) : (rec ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.has_fc ? 4 : 0);
     // one thread per history, at most 2^30 histories (2^22 blocks) per launch
     const uint64_t per_launch = 1ull << 30;
     for (uint64_t off = 0; off < P.n; off += per_launch) {
@@ -795,31 +808,37 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
 
 // variant index: FP32: bit 0 scene in LDS, bit 1 daughter grid, bit 2 five
 // waves per SIMD (no grid only), bit 3 paired global scores (no grid only);
-// FP64 (scene in global memory): 6, grid 7, with first-collision tallies 16, 17
+// FP64 (scene in global memory): 6, grid 7, with first-collision tallies 16, 17;
+// + 20 with the world-crossing code (FP32 four-wave per-lane scoring without a
+// grid: 20, 21; FP64 without a grid or first-collision tallies: 26)
 static int mixed_variant(const Params& P) {
-    if (P.fp64) return (P.has_grid ? 7 : 6) + (P.has_fc ? 10 : 0);
-    return (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
-           (P.paired && !P.has_grid ? 8 : 0);
+    if (P.fp64) return P.has_fc ? (P.has_grid ? 17 : 16) : (P.has_grid ? 7 : (P.esc ? 26 : 6));
+    const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
+                  (P.paired && !P.has_grid ? 8 : 0);
+    return v <= 1 && P.esc ? v + 20 : v;
 }
 
 // the kernel of a variant index
 template <bool REC>
 static const void* mixed_kernel(int v) {
     switch (v) {
-    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false, false>;
-    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false, false>;
-    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false, false>;
-    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false, false>;
-    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false, false>;
-    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false, false>;
-    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false, false>;
-    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false, false>;
-    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true, false>;
-    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true, false>;
-    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false>;
-    case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false>;
-    case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true>;
-    case 17: return (const void*)k_mixed<double, REC, false, true, 3, false, true>;
+    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false, false, false>;
+    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false, false, false>;
+    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false, false, false>;
+    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false, false, false>;
+    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false, false, false>;
+    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false, false, false>;
+    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false, false, false>;
+    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false, false, false>;
+    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true, false, false>;
+    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true, false, false>;
+    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false, false>;
+    case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false, false>;
+    case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true, false>;
+    case 17: return (const void*)k_mixed<double, REC, false, true, 3, false, true, false>;
+    case 20: return (const void*)k_mixed<float, REC, false, false, 4, false, false, true>;
+    case 21: return (const void*)k_mixed<float, REC, true, false, 4, false, false, true>;
+    case 26: return (const void*)k_mixed<double, REC, false, false, 2, false, false, true>;
     default: return nullptr;   // no such variant: the launch reports an error
     }
 }

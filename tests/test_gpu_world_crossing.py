@@ -1,0 +1,71 @@
+"""The world crossing folded into the leaving step: when a convex volume (box,
+cylinder, sphere) is the only daughter of a vacuum, mirrorless world of one of
+those kinds, a history that leaves it can only fly on to the world's boundary,
+and the kernels take that flight in the step that leaves the daughter; a
+history born in such a world takes its first step (into the daughter or out of
+the world) as soon as it is drawn.  Neither may change a history: every
+world x daughter pairing runs both FP64 policies element-wise against the
+oracle on the same ids (event hashes, steps, draws, end positions, times of
+flight) and the FP32 policy paired with the FP64 one."""
+import pytest
+
+from oracle import oracle as O
+from paper_2304_06226_amd import workloads as W
+
+from parity import compare_records_fp64, compare_tallies_fp64, gpu_run, paired_fp32_fp64
+
+pytestmark = pytest.mark.gpu
+
+WORLDS = {"box": (2000.0, 1500.0, 2500.0), "cylinder": (900.0, 2200.0), "sphere": (1000.0,)}
+DAUGHTERS = {"box": (10.0, 20.0, 8.0), "cylinder": (5.0, 20.0), "sphere": (6.0,)}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2304_06226_amd import binding as B
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = B.Context(device=0, seed=4096)
+    yield c
+    c.close()
+
+
+def _problem(world, daughter, n):
+    """A biased powder sample of the given solid kind alone in a vacuum world of the
+    given kind; a 14 x 14 mm Maxwellian beam, wider than the sample, so that some
+    histories cross the world without meeting it; a time-of-flight tally keeps the
+    clock running."""
+    mats = [W.sample_material().biased(scatter_bias=2.0)]
+    vols = [W.Volume(world, (0.0, 0.0, 0.0), WORLDS[world], axis=0),
+            W.Volume(daughter, (0.5, -0.5, 0.0), DAUGHTERS[daughter], axis=1, parent=0, material=0)]
+    src = W.Source("rect", origin=(0.0, 0.0, -100.0), size=(14.0, 14.0), spectrum="maxwell",
+                   lam_lo=0.5, lam_hi=5.0, kT=0.025852)
+    tallies = [W.Tally(trigger="escape", filter="scattered",
+                       axes=[W.Axis("theta2", 0.0, 180.0, 180), W.Axis("lambda", 0.5, 5.0, 20)]),
+               W.Tally(trigger="escape", filter="unscattered", axes=[W.Axis("tof", 0.0, 0.01, 50)]),
+               W.Tally(trigger="absorb")]
+    return W.Problem(mats, vols, src, tallies, n_histories=n, name=f"{daughter}-in-{world}")
+
+
+@pytest.mark.parametrize("daughter", sorted(DAUGHTERS))
+@pytest.mark.parametrize("world", sorted(WORLDS))
+def test_world_crossing_fp64_elementwise(ctx, world, daughter):
+    n = 20_000
+    prob = _problem(world, daughter, n)
+    ores = O.run(prob, first=0, n=n, threads=8, records=True)
+    # the sample is met by some histories and missed by others
+    assert 0 < (ores.records["n_steps"] == 1).sum() < n
+    for precision in ("fp64", "fp64_persistent"):
+        print(f"[case] {prob.name} {precision} n={n}", flush=True)
+        gres, grec, gst = gpu_run(ctx, prob, first=0, n=n, precision=precision)
+        same = compare_records_fp64(grec, ores.records)
+        compare_tallies_fp64(gres, ores, grec, ores.records, same)
+        assert gst["steps"] == int(ores.records["n_steps"].sum()) or not same.all()
+        assert gst["escaped"] + gst["absorbed"] + gst["killed"] == n
+
+
+@pytest.mark.parametrize("daughter", sorted(DAUGHTERS))
+@pytest.mark.parametrize("world", sorted(WORLDS))
+def test_world_crossing_fp32_pairs_with_fp64(ctx, world, daughter):
+    prob = _problem(world, daughter, 200_000)
+    paired_fp32_fp64(ctx, prob, first=0, n=200_000, label=prob.name)
