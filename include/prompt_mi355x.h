@@ -413,6 +413,14 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * Scenes with a daughter grid whose grid, box bounds and tables are staged in
  * LDS run blocks of 256 or 512 threads, whichever keeps the most waves
  * resident per CU, unless blocks_per_cu is set (then `block` is used).
+ * vacuum_steps: 1 (default) or 0.  At 1, steps that draw nothing are taken
+ * early where the scene allows it (scenes without a daughter grid): a history
+ * leaving the only, convex daughter of a vacuum, mirrorless box, cylinder or
+ * sphere world crosses the world in the same step; a history born in vacuum
+ * takes its first step as soon as it is drawn; and, in FP32 scenes without
+ * mirrors whose material volumes sit in vacuum, a history that leaves
+ * material for vacuum takes its vacuum step before the wave's other histories
+ * step again.  Histories and records are the same either way.
  * Results do not depend on these settings beyond floating-point summation
  * order. */
 typedef struct {
@@ -425,6 +433,7 @@ typedef struct {
     int32_t waves_per_simd;
     int32_t grid_chunk;
     int32_t grid_walk_cells;
+    int32_t vacuum_steps;
 } pr_tuning;
 
 int pr_set_tuning(pr_ctx* ctx, const pr_tuning* tuning);

@@ -94,7 +94,8 @@ class pr_tally_desc(C.Structure):
 class pr_tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32), ("refill_threshold", C.c_int32),
                 ("lds_tally_bytes", C.c_int32), ("bin_cache_slots", C.c_int32), ("chunk", C.c_int32),
-                ("waves_per_simd", C.c_int32), ("grid_chunk", C.c_int32), ("grid_walk_cells", C.c_int32)]
+                ("waves_per_simd", C.c_int32), ("grid_chunk", C.c_int32), ("grid_walk_cells", C.c_int32),
+                ("vacuum_steps", C.c_int32)]
 
 
 class pr_sim(C.Structure):

@@ -32,7 +32,8 @@ struct Material {
 
 struct Geometry {
     std::vector<pr_volume_desc> vols;
-    bool esc = false;   // some volume is marked exit_escapes
+    bool esc = false;    // some volume is marked exit_escapes
+    bool fold = false;   // no mirrors, and some material volume sits in a vacuum one (FP32 fold passes apply)
     // host copies of the device scene (batched runs concatenate them)
     std::vector<VolT<double>> vd;
     std::vector<VolT<float>> vf;
@@ -153,6 +154,7 @@ struct pr_ctx {
     int lds_scene_budget = 16384;       // FP32 scenes up to this size are staged into LDS
     int lds_grid_budget = 98304;        // grid scenes: staged part (grid, box bounds, tables) up to this size
     int grid_walk_cells = 0;            // FP32 grid walks pause after this many cells (0: never)
+    int vacuum_steps = 1;               // take steps that draw nothing early where the scene allows (0: never)
     DescSlot slots[4];
     int waves_per_simd = 4;             // FP32 kernels without a grid: variant built for 4 or 5 waves per SIMD
     double* scratch = nullptr;          // autotuner: tally scratch (trial runs score here)
@@ -817,6 +819,17 @@ extern "C" int pr_create_geometry(pr_ctx* c, const pr_volume_desc* vols, int32_t
             g.esc = true;
         }
     }
+    // FP32 fold passes: worth it where histories go in and out of material volumes
+    // that sit in vacuum; scenes with mirrors (guides) mostly step through vacuum,
+    // and the extra pass there costs more than it saves
+    if (!g.esc) {
+        bool mirrors = false, mat_in_vacuum = false;
+        for (int i = 0; i < n; ++i) {
+            mirrors = mirrors || g.vd[i].mirror_mask != 0;
+            if (i > 0 && g.vd[i].mat >= 0 && g.vd[g.vd[i].parent].mat < 0) mat_in_vacuum = true;
+        }
+        g.fold = !mirrors && mat_in_vacuum;
+    }
     g.kinds = 0;
     for (int i = 0; i < n; ++i) {
         g.kinds |= 1u << g.vd[i].kind;
@@ -1136,7 +1149,9 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
                      g.scene_lds_bytes <= (P.has_grid ? c->lds_grid_budget : c->lds_scene_budget);
     P.fp64 = precision == PR_FP64_PERSISTENT ? 1 : 0;
     P.kinds = g.kinds;
-    P.esc = g.esc ? 1 : 0;
+    // 1: the lone-daughter world crossing (and the newborn step); 2: FP32 fold
+    // passes (and the newborn step); 0: neither
+    P.esc = !c->vacuum_steps ? 0 : g.esc ? 1 : (precision == PR_FP32_MIXED && g.fold && !P.has_grid) ? 2 : 0;
     make_source_dev(c->srcs[src], P.src);
     P.n_tallies = nt;
     int lds_doubles = 0;
@@ -1414,6 +1429,8 @@ extern "C" int pr_set_tuning(pr_ctx* c, const pr_tuning* t) {
         return fail(c, PR_EINVAL, "tuning.waves_per_simd must be 0, 4 or 5");
     if (t->grid_walk_cells != 0 && (t->grid_walk_cells < 2 || t->grid_walk_cells > 1024))
         return fail(c, PR_EINVAL, "tuning.grid_walk_cells must be 0 or 2..1024");
+    if (t->vacuum_steps != 0 && t->vacuum_steps != 1) return fail(c, PR_EINVAL, "tuning.vacuum_steps must be 0 or 1");
+    c->vacuum_steps = t->vacuum_steps;
     c->grid_walk_cells = t->grid_walk_cells;
     c->waves_per_simd = t->waves_per_simd == 5 ? 5 : 4;
     c->chunk = t->chunk;
@@ -1437,6 +1454,7 @@ extern "C" int pr_get_tuning(pr_ctx* c, pr_tuning* t) {
     t->waves_per_simd = c->waves_per_simd;
     t->grid_chunk = c->grid_chunk;
     t->grid_walk_cells = c->grid_walk_cells;
+    t->vacuum_steps = c->vacuum_steps;
     return PR_OK;
 }
 
@@ -1900,6 +1918,10 @@ extern "C" int pr_autotune(pr_ctx* c, const pr_sim* sims, int32_t nsims, double 
         knobs.push_back({&c->grid_chunk, {0, 64, 128, 256}});
         knobs.push_back({&c->grid_walk_cells, {0, 2, 3, 4, 6, 8, 16}});
     }
+    // single runs of scenes where steps that draw nothing can be taken early
+    bool any_vac = false;
+    for (const auto& s : sample) any_vac = any_vac || c->geoms[s.geom].esc || c->geoms[s.geom].fold;
+    if (!batched && any_vac) knobs.push_back({&c->vacuum_steps, {1, 0}});
 
     float cur = 0.f;
     rc = trial_ms(c, sample, batched, st, e0, e1, 2, &cur);

@@ -230,7 +230,9 @@ struct Params {
     int32_t walk_cells;            // FP32 grid walks pause after this many cells (0: never)
     int32_t paired;                // FP32 without a grid: a tally scores straight into global memory, so the
                                    // wave's scores leave as paired-lane atomics (the FP64 kernels always do)
-    int32_t esc;                   // some volume is marked exit_escapes (the world-crossing kernels apply)
+    int32_t esc;                   // 1: some volume is marked exit_escapes (the world-crossing kernels apply);
+                                   // 2: FP32 fold passes (a step from material into vacuum is followed by the
+                                   // vacuum step before the wave's other lanes step again); 0: neither
 };
 
 // Batched runs: many simulations (each its own geometry, source and tallies)
@@ -1104,11 +1106,11 @@ __device__ __forceinline__ R own_exit(const VolT<R>& W, int kind, const R p[3], 
 }
 
 // One step; returns true when the step was the history's first collision
-// (absorption or scattering), the event of first-collision tallies.  ESC: a
-// history leaving a volume marked exit_escapes takes the world crossing that
+// (absorption or scattering), the event of first-collision tallies.  ESC == 1:
+// a history leaving a volume marked exit_escapes takes the world crossing that
 // follows in the same step (kernels built without it leave that to the next
 // step; the history is the same either way).
-template <class R, bool REC, bool GRID, bool ESC = false>
+template <class R, bool REC, bool GRID, int ESC = 0>
 __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed, int walk_cells = 0) {
     if (s.steps >= kMaxSteps) {
         s.term = PR_END_CAPPED;
@@ -1275,7 +1277,7 @@ __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t 
     s.region = V.parent;
     hash_ev<REC>(s.hash, EV_EXIT, s.region);
     const int exit_escapes = (int)(V.kind_items4 >> 24);
-    if (ESC && exit_escapes && s.steps < kMaxSteps) {
+    if (ESC == 1 && exit_escapes && s.steps < kMaxSteps) {
         // the next step can only cross the vacuum world to its boundary: take it
         // now, as that step would (same distance, move and time; the step cap is
         // left to the next step)

@@ -322,13 +322,16 @@ struct PersistentScene<double, false, GRID> {
 // blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
 // PAIR (FP32 without a grid): paired-lane global scores, for runs with a tally
 // that scores straight into global memory.  FC (FP64): the run has
-// first-collision tallies.  ESC (no grid; FP32 with four waves and per-lane
-// scoring, and FP64): the world crossing after leaving an exit_escapes volume is
-// taken in the leaving step, and a history born in a vacuum volume takes its
-// first step in the refill pass, with the wave's other new histories (both draw
-// nothing and change no history; built only where the registers allow: the
-// other FP32 variants and the batch kernels slow down with the extra code).
-template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC, bool ESC>
+// first-collision tallies.  ESC, steps that draw nothing taken early (none
+// changes a history): 1 (no grid; FP32 with four waves and per-lane scoring, and
+// FP64): the world crossing after leaving an exit_escapes volume is taken in the
+// leaving step; 2 (FP32 with the scene in LDS, no grid): a lane whose step took
+// it from material into vacuum takes its vacuum step in a fold pass, before the
+// wave's other lanes step again; with 1 and 2 a history born in a vacuum volume
+// takes its first step in the refill pass, with the wave's other new histories.
+// Built only where it pays: the extra code slows the other instances, and the
+// batch kernels, down.
+template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC, int ESC>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
     // FP64 without a grid, and FP32 runs whose tallies score straight into global
@@ -374,11 +377,15 @@ void k_mixed(Params P) {
         const R o[3] = {(R)P.src.o[0], (R)P.src.o[1], (R)P.src.o[2]};
         start_region = locate<R, GRID>(S, o, 0);
     }
+    bool again = false;   // ESC == 2: the lane's last step took it from material into vacuum
     for (;;) {
+        // ESC == 2, a fold pass: only the lanes that just left material for vacuum
+        // step (the vacuum step, which draws nothing), with no refill before it
+        const bool fold_pass = ESC == 2 && __ballot(again) != 0ull;
         const bool idle = s.term != 0;
         const unsigned long long idle_mask = __ballot(idle);
         const int n_idle = __popcll(idle_mask);
-        if (n_idle >= P.refill_threshold || n_idle == kWave) {
+        if (!fold_pass && (n_idle >= P.refill_threshold || n_idle == kWave)) {
             // score the histories that ended since the last refill, all together
             if (kPaired && __ballot(pending) != 0ull) {
                 const bool scoring =
@@ -446,9 +453,13 @@ void k_mixed(Params P) {
             continue;
         }
         bool first = false;
-        if (s.term == 0) {
+        if (s.term == 0 && (!fold_pass || again)) {
+            const int m0 = ESC == 2 ? S.vols[s.region].mat : 0;
             first = step<R, REC, GRID, ESC>(s, S, P.seed, P.walk_cells);
             pending = s.term != 0;
+            if (ESC == 2) again = !fold_pass && s.term == 0 && m0 >= 0 && S.vols[s.region].mat < 0;
+        } else if (ESC == 2) {
+            again = false;
         }
         // first-collision tallies (a debugging trigger of the FP64 policies) score
         // the state just after the collision
@@ -789,7 +800,7 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
         (const void*)k_plain<false, false, true, false>,  (const void*)k_plain<true, false, true, false>,
         (const void*)k_plain<false, true, true, false>,   (const void*)k_plain<true, true, true, false>,
         (const void*)k_plain<false, false, false, true>,  (const void*)k_plain<true, false, false, true>};
-    const bool esc = P.esc && !P.has_grid && !P.has_fc;
+    const bool esc = P.esc == 1 && !P.has_grid && !P.has_fc;
     const int v = esc ? 8 + (rec ? 1 : 0) : (rec ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.has_fc ? 4 : 0);
     // one thread per history, at most 2^30 histories (2^22 blocks) per launch
     const uint64_t per_launch = 1ull << 30;
@@ -812,33 +823,39 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
 // + 20 with the world-crossing code (FP32 four-wave per-lane scoring without a
 // grid: 20, 21; FP64 without a grid or first-collision tallies: 26)
 static int mixed_variant(const Params& P) {
-    if (P.fp64) return P.has_fc ? (P.has_grid ? 17 : 16) : (P.has_grid ? 7 : (P.esc ? 26 : 6));
+    if (P.fp64) return P.has_fc ? (P.has_grid ? 17 : 16) : (P.has_grid ? 7 : (P.esc == 1 ? 26 : 6));
     const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
                   (P.paired && !P.has_grid ? 8 : 0);
-    return v <= 1 && P.esc ? v + 20 : v;
+    if (P.esc == 1) return v <= 1 ? v + 20 : v;
+    // fold passes: built for the LDS-scene instances (the others run without them)
+    if (P.esc == 2) return v == 1 ? 28 : v == 9 ? 29 : v == 13 ? 30 : v;
+    return v;
 }
 
 // the kernel of a variant index
 template <bool REC>
 static const void* mixed_kernel(int v) {
     switch (v) {
-    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false, false, false>;
-    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false, false, false>;
-    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false, false, false>;
-    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false, false, false>;
-    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false, false, false>;
-    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false, false, false>;
-    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false, false, false>;
-    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false, false, false>;
-    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true, false, false>;
-    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true, false, false>;
-    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false, false>;
-    case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false, false>;
-    case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true, false>;
-    case 17: return (const void*)k_mixed<double, REC, false, true, 3, false, true, false>;
-    case 20: return (const void*)k_mixed<float, REC, false, false, 4, false, false, true>;
-    case 21: return (const void*)k_mixed<float, REC, true, false, 4, false, false, true>;
-    case 26: return (const void*)k_mixed<double, REC, false, false, 2, false, false, true>;
+    case 0: return (const void*)k_mixed<float, REC, false, false, 4, false, false, 0>;
+    case 1: return (const void*)k_mixed<float, REC, true, false, 4, false, false, 0>;
+    case 2: return (const void*)k_mixed<float, REC, false, true, 4, false, false, 0>;
+    case 3: return (const void*)k_mixed<float, REC, true, true, 4, false, false, 0>;
+    case 4: return (const void*)k_mixed<float, REC, false, false, 5, false, false, 0>;
+    case 5: return (const void*)k_mixed<float, REC, true, false, 5, false, false, 0>;
+    case 6: return (const void*)k_mixed<double, REC, false, false, 2, false, false, 0>;
+    case 7: return (const void*)k_mixed<double, REC, false, true, 3, false, false, 0>;
+    case 8: return (const void*)k_mixed<float, REC, false, false, 4, true, false, 0>;
+    case 9: return (const void*)k_mixed<float, REC, true, false, 4, true, false, 0>;
+    case 12: return (const void*)k_mixed<float, REC, false, false, 5, true, false, 0>;
+    case 13: return (const void*)k_mixed<float, REC, true, false, 5, true, false, 0>;
+    case 16: return (const void*)k_mixed<double, REC, false, false, 2, false, true, 0>;
+    case 17: return (const void*)k_mixed<double, REC, false, true, 3, false, true, 0>;
+    case 20: return (const void*)k_mixed<float, REC, false, false, 4, false, false, 1>;
+    case 21: return (const void*)k_mixed<float, REC, true, false, 4, false, false, 1>;
+    case 26: return (const void*)k_mixed<double, REC, false, false, 2, false, false, 1>;
+    case 28: return (const void*)k_mixed<float, REC, true, false, 4, false, false, 2>;
+    case 29: return (const void*)k_mixed<float, REC, true, false, 4, true, false, 2>;
+    case 30: return (const void*)k_mixed<float, REC, true, false, 5, true, false, 2>;
     default: return nullptr;   // no such variant: the launch reports an error
     }
 }

@@ -24,20 +24,26 @@ it to 28 (1.086 -> 1.000 ms; 24 to 32 are within 0.5 %)."""
 # workload name -> pr_tuning fields
 TUNED = {
     "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 28, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
+               "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 4,
+               "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
     "guide": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
+              "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4,
+              "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
     "vessel": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
+               "bin_cache_slots": 0, "chunk": 256, "waves_per_simd": 5,
+               "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
     "imaging": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-                "bin_cache_slots": 0, "chunk": 128, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 3},
+                "bin_cache_slots": 0, "chunk": 128, "waves_per_simd": 4,
+                "grid_chunk": 0, "grid_walk_cells": 3, "vacuum_steps": 1},
     "paper_guide": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5, "grid_chunk": 0, "grid_walk_cells": 0},
+                    "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 5,
+                    "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
     "batch": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 16, "lds_tally_bytes": 32768,
-              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5, "grid_chunk": 128, "grid_walk_cells": 3},
+              "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 5,
+              "grid_chunk": 128, "grid_walk_cells": 3, "vacuum_steps": 1},
     "paper_chopper": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 24, "lds_tally_bytes": 32768,
                       "bin_cache_slots": 1024, "chunk": 1024, "waves_per_simd": 4, "grid_chunk": 0,
-                      "grid_walk_cells": 0},
+                      "grid_walk_cells": 0, "vacuum_steps": 1},
 }
 
 # Launch tunings of the PR_FP64_PERSISTENT policy (the same knobs; waves_per_simd
@@ -52,5 +58,6 @@ TUNED_FP64_PERSISTENT = {
     "imaging": dict(TUNED["imaging"], chunk=64, grid_walk_cells=0),
     "paper_guide": dict(TUNED["paper_guide"], refill_threshold=32),
     "paper_chopper": {"block": 256, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
-                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4, "grid_chunk": 0, "grid_walk_cells": 0},
+                      "bin_cache_slots": 256, "chunk": 256, "waves_per_simd": 4,
+                      "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
 }

@@ -177,6 +177,11 @@ def test_tuning_validation(ctx):
     assert code_of(lambda: ctx.set_tuning(bin_cache_slots=1000)) == -1
     assert code_of(lambda: ctx.set_tuning(refill_threshold=0)) == -1
     assert code_of(lambda: ctx.set_tuning(waves_per_simd=3)) == -1
+    assert code_of(lambda: ctx.set_tuning(vacuum_steps=2)) == -1
+    assert t["vacuum_steps"] == 1
+    ctx.set_tuning(vacuum_steps=0)
+    assert ctx.get_tuning()["vacuum_steps"] == 0
+    ctx.set_tuning(vacuum_steps=1)
     assert code_of(lambda: ctx.set_tuning(grid_chunk=-1)) == -1
     assert code_of(lambda: ctx.set_tuning(grid_chunk=(1 << 20) + 1)) == -1
     ctx.set_tuning(grid_chunk=128)

@@ -69,3 +69,35 @@ def test_world_crossing_fp64_elementwise(ctx, world, daughter):
 def test_world_crossing_fp32_pairs_with_fp64(ctx, world, daughter):
     prob = _problem(world, daughter, 200_000)
     paired_fp32_fp64(ctx, prob, first=0, n=200_000, label=prob.name)
+
+
+@pytest.mark.parametrize("workload,precision", [("sample", "fp32"), ("sample", "fp64_persistent"), ("sample", "fp64"),
+                                                ("vessel", "fp32"), ("vessel", "fp64_persistent")])
+def test_vacuum_steps_change_no_history(ctx, workload, precision):
+    """The same ids with steps that draw nothing taken early (vacuum_steps = 1:
+    the biased sample's world crossing folded into the leaving step and its
+    newborn steps taken in the refill pass; the vessel's FP32 fold passes) and
+    without (0): identical records and statistics, tallies equal up to summation
+    order."""
+    import numpy as np
+    from paper_2304_06226_amd.tuning import TUNED
+    n = 200_000
+    prob = W.biased_sample(n) if workload == "sample" else W.vessel_sample(n)
+    base = ctx.get_tuning()
+    out = {}
+    try:
+        for v in (1, 0):
+            print(f"[case] {workload} {precision} vacuum_steps={v}", flush=True)
+            ctx.set_tuning(**{**TUNED[workload], "vacuum_steps": v})
+            out[v] = gpu_run(ctx, prob, first=0, n=n, precision=precision)
+    finally:
+        ctx.set_tuning(**base)
+    (r1, rec1, st1), (r0, rec0, st0) = out[1], out[0]
+    for k in rec0.dtype.names:
+        diff = int((rec1[k] != rec0[k]).reshape(n, -1).any(axis=1).sum())
+        assert diff == 0, (k, diff)
+    assert st1 == st0
+    for (a, a2, an), (b, b2, bn) in zip(r1, r0):
+        assert an == bn == n
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-300)
+        np.testing.assert_allclose(a2, b2, rtol=1e-12, atol=1e-300)
