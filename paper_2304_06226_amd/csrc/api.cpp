@@ -1151,7 +1151,7 @@ static int build_params(pr_ctx* c, int32_t geom, int32_t src, const int32_t* tal
     P.kinds = g.kinds;
     // 1: the lone-daughter world crossing (and the newborn step); 2: FP32 fold
     // passes (and the newborn step); 0: neither
-    P.esc = !c->vacuum_steps ? 0 : g.esc ? 1 : (precision == PR_FP32_MIXED && g.fold && !P.has_grid) ? 2 : 0;
+    P.esc = !c->vacuum_steps ? 0 : g.esc ? 1 : (precision != PR_FP64_PLAIN && g.fold && !P.has_grid) ? 2 : 0;
     make_source_dev(c->srcs[src], P.src);
     P.n_tallies = nt;
     int lds_doubles = 0;

@@ -823,7 +823,7 @@ hipError_t launch_plain(const Params& P, bool rec, hipStream_t st) {
 // + 20 with the world-crossing code (FP32 four-wave per-lane scoring without a
 // grid: 20, 21; FP64 without a grid or first-collision tallies: 26)
 static int mixed_variant(const Params& P) {
-    if (P.fp64) return P.has_fc ? (P.has_grid ? 17 : 16) : (P.has_grid ? 7 : (P.esc == 1 ? 26 : 6));
+    if (P.fp64) return P.has_fc ? (P.has_grid ? 17 : 16) : (P.has_grid ? 7 : (P.esc == 1 ? 26 : P.esc == 2 ? 27 : 6));
     const int v = (P.scene_in_lds ? 1 : 0) + (P.has_grid ? 2 : 0) + (P.waves == 5 && !P.has_grid ? 4 : 0) +
                   (P.paired && !P.has_grid ? 8 : 0);
     if (P.esc == 1) return v <= 1 ? v + 20 : v;
@@ -853,6 +853,7 @@ static const void* mixed_kernel(int v) {
     case 20: return (const void*)k_mixed<float, REC, false, false, 4, false, false, 1>;
     case 21: return (const void*)k_mixed<float, REC, true, false, 4, false, false, 1>;
     case 26: return (const void*)k_mixed<double, REC, false, false, 2, false, false, 1>;
+    case 27: return (const void*)k_mixed<double, REC, false, false, 2, false, false, 2>;
     case 28: return (const void*)k_mixed<float, REC, true, false, 4, false, false, 2>;
     case 29: return (const void*)k_mixed<float, REC, true, false, 4, true, false, 2>;
     case 30: return (const void*)k_mixed<float, REC, true, false, 5, true, false, 2>;
