@@ -310,6 +310,19 @@ struct PersistentScene<double, false, GRID> {
     }
 };
 
+// lane l's value of x, as a wave-uniform value
+template <class R>
+__device__ __forceinline__ R readlane_r(R x, int l) {
+    if constexpr (sizeof(R) == 4) {
+        return __builtin_bit_cast(R, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), l));
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, x);
+        const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+        return __builtin_bit_cast(R, ((unsigned long long)hi << 32) | lo);
+    }
+}
+
 // R = float: the FP32 mixed policy; R = double: the persistent FP64 policy, whose
 // histories take exactly the arithmetic of the plain kernel.
 // WPE resident waves per SIMD (FP32: 4 or 5, grid variants 4; FP64: 2, grid 3,
@@ -378,6 +391,17 @@ void k_mixed(Params P) {
         start_region = locate<R, GRID>(S, o, 0);
     }
     bool again = false;   // ESC == 2: the lane's last step took it from material into vacuum
+    // A pencil beam of one wavelength starting in vacuum: every history draws
+    // nothing until it has taken its first step, so that step ends in the same
+    // state for all of them.  After the wave's first newborn has taken it, the
+    // state is kept in wave-uniform registers and later newborns start from it
+    // (builds without records only: records also carry the event hash).
+    constexpr bool kTmpl = ESC == 1 && !REC;
+    const bool tmpl_ok = kTmpl && P.src.kind == PR_PENCIL && P.src.spectrum == PR_MONO && start_region >= 0 &&
+                         S.vols[start_region].mat < 0;
+    bool have_tmpl = false;
+    R tp0 = (R)0, tp1 = (R)0, tp2 = (R)0, tt = (R)0;
+    int treg = 0, tsteps = 0, tterm = 0;
     for (;;) {
         // ESC == 2, a fold pass: only the lanes that just left material for vacuum
         // step (the vacuum step, which draws nothing), with no refill before it
@@ -431,17 +455,55 @@ void k_mixed(Params P) {
             if (!exhausted) {
                 const unsigned long long avail = cend - cnext;
                 const unsigned long long take = (unsigned long long)n_idle < avail ? (unsigned long long)n_idle : avail;
+                bool born = false;
                 if (idle) {
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<R, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
-                                             start_region);
-                        // born in a vacuum volume: the first step draws nothing and is
-                        // taken here, with the wave's other new histories
-                        if (ESC && s.term == 0 && S.vols[s.region].mat < 0)
-                            step<R, REC, GRID, ESC>(s, S, P.seed, P.walk_cells);
+                        born = true;
+                        if (kTmpl && have_tmpl) {
+                            // the state source() and the first step would give (no draws)
+                            s.h = P.first + cnext + (unsigned long long)rank;
+                            s.k = 0;
+                            s.nbuf = 0;
+                            s.w = 1.0;
+                            s.nscat = 0;
+                            s.p[0] = tp0;
+                            s.p[1] = tp1;
+                            s.p[2] = tp2;
+                            s.u[0] = (R)P.src.u[0];
+                            s.u[1] = (R)P.src.u[1];
+                            s.u[2] = (R)P.src.u[2];
+                            const R lam = (R)P.src.lam0;
+                            if (!(lam == s.lam)) s.xs_mat = -2;
+                            s.lam = lam;
+                            s.t = tt;
+                            s.region = treg;
+                            s.steps = tsteps;
+                            s.term = tterm;
+                        } else {
+                            source<R, REC, GRID>(s, P.src, S, P.seed, P.first + cnext + (unsigned long long)rank, 0,
+                                                 start_region);
+                            // born in a vacuum volume: the first step draws nothing and is
+                            // taken here, with the wave's other new histories
+                            if (ESC && s.term == 0 && S.vols[s.region].mat < 0)
+                                step<R, REC, GRID, ESC>(s, S, P.seed, P.walk_cells);
+                        }
                         pending = s.term != 0;   // born outside the world, or ended: counted at the next refill
+                    }
+                }
+                if (tmpl_ok && !have_tmpl) {
+                    const unsigned long long bm = __ballot(born);
+                    if (bm != 0ull) {
+                        const int l = __ffsll((long long)bm) - 1;
+                        tp0 = readlane_r<R>(s.p[0], l);
+                        tp1 = readlane_r<R>(s.p[1], l);
+                        tp2 = readlane_r<R>(s.p[2], l);
+                        tt = readlane_r<R>(s.t, l);
+                        treg = __builtin_amdgcn_readlane(s.region, l);
+                        tsteps = __builtin_amdgcn_readlane(s.steps, l);
+                        tterm = __builtin_amdgcn_readlane(s.term, l);
+                        have_tmpl = true;
                     }
                 }
                 cnext += take;

@@ -19,12 +19,14 @@ as a wave with paired-lane atomics; for the guide that moved the best refill
 threshold from 16 to 48 idle lanes (7.56 -> 6.22 ms per 1e8 histories).  Cheaper
 tally binning moved the biased sample's from 32 to 16 (512-id claims: 1.237 ->
 1.221 ms); taking a newborn history's first vacuum step in the refill pass moved
-it to 28 (1.086 -> 1.000 ms; 24 to 32 are within 0.5 %)."""
+it to 28 (1.086 -> 1.000 ms; 24 to 32 are within 0.5 %); starting a pencil
+beam's newborns from the first newborn's state after its first step made refills
+cheaper and 1024-id claims best (fewer claim atomics; 24 idle lanes, 0.907 ms)."""
 
 # workload name -> pr_tuning fields
 TUNED = {
-    "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 28, "lds_tally_bytes": 32768,
-               "bin_cache_slots": 256, "chunk": 512, "waves_per_simd": 4,
+    "sample": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 24, "lds_tally_bytes": 32768,
+               "bin_cache_slots": 256, "chunk": 1024, "waves_per_simd": 4,
                "grid_chunk": 0, "grid_walk_cells": 0, "vacuum_steps": 1},
     "guide": {"block": 1024, "blocks_per_cu": 0, "refill_threshold": 48, "lds_tally_bytes": 32768,
               "bin_cache_slots": 0, "chunk": 1024, "waves_per_simd": 4,

@@ -101,3 +101,50 @@ def test_vacuum_steps_change_no_history(ctx, workload, precision):
         assert an == bn == n
         np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-300)
         np.testing.assert_allclose(a2, b2, rtol=1e-12, atol=1e-300)
+
+
+def _pencil_problem(offset, n):
+    """The biased sample cylinder alone in a vacuum sphere, hit (offset 0) or missed
+    (offset 40 mm) by a 1.8 A pencil beam; a time-of-flight tally of the unscattered
+    escapes checks the clock of the copied first step."""
+    prob = W.biased_sample(n)
+    prob.source = W.Source("pencil", origin=(offset, 0.0, -100.0), direction=(0.0, 0.0, 1.0), spectrum="mono",
+                           lam0=1.8)
+    prob.tallies = [prob.tallies[0],
+                    W.Tally(trigger="escape", filter="unscattered", axes=[W.Axis("tof", 0.0, 0.005, 100)]),
+                    prob.tallies[2]]
+    prob.name = f"pencil-{offset:g}"
+    return prob
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64_persistent"])
+@pytest.mark.parametrize("offset", [0.0, 40.0])
+def test_pencil_newborns_without_records(ctx, offset, precision):
+    """Runs without records start the newborns of a one-wavelength pencil beam in
+    vacuum from the state of the wave's first newborn after its first step (all
+    of them draw nothing until then); runs with records take every step.  The
+    same ids with vacuum_steps 1 and 0, and with and without records: equal
+    statistics, tallies equal up to summation order."""
+    import numpy as np
+    from paper_2304_06226_amd.tuning import TUNED
+    n = 500_000
+    prob = _pencil_problem(offset, n)
+    base = ctx.get_tuning()
+    runs = []
+    try:
+        for v, rec in ((1, False), (0, False), (1, True)):
+            print(f"[case] {prob.name} {precision} vacuum_steps={v} records={rec}", flush=True)
+            ctx.set_tuning(**{**TUNED["sample"], "vacuum_steps": v})
+            res, _, st = gpu_run(ctx, prob, first=0, n=n, precision=precision, records=rec)
+            runs.append((res, st))
+    finally:
+        ctx.set_tuning(**base)
+    (r1, st1) = runs[0]
+    assert st1["histories"] == n
+    assert (st1["escaped"] == n) == (offset != 0.0)
+    for r, st in runs[1:]:
+        assert st == st1
+        for (a, a2, an), (b, b2, bn) in zip(r1, r):
+            assert an == bn == n
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-300)
+            np.testing.assert_allclose(a2, b2, rtol=1e-12, atol=1e-300)
