@@ -701,6 +701,16 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
         const float o[3] = {(float)sd.src.o[0], (float)sd.src.o[1], (float)sd.src.o[2]};
         start_region = locate<float, GRID>(S, o, 0);
     }
+    // A pencil beam of one wavelength starting in vacuum: every history reaches the
+    // same state after its first step (it draws nothing until then).  Once a lane
+    // of the wave has taken a first step, that state is kept in wave-uniform
+    // registers and later newborns start from it.
+    // (scenes without a daughter grid: the code costs the grid instances registers)
+    const bool tmpl_ok = !GRID && sd.src.kind == PR_PENCIL && sd.src.spectrum == PR_MONO && start_region >= 0 &&
+                         S.vols[start_region].mat < 0;
+    bool have_tmpl = false;
+    float tp0 = 0.f, tp1 = 0.f, tp2 = 0.f, tt = 0.f;
+    int treg = 0, tsteps = 0, tterm = 0;
     const unsigned long long end = sd.n;
     unsigned long long* counter = B.sim_next + sim;
     const int lane = lane_id();
@@ -739,8 +749,30 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
                     const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(idle_mask >> 32),
                                                               __builtin_amdgcn_mbcnt_lo((uint32_t)idle_mask, 0u));
                     if ((unsigned long long)rank < take) {
-                        source<float, false, GRID>(s, sd.src, S, B.seed, sd.first + shift + cnext + (unsigned long long)rank,
-                                                   0, start_region);
+                        const unsigned long long h = sd.first + shift + cnext + (unsigned long long)rank;
+                        if (!GRID && have_tmpl) {
+                            // the state source() and the first step would give (no draws)
+                            s.h = h;
+                            s.k = 0;
+                            s.nbuf = 0;
+                            s.w = 1.0;
+                            s.nscat = 0;
+                            s.p[0] = tp0;
+                            s.p[1] = tp1;
+                            s.p[2] = tp2;
+                            s.u[0] = (float)sd.src.u[0];
+                            s.u[1] = (float)sd.src.u[1];
+                            s.u[2] = (float)sd.src.u[2];
+                            const float lam = (float)sd.src.lam0;
+                            if (!(lam == s.lam)) s.xs_mat = -2;
+                            s.lam = lam;
+                            s.t = tt;
+                            s.region = treg;
+                            s.steps = tsteps;
+                            s.term = tterm;
+                        } else {
+                            source<float, false, GRID>(s, sd.src, S, B.seed, h, 0, start_region);
+                        }
                         pending = s.term != 0;
                     }
                 }
@@ -754,6 +786,21 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
         if (s.term == 0) {
             step<float, false, GRID>(s, S, B.seed, B.walk_cells);
             pending = s.term != 0;
+        }
+        if (tmpl_ok && !have_tmpl) {
+            // a lane that has just taken its first step (its history's only one so far)
+            const unsigned long long fm = __ballot(s.steps == 1 && (s.term == 0 || pending));
+            if (fm != 0ull) {
+                const int l = __ffsll((long long)fm) - 1;
+                tp0 = readlane_r<float>(s.p[0], l);
+                tp1 = readlane_r<float>(s.p[1], l);
+                tp2 = readlane_r<float>(s.p[2], l);
+                tt = readlane_r<float>(s.t, l);
+                treg = __builtin_amdgcn_readlane(s.region, l);
+                tsteps = __builtin_amdgcn_readlane(s.steps, l);
+                tterm = __builtin_amdgcn_readlane(s.term, l);
+                have_tmpl = true;
+            }
         }
     }
 }
