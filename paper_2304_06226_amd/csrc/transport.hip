@@ -342,8 +342,9 @@ __device__ __forceinline__ R readlane_r(R x, int l) {
 // it from material into vacuum takes its vacuum step in a fold pass, before the
 // wave's other lanes step again; with 1 and 2 a history born in a vacuum volume
 // takes its first step in the refill pass, with the wave's other new histories.
-// Built only where it pays: the extra code slows the other instances, and the
-// batch kernels, down.
+// Built only where it pays: the extra code slows the other instances down.  The
+// batch kernels without a grid take the world crossing of 1 (their newborns
+// start from a copied first step instead of a refill-pass step).
 template <class R, bool REC, bool SLDS, bool GRID, int WPE, bool PAIR, bool FC, int ESC>
 __global__ __launch_bounds__(GRID ? 512 : (sizeof(R) == 4 ? 1024 : 256)) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 void k_mixed(Params P) {
@@ -784,7 +785,7 @@ __device__ __forceinline__ void run_sim(const BatchParams& B, const SimDev& sd, 
             continue;
         }
         if (s.term == 0) {
-            step<float, false, GRID>(s, S, B.seed, B.walk_cells);
+            step<float, false, GRID, GRID ? 0 : 1>(s, S, B.seed, B.walk_cells);
             pending = s.term != 0;
         }
         if (tmpl_ok && !have_tmpl) {
