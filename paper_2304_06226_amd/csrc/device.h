@@ -337,6 +337,14 @@ struct M<float> {
     static __device__ __forceinline__ float uni(uint32_t a, uint32_t) { return (float)(a >> 8) * (1.0f / 16777216.0f); }
 };
 
+// floor to an integer in the value's own precision (the floor of a float is a
+// float, so FP32 needs no FP64 round trip)
+template <class R>
+__device__ __forceinline__ int floor_i(R x) {
+    if constexpr (sizeof(R) == 4) return (int)__builtin_floorf(x);
+    else return (int)__builtin_floor(x);
+}
+
 // -------------------------------------------------------------------------
 // Philox4x32-10, counter = (block, history), key = seed
 // -------------------------------------------------------------------------
@@ -821,7 +829,7 @@ __device__ __forceinline__ int locate(const SceneT<R>& S, const R p[3], int root
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
                 in = in && p[k] >= G.lo[k] && p[k] <= G.hi[k];
-                int i = (int)__builtin_floor((double)((p[k] - G.lo[k]) * G.inv_cell[k]));
+                int i = floor_i<R>((p[k] - G.lo[k]) * G.inv_cell[k]);
                 i = i < 0 ? 0 : (i >= G.n[k] ? G.n[k] - 1 : i);
                 cell = cell * G.n[k] + i;
             }
@@ -1003,7 +1011,7 @@ __device__ __forceinline__ void grid_nearest(const SceneT<R>& S, const GridT<R>&
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const R x = p[k] + t0 * u[k];
-        int i = (int)__builtin_floor((double)((x - G.lo[k]) * G.inv_cell[k]));
+        int i = floor_i<R>((x - G.lo[k]) * G.inv_cell[k]);
         i = i < 0 ? 0 : (i >= G.n[k] ? G.n[k] - 1 : i);
         ix[k] = i;
         if (u[k] > (R)0) {
