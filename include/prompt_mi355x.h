@@ -417,10 +417,12 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * early where the scene allows it (scenes without a daughter grid): a history
  * leaving the only, convex daughter of a vacuum, mirrorless box, cylinder or
  * sphere world crosses the world in the same step; a history born in vacuum
- * takes its first step as soon as it is drawn; and, in FP32 scenes without
- * mirrors whose material volumes sit in vacuum, a history that leaves
- * material for vacuum takes its vacuum step before the wave's other histories
- * step again.  Histories and records are the same either way.
+ * takes its first step as soon as it is drawn (a pencil beam of one
+ * wavelength: later histories copy the state the first one reached there);
+ * and, in scenes without mirrors whose material volumes sit in vacuum
+ * (PR_FP32_MIXED and PR_FP64_PERSISTENT), a history that leaves material for
+ * vacuum takes its vacuum step before the wave's other histories step again.
+ * Histories and records are the same either way.
  * Results do not depend on these settings beyond floating-point summation
  * order. */
 typedef struct {
