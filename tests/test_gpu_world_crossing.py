@@ -71,24 +71,41 @@ def test_world_crossing_fp32_pairs_with_fp64(ctx, world, daughter):
     paired_fp32_fp64(ctx, prob, first=0, n=200_000, label=prob.name)
 
 
+def _void_problem(n):
+    """The vessel's biased sample cylinder with a 4 x 8 x 4 mm void (vacuum) inside it,
+    and a 30 x 30 x 2 mm aluminium plate 50 mm downstream, in a vacuum sphere under the
+    vessel's Maxwellian 10 x 10 mm beam: histories enter the void from material and
+    leave both solids for the world, so fold passes follow steps that end in a vacuum
+    daughter as well as steps that leave for the world (two daughters: the
+    lone-daughter crossing does not apply)."""
+    prob = W.vessel_sample(n)
+    prob.volumes = [prob.volumes[0], prob.volumes[2],
+                    W.Volume("box", (1.0, 2.0, 0.5), (4.0, 8.0, 4.0), parent=1, material=-1),
+                    W.Volume("box", (0.0, 0.0, 50.0), (30.0, 30.0, 2.0), parent=0, material=1)]
+    prob.name = "void-in-sample"
+    return prob
+
+
 @pytest.mark.parametrize("workload,precision", [("sample", "fp32"), ("sample", "fp64_persistent"), ("sample", "fp64"),
-                                                ("vessel", "fp32"), ("vessel", "fp64_persistent")])
+                                                ("vessel", "fp32"), ("vessel", "fp64_persistent"),
+                                                ("void", "fp32"), ("void", "fp64_persistent")])
 def test_vacuum_steps_change_no_history(ctx, workload, precision):
     """The same ids with steps that draw nothing taken early (vacuum_steps = 1:
     the biased sample's world crossing folded into the leaving step and its
-    newborn steps taken in the refill pass; the vessel's FP32 fold passes) and
-    without (0): identical records and statistics, tallies equal up to summation
-    order."""
+    newborn steps taken in the refill pass; fold passes in the vessel and in a
+    sample with a void) and without (0): identical records and statistics,
+    tallies equal up to summation order."""
     import numpy as np
     from paper_2304_06226_amd.tuning import TUNED
     n = 200_000
-    prob = W.biased_sample(n) if workload == "sample" else W.vessel_sample(n)
+    prob = {"sample": W.biased_sample, "vessel": W.vessel_sample, "void": _void_problem}[workload](n)
+    tun = TUNED["sample" if workload == "sample" else "vessel"]
     base = ctx.get_tuning()
     out = {}
     try:
         for v in (1, 0):
             print(f"[case] {workload} {precision} vacuum_steps={v}", flush=True)
-            ctx.set_tuning(**{**TUNED[workload], "vacuum_steps": v})
+            ctx.set_tuning(**{**tun, "vacuum_steps": v})
             out[v] = gpu_run(ctx, prob, first=0, n=n, precision=precision)
     finally:
         ctx.set_tuning(**base)
@@ -148,3 +165,16 @@ def test_pencil_newborns_without_records(ctx, offset, precision):
             assert an == bn == n
             np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-300)
             np.testing.assert_allclose(a2, b2, rtol=1e-12, atol=1e-300)
+
+
+def test_void_scene_fp64_persistent_elementwise(ctx):
+    """The sample-with-void scene (fold passes in the persistent FP64 kernel) history
+    by history against the oracle on the same ids."""
+    n = 50_000
+    prob = _void_problem(n)
+    print(f"[case] {prob.name} fp64_persistent n={n}", flush=True)
+    gres, grec, gst = gpu_run(ctx, prob, first=0, n=n, precision="fp64_persistent")
+    ores = O.run(prob, first=0, n=n, threads=8, records=True)
+    same = compare_records_fp64(grec, ores.records)
+    compare_tallies_fp64(gres, ores, grec, ores.records, same)
+    assert gst["histories"] == n
