@@ -422,7 +422,10 @@ int pr_release_batch(pr_ctx* ctx, int32_t batch);
  * and, in scenes without mirrors whose material volumes sit in vacuum
  * (PR_FP32_MIXED and PR_FP64_PERSISTENT), a history that leaves material for
  * vacuum takes its vacuum step before the wave's other histories step again.
- * Histories and records are the same either way.
+ * Histories and records are the same either way, except that for a ray that
+ * grazes the lone sample's surface as it leaves, rounding could let a separate
+ * world step find a re-entry that the folded crossing does not look for
+ * (impossible in exact arithmetic: the solid is convex; not seen in tests).
  * Results do not depend on these settings beyond floating-point summation
  * order. */
 typedef struct {
