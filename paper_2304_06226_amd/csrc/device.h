@@ -1117,7 +1117,8 @@ __device__ __forceinline__ R own_exit(const VolT<R>& W, int kind, const R p[3], 
 // (absorption or scattering), the event of first-collision tallies.  ESC == 1:
 // a history leaving a volume marked exit_escapes takes the world crossing that
 // follows in the same step (kernels built without it leave that to the next
-// step; the history is the same either way).
+// step; the history is the same either way, short of rounding on a ray that
+// grazes the daughter as it leaves, where the next step could find a re-entry).
 template <class R, bool REC, bool GRID, int ESC = 0>
 __device__ __forceinline__ bool step(PState<R>& s, const SceneT<R>& S, uint64_t seed, int walk_cells = 0) {
     if (s.steps >= kMaxSteps) {

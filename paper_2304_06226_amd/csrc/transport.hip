@@ -335,8 +335,8 @@ __device__ __forceinline__ R readlane_r(R x, int l) {
 // blocks merge their LDS tallies at the end), 512 with a grid, 256 in FP64.
 // PAIR (FP32 without a grid): paired-lane global scores, for runs with a tally
 // that scores straight into global memory.  FC (FP64): the run has
-// first-collision tallies.  ESC, steps that draw nothing taken early (none
-// changes a history): 1 (no grid; FP32 with four waves and per-lane scoring, and
+// first-collision tallies.  ESC, steps that draw nothing taken early (no history
+// changes, short of rounding on a grazing exit in 1): 1 (no grid; FP32 with four waves and per-lane scoring, and
 // FP64): the world crossing after leaving an exit_escapes volume is taken in the
 // leaving step; 2 (FP32 with the scene in LDS, no grid): a lane whose step took
 // it from material into vacuum takes its vacuum step in a fold pass, before the
